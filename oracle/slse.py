@@ -1,0 +1,118 @@
+"""The SLSE-FRS iteration for the oracle (Alg. 2, eqs. (98) and (99)).
+
+Stage 1 runs a_i M-IHS steps on each sketched subproblem i = 1..K,
+
+    beta_{t+1} = beta_t - mu H_hat^{-1} grad f(beta_t; S_i X, S_i Y) + eta (beta_t - beta_{t-1}),
+
+and stage 2 runs s full-data steps of the same form (eq. (99)), with
+grad f(beta; X, Y) = X^T (X beta - Y) (Sec. 1) and the fixed Hessian sketch
+H_hat = (S_hat X)^T S_hat X (Sec. 3) applied through its QR factor R:
+H_hat^{-1} v = R^{-1} R^{-T} v (implementation details appendix).
+
+Readings where the paper is silent:
+  * beta_0 = 0 and beta_{-1} = beta_0;
+  * momentum carries across subproblems and into stage 2 (Alg. 2 keeps one
+    global t); `momentum_reset=True` restarts it at each subproblem instead,
+    as the proofs do;
+  * the stage-2 loop "for t = T_dagger to T" is read as exactly s steps;
+  * defaults mu = (1 - eta)^2, eta = d / r (Sec. 5 parameter choice).
+The gradient is formed in residual form g = c X^T (Y - X beta) = -c grad f and
+added with +mu.
+"""
+import numpy as np
+from scipy.linalg import solve_triangular
+
+from .ols import qr_r
+from .sketch import sketch as make_sketch
+
+ROW_BLOCK = 1 << 16
+
+
+def default_params(d, r):
+    eta = d / r
+    return (1.0 - eta) ** 2, eta
+
+
+def precond_factor(Ahat, d, hat_scale):
+    """R with R^T R = hat_scale * Ahat[:, :d]^T Ahat[:, :d] (Householder QR)."""
+    return qr_r(np.sqrt(hat_scale) * np.asarray(Ahat[:, :d], np.float64))
+
+
+def apply_precond(R, v):
+    """H_hat^{-1} v = R^{-1} (R^{-T} v)."""
+    return solve_triangular(R, solve_triangular(R, v, trans="T"))
+
+
+def sketched_grad(Ai, d, c, beta):
+    """c * B^T (b - B beta) for the sketched rows Ai = [B | b]."""
+    B = Ai[:, :d]
+    return c * (B.T @ (Ai[:, d] - B @ beta))
+
+
+def full_grad(X, Y, beta, row_block=ROW_BLOCK):
+    """X^T (Y - X beta) in float64, streamed over row blocks."""
+    d = X.shape[1]
+    g = np.zeros(d)
+    for i0 in range(0, X.shape[0], row_block):
+        Xb = np.asarray(X[i0:i0 + row_block], np.float64)
+        Yb = np.asarray(Y[i0:i0 + row_block], np.float64)
+        g += Xb.T @ (Yb - Xb @ beta)
+    return g
+
+
+def mihs_step(beta, beta_prev, g, R, mu, eta):
+    return beta + mu * apply_precond(R, g) + eta * (beta - beta_prev)
+
+
+def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
+             momentum_reset=False, sk=None, **sketch_kw):
+    """Run Alg. 2 and return (beta_T, trajectory, info).
+
+    trajectory[t] is beta_t for t = 0..T (T = sum(a) + s).  `sk` may pass a
+    precomputed oracle sketch (same seed and sizes) to avoid recomputing it.
+    """
+    d = X.shape[1]
+    if mu is None or eta is None:
+        mu0, eta0 = default_params(d, r)
+        mu = mu0 if mu is None else mu
+        eta = eta0 if eta is None else eta
+    if sk is None:
+        sk = make_sketch(kind, X, Y, seed, m, r, **sketch_kw)
+    R = precond_factor(sk["Ahat"], d, sk["hat_scale"])
+    beta = np.zeros(d) if beta0 is None else np.asarray(beta0, np.float64).copy()
+    beta_prev = beta.copy()
+    traj = [beta.copy()]
+    for i, (mi, ai) in enumerate(zip(sk["m"], a)):
+        Ai = sk["A"][sk["offset"][i]: sk["offset"][i] + mi]
+        if momentum_reset:
+            beta_prev = beta.copy()
+        for _ in range(ai):
+            g = sketched_grad(Ai, d, sk["scale"][i], beta)
+            beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
+            traj.append(beta.copy())
+    if momentum_reset:
+        beta_prev = beta.copy()
+    for _ in range(s):
+        g = full_grad(X, Y, beta)
+        beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
+        traj.append(beta.copy())
+    return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta)
+
+
+def paper_schedule(n, d, m1_factor=8):
+    """m_1 = 8d, m_{i+1} = 2 m_i, m_K = the largest power of 2 <= N/2 (Sec. 5, Sec. 3).
+
+    When 8d is not a power of 2 the schedule starts at the power of 2 above it.
+    """
+    m1 = 1 << max(0, (m1_factor * d - 1).bit_length())
+    mk = 1 << ((n // 2).bit_length() - 1)
+    m = []
+    v = m1
+    while v <= mk:
+        m.append(v)
+        v *= 2
+    return m
+
+
+def rel_err(beta, ref):
+    return float(np.linalg.norm(np.asarray(beta) - ref) / np.linalg.norm(ref))
