@@ -1,0 +1,78 @@
+// Shared host/device helpers of libslse: status plumbing, HIP checks, small
+// device utilities.  Internal header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/slse.h"
+
+namespace slse {
+
+// ---------------------------------------------------------------------------
+// Errors.  Internal code throws slse::Error; the C-ABI entry points catch it
+// and turn it into a status plus a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error {
+  slse_status status;
+  std::string msg;
+};
+
+void set_last_error(const std::string& msg);
+
+[[noreturn]] inline void fail(slse_status st, const std::string& msg) { throw Error{st, msg}; }
+
+inline void require(bool ok, const std::string& msg) {
+  if (!ok) fail(SLSE_EINVAL, msg);
+}
+
+#define SLSE_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::slse::fail(e_ == hipErrorOutOfMemory ? SLSE_ENOMEM : SLSE_EDEVICE,             \
+                   std::string(#call) + " failed: " + hipGetErrorString(e_));          \
+    }                                                                                  \
+  } while (0)
+
+#define SLSE_LAUNCH_CHECK() SLSE_HIP(hipGetLastError())
+
+inline size_t dtype_size(slse_dtype t) {
+  switch (t) {
+    case SLSE_F32: return 4;
+    case SLSE_F64: return 8;
+    case SLSE_BF16: return 2;
+  }
+  return 0;
+}
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+inline int ilog2_exact(int64_t v) {
+  int p = 0;
+  while ((int64_t(1) << p) < v) ++p;
+  return p;
+}
+
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_xor(T v, int mask) {
+  return __shfl_xor(v, mask, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_group_sum(T v, int group) {
+  // all-reduce inside aligned groups of `group` lanes (power of 2 <= 64)
+  for (int m = group >> 1; m > 0; m >>= 1) v += wave_xor(v, m);
+  return v;
+}
+
+}  // namespace slse

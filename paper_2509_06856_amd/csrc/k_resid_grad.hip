@@ -1,0 +1,296 @@
+// Fused residual-gradient pass g = X^T (Y - X beta) (the full-data gradient
+// of eq. (99), and of eq. (98) on a sketched prefix), reading X once.
+//
+// Layout: a row of X is split over a group of `lpr` lanes; lane l of the group
+// owns the vector chunks c*lpr + l (c < NCH) of VEC consecutive elements, so a
+// wave's loads of one row are contiguous.  Per row the group forms the partial
+// dot x_j . beta, all-reduces it across its lanes (xor shuffles), and every
+// lane folds r_j = y_j - x_j . beta into its own slice of g.  A wave streams
+// 64/lpr rows per step, UNROLL steps in flight.  At the end the wave's row
+// groups, then the block's waves, are summed; the block writes one partial
+// row; the last block of every group of `group_size` blocks adds its group's
+// rows in block order (deterministic for a fixed launch shape).
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace slse {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int VEC>
+struct VecT;
+template <>
+struct VecT<double, 2> {
+  using type = f64x2;
+};
+template <>
+struct VecT<float, 4> {
+  using type = f32x4;
+};
+template <>
+struct VecT<double, 1> {
+  using type = double;
+};
+template <>
+struct VecT<float, 1> {
+  using type = float;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
+  using V = typename VecT<T, VEC>::type;
+  V x = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  if constexpr (VEC == 1) {
+    v[0] = x;
+  } else {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) v[i] = x[i];
+  }
+}
+
+template <typename T, typename Acc, int VEC, int NCH, bool HAS_Y>
+__global__ __launch_bounds__(kThreads) void resid_grad_kernel(
+    int64_t n, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t incy,
+    const double* __restrict__ beta, int lpr, double* __restrict__ partial,
+    double* __restrict__ gpart, int* __restrict__ counters, int group_size, int ldp,
+    const int* __restrict__ done) {
+  constexpr int UNROLL = NCH >= 8 ? 1 : (8 / NCH);
+  if (done && *done) return;
+  __shared__ double s_red[kWaves][1025];
+  __shared__ int s_ticket;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gpw = 64 / lpr;  // row groups per wave
+  const int grp = lane / lpr;
+  const int l = lane - grp * lpr;
+
+  // beta slice of this lane
+  Acc b[NCH][VEC];
+  bool full[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int col0 = (c * lpr + l) * VEC;
+    full[c] = col0 + VEC <= d;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) b[c][v] = (col0 + v < d) ? (Acc)beta[col0 + v] : (Acc)0;
+  }
+
+  Acc acc[NCH][VEC];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[c][v] = 0;
+  Acc rr = 0;
+
+  const int64_t stride = (int64_t)gridDim.x * kWaves * gpw;
+  const int64_t gg = ((int64_t)blockIdx.x * kWaves + wave) * gpw + grp;
+
+  for (int64_t base = gg; base < n; base += stride * UNROLL) {
+    T x[UNROLL][NCH][VEC];
+    T y[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t row = base + (int64_t)u * stride;
+      const bool ok = row < n;
+      const T* xr = X + (ok ? row : 0) * ldx;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int col0 = (c * lpr + l) * VEC;
+        if (ok && full[c]) {
+          load_vec<T, VEC>(xr + col0, x[u][c]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) x[u][c][v] = (ok && col0 + v < d) ? xr[col0 + v] : (T)0;
+        }
+      }
+      if constexpr (HAS_Y) {
+        y[u] = ok ? Y[row * incy] : (T)0;
+      } else {
+        y[u] = 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      Acc dot = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) dot = fma((Acc)x[u][c][v], b[c][v], dot);
+      dot = lane_group_sum(dot, lpr);
+      const Acc r = (Acc)y[u] - dot;  // zero for rows past n (x = y = 0)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, (Acc)x[u][c][v], acc[c][v]);
+      rr = fma(r, r, rr);
+    }
+  }
+
+  // sum the wave's row groups: lanes with equal l hold the same columns
+  double accd[NCH][VEC];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      double t = (double)acc[c][v];
+      for (int m = lpr; m < 64; m <<= 1) t += wave_xor(t, m);
+      accd[c][v] = t;
+    }
+  double rrd = (double)rr;  // every lane of a group holds the same r: count lane l == 0 only
+  rrd = (l == 0) ? rrd : 0.0;
+  for (int m = 1; m < 64; m <<= 1) rrd += wave_xor(rrd, m);
+
+  // block reduction through LDS (columns d.. handled by the spill loop below)
+  double* prow = partial + (int64_t)blockIdx.x * ldp;
+  for (int c0 = 0; c0 < d + 1; c0 += 1024) {
+    if (grp == 0) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int col = (c * lpr + l) * VEC + v;
+          if (col >= c0 && col < c0 + 1024 && col < d) s_red[wave][col - c0] = accd[c][v];
+        }
+      if (l == 0 && d >= c0 && d < c0 + 1024) s_red[wave][d - c0] = rrd;
+    }
+    __syncthreads();
+    for (int col = c0 + threadIdx.x; col < min(d + 1, c0 + 1024); col += kThreads) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += s_red[w][col - c0];
+      prow[col] = t;
+    }
+    __syncthreads();
+  }
+
+  // last block of the group sums the group's partial rows in block order
+  __threadfence();
+  __syncthreads();
+  const int group = blockIdx.x / group_size;
+  const int g0 = group * group_size;
+  const int gsz = min(group_size, (int)gridDim.x - g0);
+  if (threadIdx.x == 0) s_ticket = atomicAdd(&counters[group], 1);
+  __syncthreads();
+  if (s_ticket == gsz - 1) {
+    __threadfence();
+    for (int col = threadIdx.x; col < d + 1; col += kThreads) {
+      double t = 0.0;
+      for (int bk = 0; bk < gsz; ++bk) t += partial[(int64_t)(g0 + bk) * ldp + col];
+      gpart[(int64_t)group * ldp + col] = t;
+    }
+    if (threadIdx.x == 0) atomicExch(&counters[group], 0);
+  }
+}
+
+__global__ void finalize_grad_kernel(const double* __restrict__ gpart, int groups, int ldp, int d,
+                                     double scale, double* __restrict__ g, double* __restrict__ rn) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col > d) return;
+  double t = 0.0;
+  for (int k = 0; k < groups; ++k) t += gpart[(int64_t)k * ldp + col];
+  if (col < d) {
+    g[col] = scale * t;
+  } else if (rn) {
+    rn[0] = scale * t;
+  }
+}
+
+template <typename T, typename Acc, int VEC, int NCH>
+void launch_t(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
+  const T* X = static_cast<const T*>(a.X);
+  const T* Y = static_cast<const T*>(a.Y);
+  if (Y) {
+    resid_grad_kernel<T, Acc, VEC, NCH, true><<<pl.blocks, kThreads, 0, s>>>(
+        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters,
+        pl.group_size, pl.ldp, a.done);
+  } else {
+    resid_grad_kernel<T, Acc, VEC, NCH, false><<<pl.blocks, kThreads, 0, s>>>(
+        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters,
+        pl.group_size, pl.ldp, a.done);
+  }
+}
+
+template <typename T, typename Acc, int VEC>
+void launch_nch(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
+  switch (pl.nch) {
+    case 1: launch_t<T, Acc, VEC, 1>(pl, a, s); break;
+    case 2: launch_t<T, Acc, VEC, 2>(pl, a, s); break;
+    case 4: launch_t<T, Acc, VEC, 4>(pl, a, s); break;
+    case 8: launch_t<T, Acc, VEC, 8>(pl, a, s); break;
+    case 16: launch_t<T, Acc, VEC, 16>(pl, a, s); break;
+    default: fail(SLSE_EUNSUPPORTED, "resid_grad: unsupported chunk count");
+  }
+}
+
+template <typename T, typename Acc>
+void launch_vec(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  if (pl.vec == V) {
+    launch_nch<T, Acc, V>(pl, a, s);
+  } else {
+    launch_nch<T, Acc, 1>(pl, a, s);
+  }
+}
+
+}  // namespace
+
+ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
+                              int max_blocks) {
+  ResidGradPlan pl;
+  const int es = (int)dtype_size(storage);
+  const int vfull = 16 / es;
+  const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * es) % 16 == 0);
+  pl.vec = aligned ? vfull : 1;
+  const int nvec = (int)ceil_div(d, pl.vec);
+  // widest power-of-2 lane group that still leaves >= 2 vector chunks per lane
+  int lpr = 1;
+  while (lpr < 64 && lpr * 4 <= nvec) lpr *= 2;
+  int nch = (int)ceil_div(nvec, lpr);
+  int p2 = 1;
+  while (p2 < nch) p2 *= 2;
+  if (p2 > 16) fail(SLSE_EUNSUPPORTED, "resid_grad: d too large for this build");
+  pl.lpr = lpr;
+  pl.nch = p2;
+  pl.ldp = (int)round_up(d + 1, 8);
+  const int rows_per_block_step = kWaves * (64 / lpr);
+  const int unroll = p2 >= 8 ? 1 : 8 / p2;
+  int64_t want = ceil_div(std::max<int64_t>(n, 1), (int64_t)rows_per_block_step * unroll);
+  pl.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, max_blocks));
+  pl.group_size = 32;
+  pl.groups = (int)ceil_div(pl.blocks, pl.group_size);
+  return pl;
+}
+
+void launch_resid_grad(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
+  if (a.storage == SLSE_F64) {
+    if (a.accum == SLSE_F64)
+      launch_vec<double, double>(pl, a, s);
+    else
+      launch_vec<double, float>(pl, a, s);
+  } else if (a.storage == SLSE_F32) {
+    if (a.accum == SLSE_F64)
+      launch_vec<float, double>(pl, a, s);
+    else
+      launch_vec<float, float>(pl, a, s);
+  } else {
+    fail(SLSE_EUNSUPPORTED, "resid_grad: storage must be F32 or F64");
+  }
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_finalize_grad(const double* gpart, int groups, int ldp, int d, double scale,
+                          double* g_out, double* rnorm2_out, hipStream_t s) {
+  const int threads = 256;
+  finalize_grad_kernel<<<(int)ceil_div(d + 1, threads), threads, 0, s>>>(gpart, groups, ldp, d,
+                                                                         scale, g_out, rnorm2_out);
+  SLSE_LAUNCH_CHECK();
+}
+
+}  // namespace slse

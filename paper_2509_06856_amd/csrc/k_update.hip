@@ -1,0 +1,150 @@
+// M-IHS step with a fixed Hessian sketch (eqs. (98) and (99)):
+//   beta_{t+1} = beta_t + mu * H_hat^{-1} g_t + eta * (beta_t - beta_{t-1}),
+// g_t = c X^T (Y - X beta_t) being the negative gradient produced by the fused
+// residual-gradient pass (its per-group partial rows are summed here, in a
+// fixed order).  H_hat^{-1} is applied as the dense symmetric matrix
+// M = R^{-1} R^{-T} (a GEMV spread over blocks).  The step also reduces
+//   ||M g_t||^2 and ||beta_{t+1}||^2,
+// whose ratio estimates the relative error of beta_t against the fixed point
+// (beta_hat - beta_t = H^{-1} g_t and M ~ H^{-1}); the last block to finish
+// writes it, flags non-finite values and raises `done` when it meets tol.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace slse {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int rows_per_block) {
+  if (a.done && *a.done) return;
+  extern __shared__ double s_g[];
+  __shared__ double s_red[3][kWaves];
+  __shared__ int s_ticket;
+  const int d = a.d;
+  for (int k = threadIdx.x; k < d; k += kThreads) {
+    double t = 0.0;
+    for (int q = 0; q < a.groups; ++q) t += a.gpart[(int64_t)q * a.ldp + k];
+    double g = a.scale * t;
+    if (a.w) g += a.w[k];
+    s_g[k] = g;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double gp = 0.0, pp = 0.0, bb = 0.0;
+  const int row0 = blockIdx.x * rows_per_block;
+  for (int j = wave; j < rows_per_block; j += kWaves) {
+    const int i = row0 + j;
+    if (i >= d) break;
+    const double* Mi = a.M + (int64_t)i * a.ldm;
+    double p = 0.0;
+    for (int k = lane; k < d; k += 64) p = fma(Mi[k], s_g[k], p);
+    for (int m = 32; m > 0; m >>= 1) p += wave_xor(p, m);
+    if (lane == 0) {
+      const double bi = a.beta[i];
+      const double bn = bi + a.mu * p + a.eta * (bi - a.beta_prev[i]);
+      a.beta_next[i] = bn;
+      if (a.beta_out) a.beta_out[i] = bn;
+      if (a.traj_row) a.traj_row[i] = bn;
+      gp += s_g[i] * p;
+      pp += p * p;
+      bb += bn * bn;
+    }
+  }
+  if (!a.sur_partial) return;
+  if (lane == 0) {
+    s_red[0][wave] = gp;
+    s_red[1][wave] = pp;
+    s_red[2][wave] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += s_red[threadIdx.x][w];
+    a.sur_partial[3 * blockIdx.x + threadIdx.x] = t;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_ticket = atomicAdd(a.sur_counter, 1);
+  __syncthreads();
+  if (s_ticket != (int)gridDim.x - 1) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double tgp = 0.0, tpp = 0.0, tbb = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) {
+      tgp += a.sur_partial[3 * b + 0];
+      tpp += a.sur_partial[3 * b + 1];
+      tbb += a.sur_partial[3 * b + 2];
+    }
+    const double est = tbb > 0.0 ? sqrt(tpp / tbb) : sqrt(tpp);
+    if (a.sur_out) a.sur_out[0] = est;
+    const bool finite = isfinite(tgp) && isfinite(tpp) && isfinite(tbb);
+    if (!finite && a.status) atomicExch(a.status, 1);
+    if (a.done && a.tol2 > 0.0 && (!finite || est * est <= a.tol2)) atomicExch(a.done, 1);
+    atomicExch(a.sur_counter, 0);
+  }
+}
+
+__global__ void fill_i32_kernel(int* __restrict__ p, int v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void copy_f64_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 4096)); }
+
+int rows_per_block_for(int d) {
+  // about 64 blocks: each block re-reads the group partials, so fewer blocks
+  // for larger d keep that traffic near the size of M itself
+  int rpb = (int)ceil_div(d, 64);
+  return (int)round_up(std::max(rpb, kWaves), kWaves);
+}
+
+}  // namespace
+
+int update_blocks(int d) { return (int)ceil_div(d, rows_per_block_for(d)); }
+
+void launch_update(const UpdateArgs& a, hipStream_t s) {
+  const int rpb = rows_per_block_for(a.d);
+  const int blocks = (int)ceil_div(a.d, rpb);
+  const size_t shm = (size_t)a.d * sizeof(double);
+  if (shm > 64 * 1024) fail(SLSE_EUNSUPPORTED, "update: d too large for this build");
+  mihs_update_kernel<<<blocks, kThreads, shm, s>>>(a, rpb);
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_fill_i32(int* dst, int value, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  fill_i32_kernel<<<grid_for(n), 256, 0, s>>>(dst, value, n);
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_fill_f64(double* dst, double value, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  fill_f64_kernel<<<grid_for(n), 256, 0, s>>>(dst, value, n);
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  copy_f64_kernel<<<grid_for(n), 256, 0, s>>>(src, dst, n);
+  SLSE_LAUNCH_CHECK();
+}
+
+}  // namespace slse

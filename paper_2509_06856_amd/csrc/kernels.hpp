@@ -1,0 +1,210 @@
+// Internal launchers of libslse's device kernels.  Every launcher enqueues on
+// `stream` and checks the launch; shapes are validated by the caller.
+#pragma once
+
+#include "common.hpp"
+
+namespace slse {
+
+// --------------------------------------------------------------------------
+// Fused residual-gradient (one pass over X): per-group partial sums of
+//   X[0:n]^T (Y - X beta)   and   ||Y - X beta||^2
+// written to gpart[group][0..d] (index d holds the residual norm).  The
+// launch reduces its block partials to `groups` rows itself (the last block
+// of each group sums its group's blocks in a fixed order).
+// --------------------------------------------------------------------------
+struct ResidGradPlan {
+  int blocks = 0;
+  int groups = 0;
+  int group_size = 0;
+  int lpr = 0;   // lanes per row
+  int vec = 0;   // elements per vector load
+  int nch = 0;   // vector chunks per lane
+  int ldp = 0;   // leading dimension of partial rows (>= d + 1)
+};
+
+ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
+                              int max_blocks);
+
+struct ResidGradArgs {
+  int64_t n = 0;
+  int d = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  const void* Y = nullptr;  // may be null (Y = 0)
+  int64_t incy = 1;
+  slse_dtype storage = SLSE_F64;
+  slse_dtype accum = SLSE_F64;
+  const double* beta = nullptr;
+  double* partial = nullptr;  // [blocks][ldp]
+  double* gpart = nullptr;    // [groups][ldp]
+  int* counters = nullptr;    // [groups], zero before the first launch; left zero
+  const int* done = nullptr;  // optional early-exit flag
+};
+
+void launch_resid_grad(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s);
+
+// g = scale * sum_g gpart[g][0..d) (and rnorm2 = scale * sum_g gpart[g][d]).
+void launch_finalize_grad(const double* gpart, int groups, int ldp, int d, double scale,
+                          double* g_out, double* rnorm2_out, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// M-IHS update (eqs. (98)/(99)) with the preconditioner M = H_hat^{-1}:
+//   g      = scale * sum_groups gpart (+ w)
+//   p      = M g
+//   beta'  = beta + mu p + eta (beta - beta_prev)
+// surrogate ||R^{-T} g||^2 = g . p is reduced into sur_out[0] (if given);
+// when tol2 > 0 the step that brings it to <= tol2 * sur_ref[0] raises
+// `done`, and later steps are skipped.
+// --------------------------------------------------------------------------
+struct UpdateArgs {
+  const double* gpart = nullptr;
+  int groups = 0;
+  int ldp = 0;
+  int d = 0;
+  double scale = 1.0;
+  const double* w = nullptr;  // added to g (adjoint right-hand side), may be null
+  const double* M = nullptr;
+  int64_t ldm = 0;
+  const double* beta = nullptr;
+  const double* beta_prev = nullptr;
+  double* beta_next = nullptr;
+  double mu = 1.0;
+  double eta = 0.0;
+  double* beta_out = nullptr;     // copy of beta_next (may be null)
+  double* traj_row = nullptr;     // copy of beta_next (may be null)
+  double* sur_partial = nullptr;  // [blocks] scratch
+  int* sur_counter = nullptr;     // zero before first use; left zero
+  double* sur_out = nullptr;      // surrogate of this step (may be null)
+  const double* sur_ref = nullptr;
+  double tol2 = 0.0;
+  int* done = nullptr;            // early-exit flag (may be null)
+  int* status = nullptr;          // set to 1 on a non-finite surrogate (may be null)
+};
+
+int update_blocks(int d);
+void launch_update(const UpdateArgs& a, hipStream_t s);
+
+// beta' = beta + mu * M * v (used for lambda_0 = H_hat^{-1} w; beta_prev = beta).
+void launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+void launch_fill_i32(int* dst, int value, int64_t n, hipStream_t s);
+void launch_fill_f64(double* dst, double value, int64_t n, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// SRHT: index maps and Walsh-Hadamard passes.
+// --------------------------------------------------------------------------
+struct SrhtArgs {
+  slse_dtype t = SLSE_F64;
+  int64_t N = 0;
+  int d = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  const void* Y = nullptr;
+  uint64_t seed = 0;
+  int p = 0;  // N' = 2^p
+  int64_t mK = 0;
+  int64_t r = 0;
+  void* A = nullptr;
+  int64_t lda = 0;
+  void* Ahat = nullptr;
+  int64_t ldah = 0;
+  // scratch
+  int32_t* pi_sgn = nullptr;  // [N']
+  int32_t* slotA = nullptr;   // [N']
+  int32_t* slotH = nullptr;   // [N']
+  void* Z = nullptr;          // [N'][ldz]
+  int64_t ldz = 0;
+  int ct = 0;                 // column tile (chosen by srht_plan)
+  int bmax = 0;               // stages per pass cap
+};
+
+void srht_plan(SrhtArgs& a, int prefer_ct);
+size_t srht_z_bytes(const SrhtArgs& a);
+void launch_srht(const SrhtArgs& a, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// CountSketch and Gaussian sketches.
+// --------------------------------------------------------------------------
+struct CountSketchArgs {
+  slse_dtype t = SLSE_F64;
+  int64_t N = 0;
+  int d = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  const void* Y = nullptr;
+  uint64_t seed = 0;
+  const int64_t* m = nullptr;
+  int K = 0;
+  int64_t r = 0;
+  void* A = nullptr;  // levels back to back, m_1 first
+  int64_t lda = 0;
+  void* Ahat = nullptr;
+  int64_t ldah = 0;
+};
+void launch_countsketch(const CountSketchArgs& a, hipStream_t s);
+
+struct GaussianArgs {
+  slse_dtype t = SLSE_F64;
+  int64_t N = 0;
+  int d = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  const void* Y = nullptr;
+  uint64_t seed = 0;
+  int64_t m = 0;
+  uint64_t stream_id = 7;
+  void* A = nullptr;
+  int64_t lda = 0;
+  float* partial = nullptr;   // split-K scratch
+  double* partial64 = nullptr;
+  int splits = 0;
+};
+size_t gaussian_scratch_bytes(const GaussianArgs& a);
+void gaussian_plan(GaussianArgs& a);
+void launch_gaussian(const GaussianArgs& a, hipStream_t s);
+void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_t nk, int64_t j0,
+                           int64_t nj, double* out, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// Dense FP64 helpers for the factorization.
+// --------------------------------------------------------------------------
+// C[MxN] = alpha * op(A) * op(B) + beta * C, all FP64 row-major.
+void launch_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                     bool transA, const double* B, int64_t ldb, bool transB, double beta, double* C,
+                     int64_t ldc, hipStream_t s);
+// out[i][k] = s * A[i][k] for i < rows, k < d (A in F32 or F64).
+void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_dtype at, double s,
+                          double* out, int64_t ldo, hipStream_t st);
+// R = upper Cholesky factor of the SPD d x d matrix G (R^T R = G); info[0] = 0 or (j+1) of the
+// first bad pivot.  G is read only.
+void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr, int* info,
+                     hipStream_t s);
+// L = R^{-T} (lower triangular, row-major d x d) for upper triangular R.
+void launch_tri_inv_t(int d, const double* R, int64_t ldr, double* L, int64_t ldl, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// Adjoint rank-2 pass: dY = X lambda, dX = r lambda^T - (X lambda) beta^T.
+// --------------------------------------------------------------------------
+struct AdjointArgs {
+  int64_t n = 0;
+  int d = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  const void* Y = nullptr;
+  slse_dtype t = SLSE_F64;
+  const double* beta = nullptr;
+  const double* lambda = nullptr;
+  void* dX = nullptr;
+  int64_t lddx = 0;
+  void* dY = nullptr;
+  slse_dtype gt = SLSE_F64;
+};
+void launch_adjoint(const AdjointArgs& a, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// Test hooks.
+// --------------------------------------------------------------------------
+void launch_debug_stream(int what, uint64_t seed, int stream_id, int64_t aux, int64_t start,
+                         int64_t count, int64_t* out, hipStream_t s);
+
+}  // namespace slse

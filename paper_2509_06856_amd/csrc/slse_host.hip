@@ -1,0 +1,940 @@
+// Host side of libslse: context and scratch memory, the solve driver of
+// Alg. 2 (sketch once, factor H_hat, stage-1 steps on nested sketched
+// prefixes, stage-2 full-data steps), its hipGraph capture, the adjoint
+// driver and the C-ABI entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace slse {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Scratch arena: named grow-only device buffers.  Growing a buffer frees the
+// old one, so every captured graph is dropped when that happens.
+// ---------------------------------------------------------------------------
+struct Arena {
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  bool grew = false;
+
+  void* get(const std::string& name, size_t bytes, bool zero_init = false) {
+    bytes = std::max<size_t>(bytes, 256);
+    Buf& b = bufs[name];
+    if (b.bytes >= bytes) return b.p;
+    if (b.p) SLSE_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    void* p = nullptr;
+    SLSE_HIP(hipMalloc(&p, bytes));
+    if (zero_init) {
+      SLSE_HIP(hipMemset(p, 0, bytes));
+      SLSE_HIP(hipDeviceSynchronize());
+    }
+    b.p = p;
+    b.bytes = bytes;
+    grew = true;
+    return p;
+  }
+  template <typename T>
+  T* get_t(const std::string& name, size_t count, bool zero_init = false) {
+    return static_cast<T*>(get(name, count * sizeof(T), zero_init));
+  }
+  void release() {
+    for (auto& kv : bufs)
+      if (kv.second.p) (void)hipFree(kv.second.p);
+    bufs.clear();
+  }
+};
+
+}  // namespace slse
+
+struct slse_ctx {
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t capture_stream = nullptr;
+  slse::Arena arena;
+  // preconditioner of the last solve (reused by slse_backward)
+  struct {
+    bool valid = false;
+    uint64_t seed = 0;
+    int kind = -1;
+    int64_t N = 0, d = 0, r = 0;
+    const void* X = nullptr;
+    int precision = 0;
+  } pre;
+  std::map<std::string, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+};
+
+namespace slse {
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    SLSE_HIP(hipGetDevice(&prev));
+    if (prev != dev) SLSE_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Validation and layout of the sketch.
+// ---------------------------------------------------------------------------
+struct SketchShape {
+  slse_sketch_kind kind;
+  int64_t N, d, r;
+  int K;
+  std::vector<int64_t> m;
+  int p = 0;
+  int64_t n_pad = 0;
+  int64_t rows_A = 0;
+  std::vector<int64_t> offset;
+  std::vector<double> scale;
+  double hat_scale = 1.0;
+};
+
+SketchShape make_sketch_shape(slse_sketch_kind kind, int64_t N, int64_t d, const int64_t* m, int K,
+                              int64_t r) {
+  require(N > 0 && d >= 1 && N > d, "need N > d >= 1");
+  require(d <= 1024, "d > 1024 is not supported by this build");
+  require(K >= 1 && K <= SLSE_MAX_LEVELS && m != nullptr, "need 1 <= K <= SLSE_MAX_LEVELS");
+  require(r > d, "need r > d");
+  SketchShape s;
+  s.kind = kind;
+  s.N = N;
+  s.d = d;
+  s.r = r;
+  s.K = K;
+  s.m.assign(m, m + K);
+  require(s.m[0] >= 1, "sketch sizes must be positive");
+  for (int i = 1; i < K; ++i) require(s.m[i] > s.m[i - 1], "sketch sizes must increase");
+  s.offset.resize(K);
+  s.scale.resize(K);
+  if (kind == SLSE_SRHT) {
+    s.p = std::max(1, ilog2_exact(N));
+    require(s.p <= 30, "N too large for this build (N' <= 2^30)");
+    s.n_pad = int64_t(1) << s.p;
+    require(s.m[K - 1] <= s.n_pad && r <= s.n_pad, "SRHT: m_K and r must be <= N'");
+    for (int i = 0; i < K; ++i) {
+      s.offset[i] = 0;
+      s.scale[i] = 1.0 / (double)s.m[i];
+    }
+    s.rows_A = s.m[K - 1];
+    s.hat_scale = 1.0 / (double)r;
+  } else if (kind == SLSE_COUNTSKETCH) {
+    s.n_pad = N;
+    int64_t off = 0;
+    for (int i = 0; i < K; ++i) {
+      require(is_pow2(s.m[i]), "CountSketch: every m_i must be a power of 2");
+      s.offset[i] = off;
+      s.scale[i] = 1.0;
+      off += s.m[i];
+    }
+    s.rows_A = off;
+    s.hat_scale = 1.0;
+  } else if (kind == SLSE_GAUSSIAN) {
+    s.n_pad = N;
+    for (int i = 0; i < K; ++i) {
+      s.offset[i] = 0;
+      s.scale[i] = 1.0 / (double)s.m[i];
+    }
+    s.rows_A = s.m[K - 1];
+    s.hat_scale = 1.0 / (double)r;
+  } else {
+    fail(SLSE_EINVAL, "unknown sketch kind");
+  }
+  return s;
+}
+
+void fill_layout(const SketchShape& s, slse_sketch_layout* L) {
+  if (!L) return;
+  std::memset(L, 0, sizeof(*L));
+  L->K = s.K;
+  for (int i = 0; i < s.K; ++i) {
+    L->m[i] = s.m[i];
+    L->offset[i] = s.offset[i];
+    L->scale[i] = s.scale[i];
+  }
+  L->rows_A = s.rows_A;
+  L->r = s.r;
+  L->hat_scale = s.hat_scale;
+  L->n_pad = s.n_pad;
+}
+
+// Reserve every scratch buffer the sketch needs (no kernel launched).
+void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs* srht,
+                    GaussianArgs* ga, GaussianArgs* gh) {
+  if (s.kind == SLSE_SRHT) {
+    srht->t = t;
+    srht->N = s.N;
+    srht->d = (int)s.d;
+    srht->p = s.p;
+    srht->mK = s.m[s.K - 1];
+    srht->r = s.r;
+    srht_plan(*srht, 0);
+    srht->pi_sgn = ctx->arena.get_t<int32_t>("srht_pi", s.n_pad);
+    srht->slotA = ctx->arena.get_t<int32_t>("srht_slotA", s.n_pad);
+    srht->slotH = ctx->arena.get_t<int32_t>("srht_slotH", s.n_pad);
+    const size_t zb = srht_z_bytes(*srht);
+    srht->Z = zb ? ctx->arena.get("srht_Z", zb) : nullptr;
+  } else if (s.kind == SLSE_GAUSSIAN) {
+    for (GaussianArgs* g : {ga, gh}) {
+      g->t = t;
+      g->N = s.N;
+      g->d = (int)s.d;
+    }
+    ga->m = s.m[s.K - 1];
+    ga->stream_id = 7;
+    gh->m = s.r;
+    gh->stream_id = 8;
+    gaussian_plan(*ga);
+    gaussian_plan(*gh);
+    const size_t b = std::max(gaussian_scratch_bytes(*ga), gaussian_scratch_bytes(*gh));
+    void* p = ctx->arena.get("gauss_part", b);
+    ga->partial = gh->partial = static_cast<float*>(p);
+    ga->partial64 = gh->partial64 = static_cast<double*>(p);
+  }
+}
+
+void enqueue_sketch(const SketchShape& s, uint64_t seed, const void* X, int64_t ldx, const void* Y,
+                    slse_dtype t, void* A, int64_t lda, void* Ahat, int64_t ldah, SrhtArgs srht,
+                    GaussianArgs ga, GaussianArgs gh, hipStream_t st) {
+  if (s.kind == SLSE_SRHT) {
+    srht.X = X;
+    srht.ldx = ldx;
+    srht.Y = Y;
+    srht.seed = seed;
+    srht.A = A;
+    srht.lda = lda;
+    srht.Ahat = Ahat;
+    srht.ldah = ldah;
+    launch_srht(srht, st);
+  } else if (s.kind == SLSE_COUNTSKETCH) {
+    CountSketchArgs c;
+    c.t = t;
+    c.N = s.N;
+    c.d = (int)s.d;
+    c.X = X;
+    c.ldx = ldx;
+    c.Y = Y;
+    c.seed = seed;
+    c.m = s.m.data();
+    c.K = s.K;
+    c.r = s.r;
+    c.A = A;
+    c.lda = lda;
+    c.Ahat = Ahat;
+    c.ldah = ldah;
+    launch_countsketch(c, st);
+  } else {
+    for (GaussianArgs* g : {&ga, &gh}) {
+      g->X = X;
+      g->ldx = ldx;
+      g->Y = Y;
+      g->seed = seed;
+    }
+    ga.A = A;
+    ga.lda = lda;
+    gh.A = Ahat;
+    gh.lda = ldah;
+    launch_gaussian(ga, st);
+    launch_gaussian(gh, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factorization: R^T R = scale A^T A, then L = R^{-T} and M = L^T L = H_hat^{-1}.
+// ---------------------------------------------------------------------------
+struct FactorBufs {
+  double* Ad = nullptr;  // rows x d
+  double* G = nullptr;   // d x d
+  double* R = nullptr;   // d x d (ldr)
+  double* L = nullptr;   // d x d
+  double* M = nullptr;   // d x d
+  double* Q = nullptr;   // rows x d (QR route)
+  double* R2 = nullptr;  // d x d (QR route)
+  int* info = nullptr;   // 2 ints
+};
+
+FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_method method) {
+  FactorBufs f;
+  f.Ad = ctx->arena.get_t<double>("f_Ad", rows * d);
+  f.G = ctx->arena.get_t<double>("f_G", d * d);
+  f.R = ctx->arena.get_t<double>("f_R", d * d);
+  f.L = ctx->arena.get_t<double>("f_L", d * d);
+  f.M = ctx->arena.get_t<double>("f_M", d * d);
+  if (method == SLSE_FACTOR_QR) {
+    f.Q = ctx->arena.get_t<double>("f_Q", rows * d);
+    f.R2 = ctx->arena.get_t<double>("f_R2", d * d);
+  }
+  f.info = ctx->arena.get_t<int>("f_info", 4, true);
+  return f;
+}
+
+// R (ldr = d) and M (ldm = d) into f.R / f.M.
+void enqueue_factor(const FactorBufs& f, int64_t rows, int d, const void* A, int64_t lda,
+                    slse_dtype at, double scale, slse_factor_method method, hipStream_t st) {
+  launch_convert_scale(rows, d, A, lda, at, std::sqrt(scale), f.Ad, d, st);
+  launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st);
+  launch_cholesky(d, f.G, d, f.R, d, f.info, st);
+  if (method == SLSE_FACTOR_QR) {
+    // CholeskyQR2: Q1 = Ad R1^{-1}, R2 = chol(Q1^T Q1), R = R2 R1
+    launch_tri_inv_t(d, f.R, d, f.L, d, st);
+    launch_gemm_f64(rows, d, d, 1.0, f.Ad, d, false, f.L, d, true, 0.0, f.Q, d, st);
+    launch_gemm_f64(d, d, rows, 1.0, f.Q, d, true, f.Q, d, false, 0.0, f.G, d, st);
+    launch_cholesky(d, f.G, d, f.R2, d, f.info + 1, st);
+    launch_gemm_f64(d, d, d, 1.0, f.R2, d, false, f.R, d, false, 0.0, f.G, d, st);
+    launch_copy_f64(f.G, f.R, (int64_t)d * d, st);
+  }
+  launch_tri_inv_t(d, f.R, d, f.L, d, st);
+  launch_gemm_f64(d, d, d, 1.0, f.L, d, true, f.L, d, false, 0.0, f.M, d, st);
+}
+
+// ---------------------------------------------------------------------------
+// The M-IHS iteration engine shared by the forward solve and the adjoint.
+// ---------------------------------------------------------------------------
+struct IterBufs {
+  double* beta[3];
+  double* partial = nullptr;
+  double* gpart = nullptr;
+  int* counters = nullptr;
+  double* sur_partial = nullptr;
+  int* sur_counter = nullptr;
+  int* flags = nullptr;  // [0] done, [1] non-finite
+  int max_blocks = 1024;
+};
+
+IterBufs reserve_iter(slse_ctx* ctx, int64_t d, const char* tag) {
+  IterBufs b;
+  std::string t(tag);
+  for (int i = 0; i < 3; ++i) b.beta[i] = ctx->arena.get_t<double>(t + "_beta" + char('0' + i), d);
+  b.max_blocks = std::max(256, 4 * ctx->num_cus);
+  const int64_t ldp = round_up(d + 1, 8);
+  b.partial = ctx->arena.get_t<double>(t + "_partial", b.max_blocks * ldp);
+  const int groups = (int)ceil_div(b.max_blocks, 32);
+  b.gpart = ctx->arena.get_t<double>(t + "_gpart", groups * ldp);
+  b.counters = ctx->arena.get_t<int>(t + "_counters", groups, true);
+  b.sur_partial = ctx->arena.get_t<double>(t + "_surp", 3 * update_blocks((int)d) + 8);
+  b.sur_counter = ctx->arena.get_t<int>(t + "_surc", 4, true);
+  b.flags = ctx->arena.get_t<int>(t + "_flags", 4);
+  return b;
+}
+
+struct Stepper {
+  IterBufs b;
+  int d;
+  const double* M;
+  int cur = 0, prev = 0;
+  int t = 0;  // iterate index
+  hipStream_t st;
+
+  void start(const double* beta0, double* traj) {
+    if (beta0)
+      launch_copy_f64(beta0, b.beta[0], d, st);
+    else
+      launch_fill_f64(b.beta[0], 0.0, d, st);
+    if (traj) launch_copy_f64(b.beta[0], traj, d, st);
+    launch_fill_i32(b.flags, 0, 4, st);
+    cur = prev = 0;
+    t = 0;
+  }
+  void reset_momentum() { prev = cur; }
+
+  // one M-IHS step on rows [0, n) of (X, Y)
+  void step(int64_t n, const void* X, int64_t ldx, const void* Y, int64_t incy, slse_dtype storage,
+            slse_dtype accum, double scale, const double* w, double mu, double eta, double* beta_out,
+            double* traj, double* sur, double tol) {
+    const ResidGradPlan pl = plan_resid_grad(n, d, storage, X, ldx, b.max_blocks);
+    ResidGradArgs a;
+    a.n = n;
+    a.d = d;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.incy = incy;
+    a.storage = storage;
+    a.accum = accum;
+    a.beta = b.beta[cur];
+    a.partial = b.partial;
+    a.gpart = b.gpart;
+    a.counters = b.counters;
+    a.done = b.flags;
+    launch_resid_grad(pl, a, st);
+    const int next = (cur + 1) % 3 == prev ? (cur + 2) % 3 : (cur + 1) % 3;
+    UpdateArgs u;
+    u.gpart = b.gpart;
+    u.groups = pl.groups;
+    u.ldp = pl.ldp;
+    u.d = d;
+    u.scale = scale;
+    u.w = w;
+    u.M = M;
+    u.ldm = d;
+    u.beta = b.beta[cur];
+    u.beta_prev = b.beta[prev];
+    u.beta_next = b.beta[next];
+    u.mu = mu;
+    u.eta = eta;
+    u.beta_out = beta_out;
+    u.traj_row = traj ? traj + (int64_t)(t + 1) * d : nullptr;
+    u.sur_partial = b.sur_partial;
+    u.sur_counter = b.sur_counter;
+    u.sur_out = sur ? sur + t : nullptr;
+    u.tol2 = tol > 0 ? tol * tol : 0.0;
+    u.done = b.flags;
+    u.status = b.flags + 1;
+    launch_update(u, st);
+    prev = cur;
+    cur = next;
+    ++t;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Solve.
+// ---------------------------------------------------------------------------
+struct SolvePlan {
+  SketchShape sk;
+  slse_dtype st_t;    // storage of the data and of the sketch
+  slse_dtype acc1;    // stage-1 accumulation
+  void* A = nullptr;
+  int64_t lda = 0;
+  void* Ahat = nullptr;
+  int64_t ldah = 0;
+  SrhtArgs srht;
+  GaussianArgs ga, gh;
+  FactorBufs f;
+  IterBufs it;
+};
+
+void check_params(const slse_problem* p, const slse_params* q) {
+  require(p && q, "null problem or params");
+  require(p->X && p->Y, "null X or Y");
+  require(p->ldx >= p->d, "ldx < d");
+  require(p->dtype == SLSE_F32 || p->dtype == SLSE_F64, "data dtype must be F32 or F64");
+  if (q->precision == SLSE_PREC_F64)
+    require(p->dtype == SLSE_F64, "precision F64 needs F64 data");
+  else if (q->precision == SLSE_PREC_MIXED)
+    require(p->dtype == SLSE_F32, "precision MIXED needs F32 data");
+  else
+    fail(SLSE_EINVAL, "unknown precision");
+  require(q->s_max >= 0, "s_max < 0");
+  for (int i = 0; i < q->K; ++i) require(q->a[i] >= 0, "a_i < 0");
+  require(std::isfinite(q->mu) && std::isfinite(q->eta), "mu, eta must be finite");
+  require(q->factor == SLSE_FACTOR_CHOL || q->factor == SLSE_FACTOR_QR, "unknown factor method");
+}
+
+SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* q) {
+  SolvePlan pl;
+  pl.sk = make_sketch_shape(q->kind, p->N, p->d, q->m, q->K, q->r);
+  pl.st_t = p->dtype;
+  pl.acc1 = q->precision == SLSE_PREC_MIXED ? SLSE_F32 : SLSE_F64;
+  const size_t es = dtype_size(pl.st_t);
+  const int64_t align = 16 / (int64_t)es;
+  pl.lda = round_up(p->d + 1, align);
+  pl.ldah = pl.lda;
+  pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
+  pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
+  reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh);
+  pl.f = reserve_factor(ctx, pl.sk.r, p->d, q->factor);
+  pl.it = reserve_iter(ctx, p->d, "it");
+  return pl;
+}
+
+void enqueue_solve(const SolvePlan& pl, const slse_problem* p, const slse_params* q,
+                   double* beta_out, hipStream_t st) {
+  const int d = (int)p->d;
+  const SketchShape& sk = pl.sk;
+  enqueue_sketch(sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah, pl.srht,
+                 pl.ga, pl.gh, st);
+  enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
+  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st};
+  S.start(q->beta0, q->trajectory);
+  launch_copy_f64(S.b.beta[0], beta_out, d, st);
+  const size_t es = dtype_size(pl.st_t);
+  // stage 1: a_i steps on the prefix of m_i sketched rows (eq. (98))
+  for (int i = 0; i < sk.K; ++i) {
+    if (q->momentum_reset) S.reset_momentum();
+    const char* base = static_cast<const char*>(pl.A) + (size_t)sk.offset[i] * pl.lda * es;
+    for (int j = 0; j < q->a[i]; ++j) {
+      S.step(sk.m[i], base, pl.lda, base + (size_t)d * es, pl.lda, pl.st_t, pl.acc1, sk.scale[i],
+             nullptr, q->mu, q->eta, beta_out, q->trajectory, q->surrogate, 0.0);
+    }
+  }
+  // stage 2: full-data steps (eq. (99))
+  if (q->momentum_reset) S.reset_momentum();
+  for (int j = 0; j < q->s_max; ++j) {
+    slse_dtype acc = SLSE_F64;
+    if (q->precision == SLSE_PREC_MIXED && j < q->fp32_sweeps) acc = SLSE_F32;
+    S.step(p->N, p->X, p->ldx, p->Y, 1, pl.st_t, acc, 1.0, nullptr, q->mu, q->eta, beta_out,
+           q->trajectory, q->surrogate, q->tol);
+  }
+}
+
+std::string graph_key(const slse_problem* p, const slse_params* q, const double* beta_out,
+                      hipStream_t st) {
+  std::string k;
+  auto add = [&k](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
+  add(p, sizeof(*p));
+  add(q, sizeof(*q));
+  add(&beta_out, sizeof(beta_out));
+  (void)st;
+  return k;
+}
+
+slse_status finish_report(slse_ctx* ctx, const SolvePlan& pl, const slse_params* q,
+                          slse_report* rep, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  (void)ctx;
+  int flags[4] = {0, 0, 0, 0};
+  int info[2] = {0, 0};
+  SLSE_HIP(hipMemcpyAsync(flags, pl.it.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+  SLSE_HIP(hipMemcpyAsync(info, pl.f.info, sizeof(info), hipMemcpyDeviceToHost, st));
+  SLSE_HIP(hipStreamSynchronize(st));
+  slse_status status = SLSE_OK;
+  if (info[0] != 0 || info[1] != 0)
+    status = SLSE_ESINGULAR;
+  else if (flags[1])
+    status = SLSE_ENONFINITE;
+  else if (q->tol > 0 && !flags[0])
+    status = SLSE_ENOTCONV;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->status = status;
+    int s1 = 0;
+    for (int i = 0; i < q->K; ++i) s1 += q->a[i];
+    rep->stage1_steps = s1;
+    rep->stage2_steps = q->s_max;
+    if (q->surrogate) {
+      const int T = s1 + q->s_max;
+      std::vector<double> sur(T > 0 ? T : 1, 0.0);
+      if (T > 0) {
+        SLSE_HIP(hipMemcpy(sur.data(), q->surrogate, sizeof(double) * T, hipMemcpyDeviceToHost));
+        int taken = 0;
+        for (int t = s1; t < T; ++t) {
+          ++taken;
+          if (q->tol > 0 && sur[t] <= q->tol) break;
+        }
+        rep->stage2_steps = q->tol > 0 ? taken : q->s_max;
+        rep->surrogate0 = s1 < T ? sur[s1] : sur[0];
+        const int last = std::min(T - 1, std::max(0, s1 + rep->stage2_steps - 1));
+        rep->surrogate_final = sur[last];
+      }
+    }
+    if (e0 && e1) {
+      float ms = 0.f;
+      SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      rep->ms_total = ms;
+    }
+  }
+  return status;
+}
+
+slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                       double* beta_out, slse_report* rep, hipStream_t st) {
+  check_params(p, q);
+  require(beta_out != nullptr, "null beta_out");
+  ctx->arena.grew = false;
+  SolvePlan pl = reserve_solve(ctx, p, q);
+  if (ctx->arena.grew) ctx->drop_graphs();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rep) {
+    SLSE_HIP(hipEventCreate(&e0));
+    SLSE_HIP(hipEventCreate(&e1));
+    SLSE_HIP(hipEventRecord(e0, st));
+  }
+  if (q->use_graph) {
+    const std::string key = graph_key(p, q, beta_out, st);
+    auto itg = ctx->graphs.find(key);
+    if (itg == ctx->graphs.end()) {
+      hipGraph_t g = nullptr;
+      SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_solve(pl, p, q, beta_out, ctx->capture_stream);
+      } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(ctx->capture_stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+      }
+      SLSE_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
+      hipGraphExec_t ge = nullptr;
+      SLSE_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      SLSE_HIP(hipGraphDestroy(g));
+      itg = ctx->graphs.emplace(key, ge).first;
+    }
+    SLSE_HIP(hipGraphLaunch(itg->second, st));
+  } else {
+    enqueue_solve(pl, p, q, beta_out, st);
+  }
+  ctx->pre.valid = true;
+  ctx->pre.seed = q->seed;
+  ctx->pre.kind = q->kind;
+  ctx->pre.N = p->N;
+  ctx->pre.d = p->d;
+  ctx->pre.r = q->r;
+  ctx->pre.X = p->X;
+  ctx->pre.precision = q->precision;
+  slse_status status = SLSE_OK;
+  if (rep) SLSE_HIP(hipEventRecord(e1, st));
+  if (rep || q->tol > 0) status = finish_report(ctx, pl, q, rep, st, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// Backward: lambda from (X^T X) lambda = w by the preconditioned iteration,
+// then the rank-2 pass.
+// ---------------------------------------------------------------------------
+slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                          const double* beta_hat, const double* w, void* dX, int64_t lddx, void* dY,
+                          slse_dtype grad_t, double* lambda_out, slse_report* rep, hipStream_t st) {
+  check_params(p, q);
+  require(beta_hat && w, "null beta_hat or w");
+  require(grad_t == SLSE_F32 || grad_t == SLSE_F64, "grad dtype must be F32 or F64");
+  if (dX) require(lddx >= p->d, "lddx < d");
+  const int d = (int)p->d;
+  ctx->arena.grew = false;
+  const bool reuse = ctx->pre.valid && ctx->pre.seed == q->seed && ctx->pre.kind == q->kind &&
+                     ctx->pre.N == p->N && ctx->pre.d == p->d && ctx->pre.r == q->r &&
+                     ctx->pre.X == p->X && ctx->pre.precision == q->precision;
+  SolvePlan pl;
+  pl.sk = make_sketch_shape(q->kind, p->N, p->d, q->m, q->K, q->r);
+  pl.st_t = p->dtype;
+  pl.f = reserve_factor(ctx, q->r, p->d, q->factor);
+  if (!reuse) {
+    // sketch only what H_hat needs (the smallest level keeps the sketch cheap)
+    const size_t es = dtype_size(pl.st_t);
+    pl.lda = pl.ldah = round_up(p->d + 1, 16 / (int64_t)es);
+    pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
+    pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
+    reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh);
+  }
+  IterBufs ib = reserve_iter(ctx, p->d, "adj");
+  double* lam0 = ctx->arena.get_t<double>("adj_lam0", d);
+  double* zero = ctx->arena.get_t<double>("adj_zero", (int64_t)d * 1);
+  if (ctx->arena.grew) ctx->drop_graphs();
+  if (!reuse) {
+    enqueue_sketch(pl.sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah,
+                   pl.srht, pl.ga, pl.gh, st);
+    enqueue_factor(pl.f, pl.sk.r, d, pl.Ahat, pl.ldah, pl.st_t, pl.sk.hat_scale, q->factor, st);
+    ctx->pre.valid = false;
+  }
+  // lambda_0 = M w: one update step with g = w from a zero gradient and beta = 0
+  Stepper S{ib, d, pl.f.M, 0, 0, 0, st};
+  S.start(nullptr, nullptr);
+  launch_fill_f64(zero, 0.0, d, st);
+  {
+    // gpart rows of zero: reuse the update kernel with groups = 0 and w added
+    UpdateArgs u;
+    u.gpart = ib.gpart;
+    u.groups = 0;
+    u.ldp = (int)round_up(d + 1, 8);
+    u.d = d;
+    u.scale = 1.0;
+    u.w = w;
+    u.M = pl.f.M;
+    u.ldm = d;
+    u.beta = zero;
+    u.beta_prev = zero;
+    u.beta_next = ib.beta[0];
+    u.mu = 1.0;
+    u.eta = 0.0;
+    u.beta_out = lam0;
+    launch_update(u, st);
+  }
+  // s_max full-data steps on (X^T X) lambda = w: g = w + X^T (0 - X lambda)
+  for (int j = 0; j < q->s_max; ++j) {
+    S.step(p->N, p->X, p->ldx, nullptr, 1, p->dtype, SLSE_F64, 1.0, w, q->mu, q->eta, lambda_out,
+           nullptr, nullptr, 0.0);
+  }
+  const double* lam = ib.beta[S.cur];
+  if (lambda_out && q->s_max == 0) launch_copy_f64(lam, lambda_out, d, st);
+  AdjointArgs a;
+  a.n = p->N;
+  a.d = d;
+  a.X = p->X;
+  a.ldx = p->ldx;
+  a.Y = p->Y;
+  a.t = p->dtype;
+  a.beta = beta_hat;
+  a.lambda = lam;
+  a.dX = dX;
+  a.lddx = lddx;
+  a.dY = dY;
+  a.gt = grad_t;
+  if (dX || dY) launch_adjoint(a, st);
+  slse_status status = SLSE_OK;
+  if (rep) {
+    int flags[4] = {0, 0, 0, 0};
+    int info[2] = {0, 0};
+    SLSE_HIP(hipMemcpyAsync(flags, ib.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipMemcpyAsync(info, pl.f.info, sizeof(info), hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipStreamSynchronize(st));
+    if (info[0] || info[1]) status = SLSE_ESINGULAR;
+    else if (flags[1]) status = SLSE_ENONFINITE;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->status = status;
+    rep->stage2_steps = q->s_max;
+  }
+  return status;
+}
+
+template <typename F>
+slse_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return SLSE_EDEVICE;
+  } catch (...) {
+    set_last_error("unknown error");
+    return SLSE_EDEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace slse
+
+using namespace slse;
+
+extern "C" {
+
+const char* slse_last_error(void) { return g_last_error.c_str(); }
+
+const char* slse_version(void) { return "libslse 0.1 (gfx950)"; }
+
+slse_status slse_ctx_create(slse_ctx** out, int device) {
+  return guarded([&]() -> slse_status {
+    require(out != nullptr, "null out");
+    int n = 0;
+    SLSE_HIP(hipGetDeviceCount(&n));
+    require(device >= 0 && device < n, "bad device index");
+    DeviceGuard g(device);
+    auto ctx = std::make_unique<slse_ctx>();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    SLSE_HIP(hipGetDeviceProperties(&prop, device));
+    ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    SLSE_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    *out = ctx.release();
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_ctx_destroy(slse_ctx* ctx) {
+  if (!ctx) return SLSE_OK;
+  return guarded([&]() -> slse_status {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->drop_graphs();
+    ctx->arena.release();
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_ctx_trim(slse_ctx* ctx) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    DeviceGuard g(ctx->device);
+    SLSE_HIP(hipDeviceSynchronize());
+    ctx->drop_graphs();
+    ctx->arena.release();
+    ctx->pre.valid = false;
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_sketch_apply(slse_ctx* ctx, slse_sketch_kind kind, uint64_t seed, int64_t N,
+                              int64_t d, const void* X, int64_t ldx, const void* Y,
+                              slse_dtype in_t, const int64_t* m, int32_t K, int64_t r, void* A,
+                              int64_t lda, void* Ahat, int64_t ldah, slse_dtype out_t,
+                              slse_sketch_layout* layout_out, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    require(X && Y && A && Ahat, "null pointer");
+    require(ldx >= d && lda >= d + 1 && ldah >= d + 1, "leading dimension too small");
+    require(in_t == SLSE_F32 || in_t == SLSE_F64, "in dtype must be F32 or F64");
+    if (out_t != in_t) fail(SLSE_EUNSUPPORTED, "out dtype must equal in dtype in this build");
+    DeviceGuard g(ctx->device);
+    SketchShape s = make_sketch_shape(kind, N, d, m, K, r);
+    SrhtArgs srht;
+    GaussianArgs ga, gh;
+    ctx->arena.grew = false;
+    reserve_sketch(ctx, s, in_t, &srht, &ga, &gh);
+    if (ctx->arena.grew) ctx->drop_graphs();
+    ctx->pre.valid = false;
+    enqueue_sketch(s, seed, X, ldx, Y, in_t, A, lda, Ahat, ldah, srht, ga, gh, as_stream(stream));
+    fill_layout(s, layout_out);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_factor(slse_ctx* ctx, int64_t rows, int64_t d, const void* A, int64_t lda,
+                        slse_dtype a_t, double scale, slse_factor_method method, double* R,
+                        int64_t ldr, double* M, int64_t ldm, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && A && R, "null pointer");
+    require(d >= 1 && rows >= d, "need rows >= d >= 1");
+    require(d <= 512, "d > 512 is not supported by the factorization of this build");
+    require(lda >= d && ldr >= d && (!M || ldm >= d), "leading dimension too small");
+    require(a_t == SLSE_F32 || a_t == SLSE_F64, "A dtype must be F32 or F64");
+    require(scale > 0 && std::isfinite(scale), "scale must be positive");
+    require(method == SLSE_FACTOR_CHOL || method == SLSE_FACTOR_QR, "unknown method");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = as_stream(stream);
+    ctx->arena.grew = false;
+    FactorBufs f = reserve_factor(ctx, rows, d, method);
+    if (ctx->arena.grew) ctx->drop_graphs();
+    ctx->pre.valid = false;
+    launch_fill_i32(f.info, 0, 2, st);
+    enqueue_factor(f, rows, (int)d, A, lda, a_t, scale, method, st);
+    SLSE_HIP(hipMemcpy2DAsync(R, ldr * sizeof(double), f.R, d * sizeof(double), d * sizeof(double),
+                              d, hipMemcpyDeviceToDevice, st));
+    if (M)
+      SLSE_HIP(hipMemcpy2DAsync(M, ldm * sizeof(double), f.M, d * sizeof(double),
+                                d * sizeof(double), d, hipMemcpyDeviceToDevice, st));
+    int info[2] = {0, 0};
+    SLSE_HIP(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipStreamSynchronize(st));
+    if (info[0] || info[1]) {
+      set_last_error("factorization: non-positive or non-finite pivot at column " +
+                     std::to_string((info[0] ? info[0] : info[1]) - 1));
+      return SLSE_ESINGULAR;
+    }
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const void* X, int64_t ldx,
+                                  const void* Y, slse_dtype storage, const double* beta,
+                                  double scale, slse_dtype accum, double* g_out,
+                                  double* rnorm2_out, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && beta && g_out, "null pointer");
+    require(n >= 0 && d >= 1 && d <= 1024, "need n >= 0 and 1 <= d <= 1024");
+    require(n == 0 || X != nullptr, "null X");
+    require(ldx >= d, "ldx < d");
+    require(storage == SLSE_F32 || storage == SLSE_F64, "storage must be F32 or F64");
+    require(accum == SLSE_F32 || accum == SLSE_F64, "accum must be F32 or F64");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = as_stream(stream);
+    ctx->arena.grew = false;
+    IterBufs b = reserve_iter(ctx, d, "rg");
+    if (ctx->arena.grew) ctx->drop_graphs();
+    const ResidGradPlan pl = plan_resid_grad(n, (int)d, storage, X, ldx, b.max_blocks);
+    if (n == 0) {
+      launch_fill_f64(g_out, 0.0, d, st);
+      if (rnorm2_out) launch_fill_f64(rnorm2_out, 0.0, 1, st);
+      return SLSE_OK;
+    }
+    ResidGradArgs a;
+    a.n = n;
+    a.d = (int)d;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.incy = 1;
+    a.storage = storage;
+    a.accum = accum;
+    a.beta = beta;
+    a.partial = b.partial;
+    a.gpart = b.gpart;
+    a.counters = b.counters;
+    launch_resid_grad(pl, a, st);
+    launch_finalize_grad(b.gpart, pl.groups, pl.ldp, (int)d, scale, g_out, rnorm2_out, st);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                       double* beta_out, slse_report* rep, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    DeviceGuard g(ctx->device);
+    return solve_impl(ctx, p, q, beta_out, rep, as_stream(stream));
+  });
+}
+
+slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                          const double* beta_hat, const double* w, void* dX, int64_t lddx,
+                          void* dY, slse_dtype grad_t, double* lambda_out, slse_report* rep,
+                          void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    DeviceGuard g(ctx->device);
+    return backward_impl(ctx, p, q, beta_hat, w, dX, lddx, dY, grad_t, lambda_out, rep,
+                         as_stream(stream));
+  });
+}
+
+slse_status slse_solve_batched(slse_ctx* ctx, int32_t B, const slse_problem* ps,
+                               const slse_params* qs, double* const* betas, slse_report* reps,
+                               void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    require(B >= 0 && (B == 0 || (ps && qs && betas)), "bad batch arguments");
+    fail(SLSE_EUNSUPPORTED, "batched solve not built yet");
+  });
+}
+
+slse_status slse_debug_stream(slse_ctx* ctx, int32_t what, uint64_t seed, int32_t stream_id,
+                              int64_t aux, int64_t start, int64_t count, int64_t* out,
+                              void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && out, "null pointer");
+    require(what >= 0 && what <= 7, "bad selector");
+    require(count >= 0 && start >= 0, "bad range");
+    if (what == 1 || what == 2) {
+      require(aux >= 1 && aux <= 62, "permutation bits out of range");
+      require(start + count <= (int64_t(1) << aux), "index outside the permutation domain");
+    }
+    if (what == 4 || what == 5) require(is_pow2(aux), "bucket count must be a power of 2");
+    if (what == 6 || what == 7) require(aux >= 1, "bucket count must be positive");
+    DeviceGuard g(ctx->device);
+    launch_debug_stream(what, seed, stream_id, aux, start, count, out, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int64_t k0,
+                                int64_t nk, int64_t j0, int64_t nj, double* out, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && out, "null pointer");
+    require(k0 >= 0 && j0 >= 0 && nk >= 0 && nj >= 0, "bad range");
+    DeviceGuard g(ctx->device);
+    launch_debug_gaussian(seed, (uint64_t)stream_id, k0, nk, j0, nj, out, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+"""PyTorch-facing wrappers of libslse (names follow include/slse.h).
+
+Tensors supply device memory and the current HIP stream; each call forwards
+pointers and sizes to the C ABI and nothing else: the sketch, the factor, the
+M-IHS iteration and the adjoint all run in the library's kernels.
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.SLSE_F32, torch.float64: L.SLSE_F64}
+_KIND = {"srht": L.SLSE_SRHT, "countsketch": L.SLSE_COUNTSKETCH, "gaussian": L.SLSE_GAUSSIAN}
+_FACTOR = {"chol": L.SLSE_FACTOR_CHOL, "qr": L.SLSE_FACTOR_QR}
+_PREC = {"f64": L.SLSE_PREC_F64, "mixed": L.SLSE_PREC_MIXED}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libslse works on device tensors")
+
+
+class Context:
+    """An slse_ctx bound to one device (scratch memory, graphs, cached factor)."""
+
+    def __init__(self, device=0):
+        self.lib = L.load()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        L.check(self.lib.slse_ctx_create(ctypes.byref(h), self.device.index or 0))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.slse_ctx_destroy(self.h)
+            self.h = None
+
+    def trim(self):
+        L.check(self.lib.slse_ctx_trim(self.h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device=None):
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def paper_params(d, r=None):
+    """eta = d/r and mu = (1 - eta)^2 (Sec. 5 parameter choice), r = 6d by default."""
+    r = 6 * d if r is None else r
+    eta = d / r
+    return r, (1.0 - eta) ** 2, eta
+
+
+def paper_schedule(n, d, m1_factor=8):
+    """m_1 = 8d (rounded up to a power of 2), doubling to the largest power of 2 <= N/2."""
+    m1 = 1 << max(0, (m1_factor * d - 1).bit_length())
+    mk = 1 << ((n // 2).bit_length() - 1)
+    m = []
+    v = m1
+    while v <= mk:
+        m.append(v)
+        v *= 2
+    return m
+
+
+@dataclass
+class Params:
+    kind: str = "srht"
+    seed: int = 0
+    m: List[int] = field(default_factory=list)
+    a: List[int] = field(default_factory=list)
+    r: int = 0
+    mu: Optional[float] = None
+    eta: Optional[float] = None
+    s_max: int = 20
+    tol: float = 0.0
+    precision: str = "f64"
+    fp32_sweeps: int = 0
+    momentum_reset: bool = False
+    factor: str = "chol"
+    use_graph: bool = False
+
+    def to_c(self, d, beta0=None, trajectory=None, surrogate=None):
+        q = L.slse_params()
+        q.kind = _KIND[self.kind]
+        q.seed = self.seed
+        q.K = len(self.m)
+        if q.K > L.SLSE_MAX_LEVELS or len(self.a) != q.K:
+            raise ValueError("m and a must have the same length <= SLSE_MAX_LEVELS")
+        for i, (mi, ai) in enumerate(zip(self.m, self.a)):
+            q.m[i] = int(mi)
+            q.a[i] = int(ai)
+        r, mu, eta = paper_params(d, self.r or None)
+        q.r = r
+        q.mu = mu if self.mu is None else self.mu
+        q.eta = eta if self.eta is None else self.eta
+        q.s_max = self.s_max
+        q.tol = self.tol
+        q.precision = _PREC[self.precision]
+        q.fp32_sweeps = self.fp32_sweeps
+        q.momentum_reset = 1 if self.momentum_reset else 0
+        q.factor = _FACTOR[self.factor]
+        q.beta0 = _ptr(beta0).value
+        q.trajectory = _ptr(trajectory).value
+        q.surrogate = _ptr(surrogate).value
+        q.use_graph = 1 if self.use_graph else 0
+        return q
+
+
+def _problem(X, Y):
+    _need_cuda(X, Y)
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D row-major")
+    if Y.dim() != 1 or Y.stride(0) != 1 or Y.shape[0] != X.shape[0]:
+        raise ValueError("Y must be contiguous with N entries")
+    if X.dtype != Y.dtype or X.dtype not in _DT:
+        raise ValueError("X and Y must share dtype float32 or float64")
+    p = L.slse_problem()
+    p.N, p.d = X.shape
+    p.X = X.data_ptr()
+    p.ldx = X.stride(0)
+    p.Y = Y.data_ptr()
+    p.dtype = _DT[X.dtype]
+    return p
+
+
+def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True):
+    """slse_solve: returns (beta, report dict[, trajectory, surrogate])."""
+    ctx = ctx or default_context(X.device.index)
+    p = _problem(X, Y)
+    d = X.shape[1]
+    T = sum(params.a) + params.s_max
+    traj = torch.empty((T + 1, d), dtype=torch.float64, device=X.device) if record else None
+    sur = torch.empty(max(T, 1), dtype=torch.float64, device=X.device) if record else None
+    q = params.to_c(d, beta0, traj, sur)
+    beta = torch.empty(d, dtype=torch.float64, device=X.device)
+    rep = L.slse_report()
+    st = ctx.lib.slse_solve(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta),
+                            ctypes.byref(rep) if report else None, _stream(X.device))
+    if st not in (L.SLSE_OK, L.SLSE_ENOTCONV):
+        L.check(st)
+    info = dict(status=L.STATUS_NAMES.get(st, st), stage1_steps=rep.stage1_steps,
+                stage2_steps=rep.stage2_steps, surrogate0=rep.surrogate0,
+                surrogate_final=rep.surrogate_final, ms_total=rep.ms_total)
+    if record:
+        return beta, info, traj, sur
+    return beta, info
+
+
+def sketch_apply(X, Y, kind, seed, m, r, ctx=None):
+    """slse_sketch_apply: returns (A, Ahat, layout dict)."""
+    ctx = ctx or default_context(X.device.index)
+    p = _problem(X, Y)
+    N, d = X.shape
+    mK = list(m)
+    rows_A = sum(mK) if kind == "countsketch" else mK[-1]
+    align = 16 // X.element_size()
+    ld = ((d + 1 + align - 1) // align) * align
+    A = torch.empty((rows_A, ld), dtype=X.dtype, device=X.device)
+    Ah = torch.empty((r, ld), dtype=X.dtype, device=X.device)
+    marr = (ctypes.c_int64 * len(mK))(*mK)
+    lay = L.slse_sketch_layout()
+    L.check(ctx.lib.slse_sketch_apply(ctx.h, _KIND[kind], seed, N, d, _ptr(X), p.ldx, _ptr(Y),
+                                      p.dtype, marr, len(mK), r, _ptr(A), ld, _ptr(Ah), ld,
+                                      p.dtype, ctypes.byref(lay), _stream(X.device)))
+    layout = dict(K=lay.K, m=list(lay.m[:lay.K]), offset=list(lay.offset[:lay.K]),
+                  scale=list(lay.scale[:lay.K]), rows_A=lay.rows_A, r=lay.r,
+                  hat_scale=lay.hat_scale, n_pad=lay.n_pad)
+    return A[:, : d + 1], Ah[:, : d + 1], layout
+
+
+def factor(A, d, scale, method="chol", ctx=None):
+    """slse_factor on the first d columns of A: returns (R, M)."""
+    ctx = ctx or default_context(A.device.index)
+    _need_cuda(A)
+    if A.stride(1) != 1 or A.dtype not in _DT:
+        raise ValueError("A must be row-major float32/float64")
+    R = torch.empty((d, d), dtype=torch.float64, device=A.device)
+    M = torch.empty((d, d), dtype=torch.float64, device=A.device)
+    L.check(ctx.lib.slse_factor(ctx.h, A.shape[0], d, _ptr(A), A.stride(0), _DT[A.dtype], scale,
+                                _FACTOR[method], _ptr(R), d, _ptr(M), d, _stream(A.device)))
+    return R, M
+
+
+def fused_resid_grad(X, Y, beta, scale=1.0, accum="f64", ctx=None, n=None):
+    """slse_fused_resid_grad: g = scale X^T (Y - X beta) and scale ||Y - X beta||^2."""
+    ctx = ctx or default_context(X.device.index)
+    _need_cuda(X, beta)
+    if X.stride(1) != 1 or X.dtype not in _DT:
+        raise ValueError("X must be row-major float32/float64")
+    if Y is not None and (Y.stride(0) != 1 or Y.dtype != X.dtype):
+        raise ValueError("Y must be contiguous with X's dtype")
+    n = X.shape[0] if n is None else n
+    d = X.shape[1]
+    g = torch.empty(d, dtype=torch.float64, device=X.device)
+    rn = torch.empty(1, dtype=torch.float64, device=X.device)
+    L.check(ctx.lib.slse_fused_resid_grad(ctx.h, n, d, _ptr(X), X.stride(0), _ptr(Y), _DT[X.dtype],
+                                          _ptr(beta), scale, _DT[torch.float64 if accum == "f64" else torch.float32],
+                                          _ptr(g), _ptr(rn), _stream(X.device)))
+    return g, rn
+
+
+def backward(X, Y, params: Params, beta_hat, w, grad_dtype=None, ctx=None, want_dX=True, want_dY=True):
+    """slse_backward: returns (dX, dY, lambda)."""
+    ctx = ctx or default_context(X.device.index)
+    p = _problem(X, Y)
+    N, d = X.shape
+    gd = X.dtype if grad_dtype is None else grad_dtype
+    dX = torch.empty((N, d), dtype=gd, device=X.device) if want_dX else None
+    dY = torch.empty(N, dtype=gd, device=X.device) if want_dY else None
+    lam = torch.empty(d, dtype=torch.float64, device=X.device)
+    q = params.to_c(d)
+    rep = L.slse_report()
+    L.check(ctx.lib.slse_backward(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta_hat), _ptr(w),
+                                  _ptr(dX), d, _ptr(dY), _DT[gd], _ptr(lam), ctypes.byref(rep),
+                                  _stream(X.device)))
+    return dX, dY, lam
+
+
+def debug_stream(what, seed, stream_id, aux, start, count, device=0, ctx=None):
+    ctx = ctx or default_context(device)
+    n = 4 * count if what == 0 else count
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=torch.device("cuda", device))
+    L.check(ctx.lib.slse_debug_stream(ctx.h, what, seed, stream_id, aux, start, count, _ptr(out),
+                                      _stream(device)))
+    return out[:n]
+
+
+def debug_gaussian(seed, stream_id, k0, nk, j0, nj, device=0, ctx=None):
+    ctx = ctx or default_context(device)
+    out = torch.empty((max(nk, 1), max(nj, 1)), dtype=torch.float64, device=torch.device("cuda", device))
+    L.check(ctx.lib.slse_debug_gaussian(ctx.h, seed, stream_id, k0, nk, j0, nj, _ptr(out),
+                                        _stream(device)))
+    return out[:nk, :nj]
+
+
+class SLSEFunction(torch.autograd.Function):
+    """beta_hat = SLSE-FRS(X, Y) with the hand-written adjoint of slse_backward."""
+
+    @staticmethod
+    def forward(ctx, X, Y, params):
+        beta, _ = solve(X, Y, params)
+        ctx.save_for_backward(X, Y, beta)
+        ctx.params = params
+        return beta
+
+    @staticmethod
+    def backward(ctx, w):
+        X, Y, beta = ctx.saved_tensors
+        w = w.contiguous().to(torch.float64)
+        dX, dY, _ = backward(X, Y, ctx.params, beta, w, want_dX=ctx.needs_input_grad[0],
+                             want_dY=ctx.needs_input_grad[1])
+        return dX, dY, None
