@@ -1,0 +1,247 @@
+#!/usr/bin/env python
+"""SLSE-FRS on one MI355X: seconds to 1e-10 relative error against the FP64 OLS
+solution, the fused residual-gradient kernel's HBM bandwidth, and the
+mixed-precision form against the plain FP64 form.
+
+One step = one whole solve (sketch of [X|Y], factor of the Hessian sketch,
+stage-1 steps on the nested sketches, stage-2 full-data steps) on data already
+resident in HBM, replayed from a captured hipGraph.  The number of stage-2
+steps is the smallest that reaches the tolerance, found by a calibration solve
+that records every iterate and compares it with the stored oracle solution;
+the timed solves use that count and their result is checked again.
+
+    python bench.py [--steps K] [--warmup W] [--workload mixed|illcond]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "seconds to 1e-10 rel. error vs FP64 OLS; resid-grad HBM GB/s; mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_reference(name):
+    path = os.path.join(ROOT, "tests", "golden", f"ref_{name}.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def rel_err(b, ref):
+    return float(np.linalg.norm(b - ref) / np.linalg.norm(ref))
+
+
+def calibrate(G, torch, X, Y, params, beta_star, tol, s_cap):
+    """Smallest stage-2 step count whose iterate meets tol (from one recorded solve)."""
+    params.s_max = s_cap
+    params.use_graph = False
+    beta, info, traj, sur = G.solve(X, Y, params, record=True)
+    tr = traj.cpu().numpy()
+    s1 = sum(params.a)
+    errs = [rel_err(tr[s1 + s], beta_star) for s in range(s_cap + 1)]
+    for s, e in enumerate(errs):
+        if e <= tol:
+            return s, errs
+    return None, errs
+
+
+def time_solves(G, torch, X, Y, params, steps, warmup):
+    params.use_graph = True
+    beta = None
+    for _ in range(warmup):
+        beta, _ = G.solve(X, Y, params, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        beta, _ = G.solve(X, Y, params, report=False)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, beta
+
+
+def time_resid_grad(G, torch, X, Y, beta, reps=20):
+    """Average device time of one fused residual-gradient launch (HIP events)."""
+    for _ in range(3):
+        G.fused_resid_grad(X, Y, beta)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        G.fused_resid_grad(X, Y, beta)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def cpu_baseline(name, d, params_gpu, s_star, tol, n_sample):
+    """The oracle's SLSE-FRS, timed on a same-recipe sample of n_sample rows."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import ols as O
+    from oracle import slse as OS
+    from slse_inputs import make_problem
+
+    p = make_problem(name, n=n_sample)
+    bstar, _, _ = O.ols_refined(p.X, p.Y)
+    m = OS.paper_schedule(n_sample, d)
+    t0 = time.perf_counter()
+    beta, _, _ = OS.slse_frs(p.X, p.Y, params_gpu.seed, "srht", m, [2] * len(m), 6 * d, s=s_star)
+    t = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return t, rel_err(beta, bstar), threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond"])
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--s-cap", type=int, default=60)
+    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=1 << 17)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only loop the fused residual-gradient kernel (for counter runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_06856_amd import slse as G
+    from slse_inputs import fingerprint, make_problem, sketch_seed
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+    name = args.workload
+    ref = load_reference(name)
+    beta_star = np.asarray(ref["beta_star"])
+
+    t0 = time.perf_counter()
+    prob = make_problem(name)
+    log(f"generated {name} N={prob.n} d={prob.d} {prob.X.dtype} in {time.perf_counter() - t0:.1f}s")
+    fp = fingerprint(prob.X, prob.Y)
+    if fp != ref["fingerprint"]:
+        print(f"regenerated data differ from the stored reference ({fp} != {ref['fingerprint']})",
+              file=sys.stderr)
+        sys.exit(3)
+    N, d = prob.n, prob.d
+    X = torch.from_numpy(prob.X).to(dev)
+    Y = torch.from_numpy(prob.Y).to(dev)
+    del prob
+    mixed = X.dtype == torch.float32
+    m = G.paper_schedule(N, d)
+    params = G.Params(kind="srht", seed=sketch_seed(name), m=m, a=[2] * len(m), r=6 * d,
+                      precision="mixed" if mixed else "f64")
+    bytes_per_sweep = N * (d + 1) * X.element_size()
+
+    if args.kernel_only:
+        beta0 = torch.from_numpy(beta_star).to(dev)
+        t_k = time_resid_grad(G, torch, X, Y, beta0, reps=50)
+        log(f"resid_grad {t_k * 1e3:.3f} ms, {bytes_per_sweep / t_k / 1e9:.0f} GB/s")
+        return
+
+    s_star, errs = calibrate(G, torch, X, Y, params, beta_star, args.tol, args.s_cap)
+    log(f"calibration: stage-2 steps to {args.tol:g}: {s_star}; errors "
+        + " ".join(f"{e:.1e}" for e in errs[:: max(1, len(errs) // 12)]))
+    if s_star is None:
+        print(f"tolerance {args.tol} not reached in {args.s_cap} stage-2 steps", file=sys.stderr)
+        sys.exit(4)
+    params.s_max = s_star
+    t_solve, beta = time_solves(G, torch, X, Y, params, args.steps, args.warmup)
+    err = rel_err(beta.cpu().numpy(), beta_star)
+    log(f"{params.precision} solve: {t_solve * 1e3:.2f} ms, rel err {err:.2e}")
+    if err > args.tol:
+        print(f"timed solve missed the tolerance: {err:.3e}", file=sys.stderr)
+        sys.exit(5)
+
+    beta_dev = torch.from_numpy(beta_star).to(dev)
+    t_k = time_resid_grad(G, torch, X, Y, beta_dev)
+    gbs = bytes_per_sweep / t_k / 1e9
+    log(f"resid_grad: {t_k * 1e3:.3f} ms per sweep, {gbs:.0f} GB/s")
+
+    f64 = None
+    if mixed and not args.no_f64:
+        X64 = X.double()
+        Y64 = Y.double()
+        p64 = G.Params(kind="srht", seed=params.seed, m=m, a=[2] * len(m), r=6 * d, precision="f64")
+        s64, _ = calibrate(G, torch, X64, Y64, p64, beta_star, args.tol, args.s_cap)
+        if s64 is not None:
+            p64.s_max = s64
+            t64, b64 = time_solves(G, torch, X64, Y64, p64, max(3, args.steps // 2), 1)
+            e64 = rel_err(b64.cpu().numpy(), beta_star)
+            t_k64 = time_resid_grad(G, torch, X64, Y64, beta_dev)
+            f64 = dict(seconds=t64, stage2_steps=s64, rel_err=e64,
+                       resid_grad_GBs=2 * bytes_per_sweep / t_k64 / 1e9)
+            log(f"f64 solve: {t64 * 1e3:.2f} ms ({s64} stage-2 steps), rel err {e64:.2e}")
+        del X64, Y64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        n_s = min(args.cpu_rows, N)
+        t_cpu, e_cpu, threads = cpu_baseline(name, d, params, s_star, args.tol, n_s)
+        cpu = {"value": t_cpu * N / n_s, "unit": "s", "cores": threads, "kind": "oracle",
+               "sample": f"oracle SLSE-FRS (NumPy FP64, same recipe, paper schedule, {s_star} "
+                         f"stage-2 steps) on N={n_s} rows, {t_cpu:.2f}s, rel err {e_cpu:.1e}; "
+                         f"scaled by N/{n_s} to the full workload"}
+        log(f"cpu oracle sample: {t_cpu:.2f}s on {n_s} rows ({threads} threads), err {e_cpu:.1e}")
+
+    out = {
+        "metric": METRIC,
+        "value": t_solve,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_solve * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 accumulation" if mixed else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{name}: N={N}, d={d}, "
+                         + ("X=G diag(s), s log-spaced 1..1e-6, X,Y float32"
+                            if mixed else "X=G diag(s) V^T, s 1..1e-4, 5% rows x100, float64")),
+            "sketch": "srht", "r": 6 * d, "m": f"{m[0]}..{m[-1]} x2 (K={len(m)})", "a_i": 2,
+            "stage2_steps": s_star, "rel_err": err, "tol": args.tol,
+            "resid_grad_GBs": gbs,
+            "f64_form": f64,
+            "mixed_vs_f64_speedup": (f64["seconds"] / t_solve) if f64 else None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "resid_grad_kernel (fused X^T(Y - X beta), one read of [X|Y])",
+            "algorithmic_bytes": bytes_per_sweep,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -6,11 +6,13 @@
 // wave's loads of one row are contiguous.  Per row the group forms the partial
 // dot x_j . beta, all-reduces it across its lanes (xor shuffles), and every
 // lane folds r_j = y_j - x_j . beta into its own slice of g.  A wave streams
-// 64/lpr rows per step, UNROLL steps in flight.  At the end the wave's row
+// 64/lpr rows per step, UNROLL steps in flight, over one contiguous chunk of
+// rows per block.  At the end the wave's row
 // groups, then the block's waves, are summed; the block writes one partial
 // row; the last block of every group of `group_size` blocks adds its group's
 // rows in block order (deterministic for a fixed launch shape).
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -54,13 +56,20 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
   }
 }
 
+template <typename T, int VEC, int NCH>
+constexpr int unroll_for() {
+  constexpr int bytes = NCH * VEC * (int)sizeof(T);
+  constexpr int u = 256 / bytes;
+  return u < 1 ? 1 : (u > 16 ? 16 : u);
+}
+
 template <typename T, typename Acc, int VEC, int NCH, bool HAS_Y>
 __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
     int64_t n, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t incy,
     const double* __restrict__ beta, int lpr, double* __restrict__ partial,
     double* __restrict__ gpart, int* __restrict__ counters, int group_size, int ldp,
     const int* __restrict__ done) {
-  constexpr int UNROLL = NCH >= 8 ? 1 : (8 / NCH);
+  constexpr int UNROLL = unroll_for<T, VEC, NCH>();
   if (done && *done) return;
   __shared__ double s_red[kWaves][1025];
   __shared__ int s_ticket;
@@ -89,16 +98,20 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
     for (int v = 0; v < VEC; ++v) acc[c][v] = 0;
   Acc rr = 0;
 
-  const int64_t stride = (int64_t)gridDim.x * kWaves * gpw;
-  const int64_t gg = ((int64_t)blockIdx.x * kWaves + wave) * gpw + grp;
+  // each block streams one contiguous chunk of rows; at every unroll step its
+  // lane groups cover `rs` consecutive rows
+  const int rs = kWaves * gpw;
+  const int64_t chunk = round_up(ceil_div(n, (int64_t)gridDim.x), rs);
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
 
-  for (int64_t base = gg; base < n; base += stride * UNROLL) {
+  for (int64_t base = r0 + wave * gpw + grp; base < r1; base += (int64_t)rs * UNROLL) {
     T x[UNROLL][NCH][VEC];
     T y[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
-      const int64_t row = base + (int64_t)u * stride;
-      const bool ok = row < n;
+      const int64_t row = base + (int64_t)u * rs;
+      const bool ok = row < r1;
       const T* xr = X + (ok ? row : 0) * ldx;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
@@ -242,16 +255,18 @@ void launch_vec(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) 
 }  // namespace
 
 ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
-                              int max_blocks) {
+                              int grid_blocks, int capacity) {
   ResidGradPlan pl;
   const int es = (int)dtype_size(storage);
   const int vfull = 16 / es;
   const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * es) % 16 == 0);
   pl.vec = aligned ? vfull : 1;
   const int nvec = (int)ceil_div(d, pl.vec);
-  // widest power-of-2 lane group that still leaves >= 2 vector chunks per lane
+  // a row is spread over up to a full wave (so each lane holds only a few
+  // vectors of it) and many rows are kept in flight per lane instead
   int lpr = 1;
-  while (lpr < 64 && lpr * 4 <= nvec) lpr *= 2;
+  while (lpr < 64 && lpr * 2 <= nvec) lpr *= 2;
+  if (const char* e = std::getenv("SLSE_RG_LPR")) lpr = std::max(1, std::min(64, std::atoi(e)));
   int nch = (int)ceil_div(nvec, lpr);
   int p2 = 1;
   while (p2 < nch) p2 *= 2;
@@ -260,15 +275,23 @@ ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* 
   pl.nch = p2;
   pl.ldp = (int)round_up(d + 1, 8);
   const int rows_per_block_step = kWaves * (64 / lpr);
-  const int unroll = p2 >= 8 ? 1 : 8 / p2;
+  const int bytes_per_vec = pl.vec * es;
+  const int unroll = std::max(1, std::min(16, 256 / (p2 * bytes_per_vec)));
+  // an override may choose another grid, never one above the capacity the
+  // partial rows and group counters were allocated for
+  int target = std::min(grid_blocks, capacity);
+  if (const char* e = std::getenv("SLSE_RG_BLOCKS"))
+    target = std::max(1, std::min(capacity, std::atoi(e)));
   int64_t want = ceil_div(std::max<int64_t>(n, 1), (int64_t)rows_per_block_step * unroll);
-  pl.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, max_blocks));
+  pl.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, target));
   pl.group_size = 32;
   pl.groups = (int)ceil_div(pl.blocks, pl.group_size);
   return pl;
 }
 
 void launch_resid_grad(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
+  if (pl.blocks > a.capacity_blocks || pl.groups > ceil_div(a.capacity_blocks, pl.group_size))
+    fail(SLSE_EINVAL, "resid_grad: plan exceeds the scratch capacity");
   if (a.storage == SLSE_F64) {
     if (a.accum == SLSE_F64)
       launch_vec<double, double>(pl, a, s);

@@ -24,7 +24,7 @@ struct ResidGradPlan {
 };
 
 ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
-                              int max_blocks);
+                              int grid_blocks, int capacity);
 
 struct ResidGradArgs {
   int64_t n = 0;
@@ -39,6 +39,7 @@ struct ResidGradArgs {
   double* partial = nullptr;  // [blocks][ldp]
   double* gpart = nullptr;    // [groups][ldp]
   int* counters = nullptr;    // [groups], zero before the first launch; left zero
+  int capacity_blocks = 0;    // rows allocated in `partial` (groups: ceil(capacity / 32))
   const int* done = nullptr;  // optional early-exit flag
 };
 

@@ -325,14 +325,16 @@ struct IterBufs {
   double* sur_partial = nullptr;
   int* sur_counter = nullptr;
   int* flags = nullptr;  // [0] done, [1] non-finite
-  int max_blocks = 1024;
+  int max_blocks = 1024;   // capacity of the partial rows
+  int grid_blocks = 512;   // grid of the residual-gradient launches (<= max_blocks)
 };
 
 IterBufs reserve_iter(slse_ctx* ctx, int64_t d, const char* tag) {
   IterBufs b;
   std::string t(tag);
   for (int i = 0; i < 3; ++i) b.beta[i] = ctx->arena.get_t<double>(t + "_beta" + char('0' + i), d);
-  b.max_blocks = std::max(256, 4 * ctx->num_cus);
+  b.max_blocks = std::max(256, 8 * ctx->num_cus);
+  b.grid_blocks = std::max(64, 2 * ctx->num_cus);
   const int64_t ldp = round_up(d + 1, 8);
   b.partial = ctx->arena.get_t<double>(t + "_partial", b.max_blocks * ldp);
   const int groups = (int)ceil_div(b.max_blocks, 32);
@@ -368,7 +370,7 @@ struct Stepper {
   void step(int64_t n, const void* X, int64_t ldx, const void* Y, int64_t incy, slse_dtype storage,
             slse_dtype accum, double scale, const double* w, double mu, double eta, double* beta_out,
             double* traj, double* sur, double tol) {
-    const ResidGradPlan pl = plan_resid_grad(n, d, storage, X, ldx, b.max_blocks);
+    const ResidGradPlan pl = plan_resid_grad(n, d, storage, X, ldx, b.grid_blocks, b.max_blocks);
     ResidGradArgs a;
     a.n = n;
     a.d = d;
@@ -382,6 +384,7 @@ struct Stepper {
     a.partial = b.partial;
     a.gpart = b.gpart;
     a.counters = b.counters;
+    a.capacity_blocks = b.max_blocks;
     a.done = b.flags;
     launch_resid_grad(pl, a, st);
     const int next = (cur + 1) % 3 == prev ? (cur + 2) % 3 : (cur + 1) % 3;
@@ -559,6 +562,14 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
   require(beta_out != nullptr, "null beta_out");
   ctx->arena.grew = false;
   SolvePlan pl = reserve_solve(ctx, p, q);
+  // the per-step error estimates always land somewhere: the caller's buffer or ours
+  slse_params qq = *q;
+  if (!qq.surrogate) {
+    int T = q->s_max;
+    for (int i = 0; i < q->K; ++i) T += q->a[i];
+    qq.surrogate = ctx->arena.get_t<double>("sur_hist", (size_t)T + 1);
+  }
+  q = &qq;
   if (ctx->arena.grew) ctx->drop_graphs();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (rep) {
@@ -851,7 +862,7 @@ slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const voi
     ctx->arena.grew = false;
     IterBufs b = reserve_iter(ctx, d, "rg");
     if (ctx->arena.grew) ctx->drop_graphs();
-    const ResidGradPlan pl = plan_resid_grad(n, (int)d, storage, X, ldx, b.max_blocks);
+    const ResidGradPlan pl = plan_resid_grad(n, (int)d, storage, X, ldx, b.grid_blocks, b.max_blocks);
     if (n == 0) {
       launch_fill_f64(g_out, 0.0, d, st);
       if (rnorm2_out) launch_fill_f64(rnorm2_out, 0.0, 1, st);
@@ -870,6 +881,7 @@ slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const voi
     a.partial = b.partial;
     a.gpart = b.gpart;
     a.counters = b.counters;
+    a.capacity_blocks = b.max_blocks;
     launch_resid_grad(pl, a, st);
     launch_finalize_grad(b.gpart, pl.groups, pl.ldp, (int)d, scale, g_out, rnorm2_out, st);
     return SLSE_OK;

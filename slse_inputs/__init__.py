@@ -5,6 +5,7 @@ arithmetic (no sketch, no solver, no reference result).
 from .generators import (  # noqa: F401
     WORKLOADS,
     Problem,
+    fingerprint,
     make_problem,
     make_batched,
     paper_problem,

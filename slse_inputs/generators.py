@@ -19,11 +19,18 @@ regressions this library is measured on:
 
 Random numbers come from numpy.random.Generator(Philox(key=(seed, block))),
 one generator per block of 2^16 rows, so blocks can be drawn in parallel and
-the result does not depend on the thread count.  A smaller `n` (and `d`) may
-be requested for any workload to get a same-recipe problem of another size.
+the result does not depend on the thread count.  Everything after the draws
+is elementwise IEEE arithmetic in a fixed order (no BLAS, no vectorised libm),
+so a workload regenerates bit for bit on any x86-64 host with this NumPy and
+glibc; `fingerprint()` hashes the arrays to check that.  The orthogonal V of
+the ill-conditioned workload is a random butterfly network of Givens
+rotations (three sweeps over the pairs (i, i xor 2^l)), applied row by row.
+A smaller `n` (and `d`) may be requested for any workload to get a
+same-recipe problem of another size.
 """
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
+import math
 import os
 
 import numpy as np
@@ -82,13 +89,54 @@ def _fill_blocks(n, fn):
 
 
 def _logspace_scale(d, smin):
-    return np.logspace(0.0, np.log10(smin), d) if d > 1 else np.ones(1)
+    """s_k = smin^(k/(d-1)), k = 0..d-1 (scalar libm calls, so bit-reproducible)."""
+    if d == 1:
+        return np.ones(1)
+    e = math.log10(smin)
+    return np.array([math.pow(10.0, e * k / (d - 1)) for k in range(d)])
 
 
-def _haar(d, rng):
-    """Haar-distributed orthogonal d x d matrix (QR of a Gaussian, sign-fixed)."""
-    Q, R = np.linalg.qr(rng.standard_normal((d, d)))
-    return Q * np.sign(np.diag(R))[None, :]
+def _rotation_network(d, rng, sweeps=3):
+    """Layers of Givens rotations (i, i ^ 2^l) with random angles: a random orthogonal V."""
+    layers = []
+    for _ in range(sweeps):
+        l = 1
+        while l < d:
+            i = np.array([k for k in range(d) if (k & l) == 0 and (k | l) < d], dtype=np.int64)
+            theta = rng.uniform(0.0, 2.0 * math.pi, size=len(i))
+            c = np.array([math.cos(t) for t in theta])
+            s = np.array([math.sin(t) for t in theta])
+            layers.append((i, i | l, c, s))
+            l <<= 1
+    return layers
+
+
+def _apply_rotations(Xb, layers):
+    """Xb <- Xb V^T, one rotation layer at a time (elementwise, fixed order)."""
+    for i, j, c, s in layers:
+        xi = Xb[:, i]
+        xj = Xb[:, j]
+        Xb[:, i] = xi * c - xj * s
+        Xb[:, j] = xi * s + xj * c
+    return Xb
+
+
+def _matvec(Xb, beta):
+    """Xb @ beta as a fixed-order sum over columns (no BLAS)."""
+    y = np.zeros(Xb.shape[0])
+    for k in range(Xb.shape[1]):
+        y += Xb[:, k] * beta[k]
+    return y
+
+
+def fingerprint(*arrays):
+    """xxh64 of the arrays' bytes, to check that a workload regenerated bit for bit."""
+    import xxhash
+
+    h = xxhash.xxh64()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
 
 
 def make_problem(name, n=None, d=None, seed=None):
@@ -112,7 +160,7 @@ def make_problem(name, n=None, d=None, seed=None):
     elif name == "illcond":
         sigma = 1e-3
         scale = _logspace_scale(d, 1e-4)
-        V = _haar(d, head)
+        V = _rotation_network(d, head)
         k_lev = int(round(0.05 * n))
         lev = np.zeros(n, dtype=bool)
         lev[head.permutation(n)[:k_lev]] = True
@@ -133,15 +181,14 @@ def make_problem(name, n=None, d=None, seed=None):
         i0 = b * ROW_BLOCK
         i1 = min(n, i0 + ROW_BLOCK)
         G = g.standard_normal((i1 - i0, d))
-        Xb = G * scale[None, :]
+        Xb = np.asfortranarray(G * scale[None, :])  # columns contiguous for the loops below
         if V is not None:
-            Xb = Xb @ V.T
+            Xb = _apply_rotations(Xb, V)
         if lev is not None:
             Xb[lev[i0:i1]] *= 100.0
         zeta = sigma * g.standard_normal(i1 - i0)
-        Xr = Xb.astype(out_dtype)
-        X[i0:i1] = Xr
-        Y[i0:i1] = (Xb @ beta + zeta).astype(out_dtype)
+        X[i0:i1] = Xb.astype(out_dtype)
+        Y[i0:i1] = (_matvec(Xb, beta) + zeta).astype(out_dtype)
 
     _fill_blocks(n, block)
     meta["scale_min"] = float(scale.min())
@@ -166,11 +213,11 @@ def make_batched(count=64, seed=None, n_range=(1 << 14, 1 << 18), d_choices=(16,
         n, d = int(ns[b]), int(ds[b])
         z = g.standard_normal((n, d))
         w = g.chisquare(3, size=n)
-        Xb = z / np.sqrt(w / 3.0)[:, None]
-        Xb /= np.linalg.norm(Xb, axis=0)[None, :]
+        Xb = np.asfortranarray(z / np.sqrt(w / 3.0)[:, None])
+        Xb /= np.sqrt(np.add.reduce(Xb * Xb, axis=0))[None, :]
         beta = g.standard_normal(d)
         sigma = 1e-2
-        Y = Xb @ beta + sigma * g.standard_normal(n)
+        Y = _matvec(Xb, beta) + sigma * g.standard_normal(n)
         probs.append(Problem("batched", Xb.astype(np.float32), Y.astype(np.float32), beta, sigma,
                              dict(seed=seed, index=b)))
     return probs
@@ -189,9 +236,9 @@ def paper_problem(n, d, kappa, sigma2=1e-8, seed=DATA_SEED_BASE + 100, dtype=np.
         g = _gen(seed, b)
         i0 = b * ROW_BLOCK
         i1 = min(n, i0 + ROW_BLOCK)
-        Xb = g.standard_normal((i1 - i0, d)) * scale[None, :]
+        Xb = np.asfortranarray(g.standard_normal((i1 - i0, d)) * scale[None, :])
         X[i0:i1] = Xb
-        Y[i0:i1] = Xb @ beta + sigma * g.standard_normal(i1 - i0)
+        Y[i0:i1] = _matvec(Xb, beta) + sigma * g.standard_normal(i1 - i0)
 
     _fill_blocks(n, block)
     return Problem("paper", X, Y, beta, sigma, dict(seed=seed, kappa=kappa))
