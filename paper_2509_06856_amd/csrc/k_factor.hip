@@ -18,11 +18,20 @@ namespace {
 constexpr int kTile = 64;
 constexpr int kKStep = 16;
 
+// value of `v` held by lane `lane` (uniform), broadcast to the wave
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const double* __restrict__ A, int64_t lda,
                                                    int transA, const double* __restrict__ B,
                                                    int64_t ldb, int transB, double beta,
-                                                   double* __restrict__ C, int64_t ldc) {
+                                                   double* __restrict__ C, int64_t ldc,
+                                                   double* __restrict__ part, int64_t kper) {
   __shared__ double As[kKStep][kTile + 1];
   __shared__ double Bs[kKStep][kTile + 1];
   const int tx = threadIdx.x % 16;
@@ -30,7 +39,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
   const int64_t i0 = (int64_t)blockIdx.y * kTile;
   const int64_t j0 = (int64_t)blockIdx.x * kTile;
   double acc[4][4] = {};
-  for (int64_t k0 = 0; k0 < K; k0 += kKStep) {
+  const int64_t kb0 = (int64_t)blockIdx.z * kper;
+  const int64_t kend = min(K, kb0 + kper);
+  for (int64_t k0 = kb0; k0 < kend; k0 += kKStep) {
     for (int e = threadIdx.x; e < kKStep * kTile; e += 256) {
       int kk, ii;
       if (transA) {  // A stored K x M: contiguous along i
@@ -42,7 +53,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       }
       const int64_t gi = i0 + ii, gk = k0 + kk;
       double v = 0.0;
-      if (gi < M && gk < K) v = transA ? A[gk * lda + gi] : A[gi * lda + gk];
+      if (gi < M && gk < kend) v = transA ? A[gk * lda + gi] : A[gi * lda + gk];
       As[kk][ii] = v;
       int kb, jj;
       if (transB) {  // B stored N x K
@@ -54,7 +65,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       }
       const int64_t gj = j0 + jj, gkb = k0 + kb;
       double w = 0.0;
-      if (gj < N && gkb < K) w = transB ? B[gj * ldb + gkb] : B[gkb * ldb + gj];
+      if (gj < N && gkb < kend) w = transB ? B[gj * ldb + gkb] : B[gkb * ldb + gj];
       Bs[kb][jj] = w;
     }
     __syncthreads();
@@ -79,11 +90,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
     for (int v = 0; v < 4; ++v) {
       const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
       if (gi < M && gj < N) {
-        double c = alpha * acc[u][v];
-        if (beta != 0.0) c += beta * C[gi * ldc + gj];
-        C[gi * ldc + gj] = c;
+        if (part) {
+          part[((int64_t)blockIdx.z * M + gi) * N + gj] = acc[u][v];
+        } else {
+          double c = alpha * acc[u][v];
+          if (beta != 0.0) c += beta * C[gi * ldc + gj];
+          C[gi * ldc + gj] = c;
+        }
       }
     }
+}
+
+// C = alpha * sum_s part[s] + beta * C (splits summed in order)
+__global__ void gemm_reduce_kernel(int64_t M, int64_t N, int splits, const double* __restrict__ part,
+                                   double alpha, double beta, double* __restrict__ C, int64_t ldc) {
+  const int64_t n = M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < splits; ++q) t += part[(int64_t)q * n + e];
+    const int64_t i = e / N, j = e % N;
+    double c = alpha * t;
+    if (beta != 0.0) c += beta * C[i * ldc + j];
+    C[i * ldc + j] = c;
+  }
 }
 
 __global__ void convert_scale_kernel(int64_t rows, int d, const void* __restrict__ A, int64_t lda,
@@ -98,85 +128,106 @@ __global__ void convert_scale_kernel(int64_t rows, int d, const void* __restrict
   }
 }
 
-constexpr int kCholNB = 32;
-constexpr int kCholThreads = 1024;
+constexpr int kCholNB = 32;       // panel height
+constexpr int kCholThreads = 512;  // one thread per column of the panel
 constexpr int kCholMaxD = 512;
-constexpr int kCholKC = 32;
+constexpr int kCholKC = 32;       // rows of R staged per update step
 
+// Upper Cholesky R^T R = G by row panels of height 32.  Thread c owns column
+// J + c of the panel rows J..J+31 in registers.  Each panel is first reduced by
+// the rows of R above it (a GEMM against rows staged through LDS), its 32 x 32
+// diagonal block is then factored in LDS by the whole block, and the rest of
+// the panel is a triangular solve with that block, one column per thread.
 __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const double* __restrict__ G,
                                                                 int64_t ldg, double* __restrict__ R,
                                                                 int64_t ldr, int* __restrict__ info) {
-  __shared__ double P[kCholNB][kCholMaxD + 1];
   __shared__ double Kb[kCholKC][kCholNB];
-  __shared__ double s_diag;
+  __shared__ double D[kCholNB][kCholNB + 1];
   __shared__ int s_bad;
   const int t = threadIdx.x;
   if (t == 0) s_bad = 0;
   for (int J = 0; J < d; J += kCholNB) {
     const int w = min(kCholNB, d - J);
     const int ncols = d - J;
-    // 1. panel rows J..J+w of G, columns J..d
-    for (int e = t; e < w * ncols; e += kCholThreads) {
-      const int a = e / ncols, c = e % ncols;
-      P[a][c] = G[(int64_t)(J + a) * ldg + J + c];
+    const bool mine = t < ncols;
+    double acc[kCholNB];
+#pragma unroll
+    for (int a = 0; a < kCholNB; ++a) acc[a] = (mine && a < w) ? G[(int64_t)(J + a) * ldg + J + t] : 0.0;
+    // 1. subtract sum_{k < J} R[k][J+a] R[k][J+t]
+    for (int k0 = 0; k0 < J; k0 += kCholKC) {
+      const int kc = min(kCholKC, J - k0);
+      __syncthreads();
+      for (int e = t; e < kCholKC * kCholNB; e += kCholThreads) {
+        const int kk = e / kCholNB, a = e % kCholNB;
+        Kb[kk][a] = (kk < kc && a < w) ? R[(int64_t)(k0 + kk) * ldr + J + a] : 0.0;
+      }
+      double rc[kCholKC];
+#pragma unroll
+      for (int kk = 0; kk < kCholKC; ++kk)
+        rc[kk] = (mine && kk < kc) ? R[(int64_t)(k0 + kk) * ldr + J + t] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kCholKC; ++kk)
+#pragma unroll
+        for (int a = 0; a < kCholNB; ++a) acc[a] = fma(-Kb[kk][a], rc[kk], acc[a]);
     }
-    // 2. subtract sum_{k<J} R[k][J+a] R[k][J+c]
-    {
-      double acc[kCholNB];
+    // 2. factor the diagonal block: wave 0, lane c holds column c in registers,
+    //    rows of the block are broadcast lane to lane
+    if (t < 64) {
+      double col[kCholNB];
 #pragma unroll
-      for (int a = 0; a < kCholNB; ++a) acc[a] = 0.0;
-      const int c = t;
-      for (int k0 = 0; k0 < J; k0 += kCholKC) {
-        const int kc = min(kCholKC, J - k0);
-        __syncthreads();
-        for (int e = t; e < kc * w; e += kCholThreads) {
-          const int kk = e / w, a = e % w;
-          Kb[kk][a] = R[(int64_t)(k0 + kk) * ldr + J + a];
-        }
-        __syncthreads();
-        if (c < ncols) {
-          for (int kk = 0; kk < kc; ++kk) {
-            const double rc = R[(int64_t)(k0 + kk) * ldr + J + c];
+      for (int a = 0; a < kCholNB; ++a) col[a] = acc[a];
 #pragma unroll
-            for (int a = 0; a < kCholNB; ++a)
-              if (a < w) acc[a] = fma(Kb[kk][a], rc, acc[a]);
+      for (int a = 0; a < kCholNB; ++a) {
+        if (a < w) {
+          double piv = readlane_f64(col[a], a);
+          if (!(piv > 0.0) || !isfinite(piv)) {
+            if (t == 0 && !s_bad) s_bad = J + a + 1;
+            piv = 1.0;
+          }
+          const double rd = sqrt(piv);
+          const double inv = 1.0 / rd;
+          col[a] = (t == a) ? rd : col[a] * inv;  // row a of R: R[a][c]
+#pragma unroll
+          for (int b = a + 1; b < kCholNB; ++b) {
+            if (b < w) col[b] = fma(-readlane_f64(col[a], b), col[a], col[b]);
           }
         }
       }
-      __syncthreads();
-      if (c < ncols) {
+      if (t < w) {
 #pragma unroll
         for (int a = 0; a < kCholNB; ++a)
-          if (a < w) P[a][c] -= acc[a];
-      }
-    }
-    // 3. factor the panel: row a of R is row a of the panel scaled by 1/sqrt(pivot)
-    for (int a = 0; a < w; ++a) {
-      __syncthreads();
-      if (t == 0) {
-        double piv = P[a][a];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          if (!s_bad) s_bad = J + a + 1;
-          piv = 1.0;
-        }
-        s_diag = sqrt(piv);
-      }
-      __syncthreads();
-      const double inv = 1.0 / s_diag;
-      for (int c = a + t; c < ncols; c += kCholThreads) P[a][c] = (c == a) ? s_diag : P[a][c] * inv;
-      __syncthreads();
-      const int rows_left = w - a - 1;
-      for (int e = t; e < rows_left * ncols; e += kCholThreads) {
-        const int b = a + 1 + e / ncols, c = e % ncols;
-        if (c >= b) P[b][c] -= P[a][b] * P[a][c];
+          if (a < w) D[a][t] = col[a];
       }
     }
     __syncthreads();
-    // 4. write the panel rows of R (zero below the diagonal)
-    for (int e = t; e < w * d; e += kCholThreads) {
-      const int a = e / d, c = e % d;
-      const int rc = c - J;
-      R[(int64_t)(J + a) * ldr + c] = (rc >= a) ? P[a][rc] : 0.0;
+    // 3. the rest of the panel: solve D^T x = acc for each column t >= w
+    if (mine) {
+      if (t < w) {
+#pragma unroll
+        for (int a = 0; a < kCholNB; ++a) acc[a] = (a < w && a <= t) ? D[a][t] : 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a < kCholNB; ++a) {
+          if (a < w) {
+            double x = acc[a];
+#pragma unroll
+            for (int b = 0; b < kCholNB; ++b)
+              if (b < a) x = fma(-D[b][a], acc[b], x);
+            acc[a] = x / D[a][a];
+          }
+        }
+      }
+    }
+    // 4. write panel rows J..J+w of R (zero left of the diagonal)
+    for (int a = 0; a < w; ++a) {
+      double* Rr = R + (int64_t)(J + a) * ldr;
+      for (int c = t; c < J; c += kCholThreads) Rr[c] = 0.0;
+    }
+    if (mine) {
+#pragma unroll
+      for (int a = 0; a < kCholNB; ++a)
+        if (a < w) R[(int64_t)(J + a) * ldr + J + t] = acc[a];
     }
     __threadfence_block();
     __syncthreads();
@@ -184,41 +235,98 @@ __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const dou
   if (t == 0) info[0] = s_bad;
 }
 
-// L[j][i] = (R^{-1})[i][j]: one wave per j
-__global__ __launch_bounds__(256) void tri_inv_t_kernel(int d, const double* __restrict__ R,
-                                                        int64_t ldr, double* __restrict__ L,
-                                                        int64_t ldl) {
-  extern __shared__ double xs_all[];
+// Rinv = R^{-1} row by row: row i solves x^T R = e_i^T by forward
+// substitution over j with running sums s_l = -sum_{k<j} x_k R_kl, so each
+// step reads one row of R (contiguous).  Lane l keeps s for the columns
+// l, l+64, ... in registers; x_j is read from its owner lane.  A block's four
+// waves take rows i0..i0+3 and share rows of R staged through LDS.
+constexpr int kInvRows = 16;
+constexpr int kInvMaxD = 512;
+constexpr int kInvPer = kInvMaxD / 64;
+
+__global__ __launch_bounds__(256) void tri_inv_kernel(int d, const double* __restrict__ R,
+                                                      int64_t ldr, double* __restrict__ Rinv,
+                                                      int64_t ldi) {
+  __shared__ double Rs[kInvRows][kInvMaxD];
+  __shared__ double rdiag[kInvMaxD];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int j = blockIdx.x * 4 + wave;
-  if (j >= d) return;
-  double* xs = xs_all + (int64_t)wave * d;
-  for (int i = lane; i < d; i += 64) xs[i] = 0.0;
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) xs[j] = 1.0 / R[(int64_t)j * ldr + j];
-  __builtin_amdgcn_wave_barrier();
-  for (int i = j - 1; i >= 0; --i) {
-    const double* Ri = R + (int64_t)i * ldr;
-    double s = 0.0;
-    for (int k = i + 1 + lane; k <= j; k += 64) s = fma(Ri[k], xs[k], s);
-    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) xs[i] = -s / Ri[i];
-    __builtin_amdgcn_wave_barrier();
+  const int i0 = blockIdx.x * 4;
+  const int i = i0 + wave;
+  for (int l = threadIdx.x; l < d; l += 256) rdiag[l] = 1.0 / R[(int64_t)l * ldr + l];
+  double s[kInvPer];
+#pragma unroll
+  for (int k = 0; k < kInvPer; ++k) s[k] = 0.0;
+  for (int j0 = i0; j0 < d; j0 += kInvRows) {
+    const int jc = min(kInvRows, d - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < jc * d; e += 256) {
+      const int rr = e / d, c = e % d;
+      Rs[rr][c] = R[(int64_t)(j0 + rr) * ldr + c];
+    }
+    __syncthreads();
+    if (i < d) {
+      for (int jj = 0; jj < jc; ++jj) {
+        const int j = j0 + jj;
+        if (j < i) continue;
+        // x_j = (delta_ij + s_j) / R_jj, s_j held by lane j % 64 in slot j / 64
+        double sj = 0.0;
+#pragma unroll
+        for (int k = 0; k < kInvPer; ++k)
+          if (k == (j >> 6)) sj = readlane_f64(s[k], j & 63);
+        const double xj = ((j == i) ? 1.0 + sj : sj) * rdiag[j];
+#pragma unroll
+        for (int k = 0; k < kInvPer; ++k) {
+          const int l = lane + 64 * k;
+          if (l == j) {
+            s[k] = xj;  // slot j now holds x_j
+          } else if (l > j && l < d) {
+            s[k] = fma(-xj, Rs[jj][l], s[k]);
+          }
+        }
+      }
+    }
   }
-  for (int i = lane; i < d; i += 64) L[(int64_t)j * ldl + i] = (i <= j) ? xs[i] : 0.0;
+  if (i < d) {
+#pragma unroll
+    for (int k = 0; k < kInvPer; ++k) {
+      const int l = lane + 64 * k;
+      if (l < d) Rinv[(int64_t)i * ldi + l] = (l < i) ? 0.0 : s[k];
+    }
+  }
 }
 
 }  // namespace
 
+int gemm_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(M, kTile) * ceil_div(N, kTile);
+  int64_t sp = std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1));
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 128));
+  return (int)std::min<int64_t>(sp, 32);
+}
+
+size_t gemm_scratch_doubles(int64_t M, int64_t N, int64_t K) {
+  const int sp = gemm_splits(M, N, K);
+  return sp > 1 ? (size_t)sp * M * N : 0;
+}
+
 void launch_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                      bool transA, const double* B, int64_t ldb, bool transB, double beta, double* C,
-                     int64_t ldc, hipStream_t s) {
+                     int64_t ldc, hipStream_t s, double* scratch, size_t scratch_doubles) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((unsigned)ceil_div(N, kTile), (unsigned)ceil_div(M, kTile));
+  int sp = gemm_splits(M, N, K);
+  if (sp > 1 && (!scratch || scratch_doubles < (size_t)sp * M * N)) sp = 1;
+  const int64_t kper = sp > 1 ? round_up(ceil_div(K, sp), kKStep) : std::max<int64_t>(K, 1);
+  sp = (int)std::max<int64_t>(1, ceil_div(K, kper));
+  dim3 grid((unsigned)ceil_div(N, kTile), (unsigned)ceil_div(M, kTile), (unsigned)sp);
   gemm_kernel<<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0,
-                                   beta, C, ldc);
+                                   beta, C, ldc, sp > 1 ? scratch : nullptr, kper);
   SLSE_LAUNCH_CHECK();
+  if (sp > 1) {
+    const int blocks = (int)std::min<int64_t>(ceil_div(M * N, 256), 4096);
+    gemm_reduce_kernel<<<blocks, 256, 0, s>>>(M, N, sp, scratch, alpha, beta, C, ldc);
+    SLSE_LAUNCH_CHECK();
+  }
 }
 
 void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_dtype at, double s,
@@ -238,10 +346,9 @@ void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr
   SLSE_LAUNCH_CHECK();
 }
 
-void launch_tri_inv_t(int d, const double* R, int64_t ldr, double* L, int64_t ldl, hipStream_t s) {
-  const size_t shm = (size_t)4 * d * sizeof(double);
-  if (shm > 64 * 1024) fail(SLSE_EUNSUPPORTED, "tri_inv: d too large for this build");
-  tri_inv_t_kernel<<<(int)ceil_div(d, 4), 256, shm, s>>>(d, R, ldr, L, ldl);
+void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s) {
+  if (d > kInvMaxD) fail(SLSE_EUNSUPPORTED, "tri_inv: d > 512 not supported by this build");
+  tri_inv_kernel<<<(int)ceil_div(d, 4), 256, 0, s>>>(d, R, ldr, Rinv, ldi);
   SLSE_LAUNCH_CHECK();
 }
 

@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kGroupSize = 32;  // blocks summed by the last block of each group
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -67,7 +68,7 @@ template <typename T, typename Acc, int VEC, int NCH, bool HAS_Y>
 __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
     int64_t n, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t incy,
     const double* __restrict__ beta, int lpr, double* __restrict__ partial,
-    double* __restrict__ gpart, int* __restrict__ counters, int group_size, int ldp,
+    double* __restrict__ gpart, int* __restrict__ counters, int ldp,
     const int* __restrict__ done) {
   constexpr int UNROLL = unroll_for<T, VEC, NCH>();
   if (done && *done) return;
@@ -186,16 +187,21 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
   // last block of the group sums the group's partial rows in block order
   __threadfence();
   __syncthreads();
-  const int group = blockIdx.x / group_size;
-  const int g0 = group * group_size;
-  const int gsz = min(group_size, (int)gridDim.x - g0);
+  const int group = blockIdx.x / kGroupSize;
+  const int g0 = group * kGroupSize;
+  const int gsz = min(kGroupSize, (int)gridDim.x - g0);
   if (threadIdx.x == 0) s_ticket = atomicAdd(&counters[group], 1);
   __syncthreads();
   if (s_ticket == gsz - 1) {
     __threadfence();
     for (int col = threadIdx.x; col < d + 1; col += kThreads) {
+      double v[kGroupSize];
+#pragma unroll
+      for (int bk = 0; bk < kGroupSize; ++bk)
+        v[bk] = bk < gsz ? partial[(int64_t)(g0 + bk) * ldp + col] : 0.0;
       double t = 0.0;
-      for (int bk = 0; bk < gsz; ++bk) t += partial[(int64_t)(g0 + bk) * ldp + col];
+#pragma unroll
+      for (int bk = 0; bk < kGroupSize; ++bk) t += v[bk];
       gpart[(int64_t)group * ldp + col] = t;
     }
     if (threadIdx.x == 0) atomicExch(&counters[group], 0);
@@ -221,12 +227,12 @@ void launch_t(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
   const T* Y = static_cast<const T*>(a.Y);
   if (Y) {
     resid_grad_kernel<T, Acc, VEC, NCH, true><<<pl.blocks, kThreads, 0, s>>>(
-        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters,
-        pl.group_size, pl.ldp, a.done);
+        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters, pl.ldp,
+        a.done);
   } else {
     resid_grad_kernel<T, Acc, VEC, NCH, false><<<pl.blocks, kThreads, 0, s>>>(
-        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters,
-        pl.group_size, pl.ldp, a.done);
+        a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters, pl.ldp,
+        a.done);
   }
 }
 
@@ -255,21 +261,30 @@ void launch_vec(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) 
 }  // namespace
 
 ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
-                              int grid_blocks, int capacity) {
+                              int grid_blocks, int capacity, int lpr_hint) {
   ResidGradPlan pl;
   const int es = (int)dtype_size(storage);
   const int vfull = 16 / es;
   const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * es) % 16 == 0);
   pl.vec = aligned ? vfull : 1;
   const int nvec = (int)ceil_div(d, pl.vec);
-  // a row is spread over up to a full wave (so each lane holds only a few
-  // vectors of it) and many rows are kept in flight per lane instead
+  // default: about eight vector chunks per lane (measured best for wide rows);
+  // lane groups are powers of 2 up to a wave
   int lpr = 1;
-  while (lpr < 64 && lpr * 2 <= nvec) lpr *= 2;
-  if (const char* e = std::getenv("SLSE_RG_LPR")) lpr = std::max(1, std::min(64, std::atoi(e)));
+  while (lpr < 64 && lpr * 16 <= nvec) lpr *= 2;
+  if (lpr_hint > 0) lpr = lpr_hint;
+  if (const char* e = std::getenv("SLSE_RG_LPR")) lpr = std::atoi(e);
+  lpr = std::max(1, std::min(64, lpr));
+  while (lpr & (lpr - 1)) lpr &= lpr - 1;
   int nch = (int)ceil_div(nvec, lpr);
   int p2 = 1;
   while (p2 < nch) p2 *= 2;
+  while (p2 > 16 && lpr < 64) {  // too many chunks: widen the lane group
+    lpr *= 2;
+    nch = (int)ceil_div(nvec, lpr);
+    p2 = 1;
+    while (p2 < nch) p2 *= 2;
+  }
   if (p2 > 16) fail(SLSE_EUNSUPPORTED, "resid_grad: d too large for this build");
   pl.lpr = lpr;
   pl.nch = p2;
@@ -284,7 +299,7 @@ ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* 
     target = std::max(1, std::min(capacity, std::atoi(e)));
   int64_t want = ceil_div(std::max<int64_t>(n, 1), (int64_t)rows_per_block_step * unroll);
   pl.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, target));
-  pl.group_size = 32;
+  pl.group_size = kGroupSize;
   pl.groups = (int)ceil_div(pl.blocks, pl.group_size);
   return pl;
 }

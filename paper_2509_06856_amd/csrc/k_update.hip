@@ -25,8 +25,17 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
   __shared__ int s_ticket;
   const int d = a.d;
   for (int k = threadIdx.x; k < d; k += kThreads) {
+    // fixed-order sum over the groups, loads issued eight at a time
     double t = 0.0;
-    for (int q = 0; q < a.groups; ++q) t += a.gpart[(int64_t)q * a.ldp + k];
+    int q = 0;
+    for (; q + 8 <= a.groups; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = a.gpart[(int64_t)(q + u) * a.ldp + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += v[u];
+    }
+    for (; q < a.groups; ++q) t += a.gpart[(int64_t)q * a.ldp + k];
     double g = a.scale * t;
     if (a.w) g += a.w[k];
     s_g[k] = g;
@@ -73,13 +82,28 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
   __syncthreads();
   if (s_ticket != (int)gridDim.x - 1) return;
   __threadfence();
+  // the last block: every thread sums a fixed subset of the block partials,
+  // then a fixed tree over the threads (deterministic)
+  __shared__ double s_tail[3][kThreads];
+  double tgp = 0.0, tpp = 0.0, tbb = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads) {
+    tgp += a.sur_partial[3 * b + 0];
+    tpp += a.sur_partial[3 * b + 1];
+    tbb += a.sur_partial[3 * b + 2];
+  }
+  s_tail[0][threadIdx.x] = tgp;
+  s_tail[1][threadIdx.x] = tpp;
+  s_tail[2][threadIdx.x] = tbb;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < 3; ++c) s_tail[c][threadIdx.x] += s_tail[c][threadIdx.x + h];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    double tgp = 0.0, tpp = 0.0, tbb = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) {
-      tgp += a.sur_partial[3 * b + 0];
-      tpp += a.sur_partial[3 * b + 1];
-      tbb += a.sur_partial[3 * b + 2];
-    }
+    tgp = s_tail[0][0];
+    tpp = s_tail[1][0];
+    tbb = s_tail[2][0];
     const double est = tbb > 0.0 ? sqrt(tpp / tbb) : sqrt(tpp);
     if (a.sur_out) a.sur_out[0] = est;
     const bool finite = isfinite(tgp) && isfinite(tpp) && isfinite(tbb);

@@ -23,8 +23,10 @@ struct ResidGradPlan {
   int ldp = 0;   // leading dimension of partial rows (>= d + 1)
 };
 
+// lpr_hint > 0 picks the lane-group width (else a default); grid_blocks is the
+// target grid, capped by `capacity` (the rows allocated for block partials).
 ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* X, int64_t ldx,
-                              int grid_blocks, int capacity);
+                              int grid_blocks, int capacity, int lpr_hint = 0);
 
 struct ResidGradArgs {
   int64_t n = 0;
@@ -117,6 +119,7 @@ struct SrhtArgs {
   int64_t ldz = 0;
   int ct = 0;                 // column tile (chosen by srht_plan)
   int bmax = 0;               // stages per pass cap
+  bool narrow = false;        // half-width column tiles (two blocks per CU)
 };
 
 void srht_plan(SrhtArgs& a, int prefer_ct);
@@ -169,10 +172,14 @@ void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_
 // --------------------------------------------------------------------------
 // Dense FP64 helpers for the factorization.
 // --------------------------------------------------------------------------
-// C[MxN] = alpha * op(A) * op(B) + beta * C, all FP64 row-major.
+// C[MxN] = alpha * op(A) * op(B) + beta * C, all FP64 row-major.  Small outputs
+// with long K are split over K into `scratch` (gemm_scratch_doubles entries)
+// and summed in split order.
+size_t gemm_scratch_doubles(int64_t M, int64_t N, int64_t K);
 void launch_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                      bool transA, const double* B, int64_t ldb, bool transB, double beta, double* C,
-                     int64_t ldc, hipStream_t s);
+                     int64_t ldc, hipStream_t s, double* scratch = nullptr,
+                     size_t scratch_doubles = 0);
 // out[i][k] = s * A[i][k] for i < rows, k < d (A in F32 or F64).
 void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_dtype at, double s,
                           double* out, int64_t ldo, hipStream_t st);
@@ -180,8 +187,8 @@ void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_
 // first bad pivot.  G is read only.
 void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr, int* info,
                      hipStream_t s);
-// L = R^{-T} (lower triangular, row-major d x d) for upper triangular R.
-void launch_tri_inv_t(int d, const double* R, int64_t ldr, double* L, int64_t ldl, hipStream_t s);
+// Rinv = R^{-1} (upper triangular, row-major d x d) for upper triangular R.
+void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Adjoint rank-2 pass: dY = X lambda, dX = r lambda^T - (X lambda) beta^T.

@@ -4,6 +4,7 @@
 // driver and the C-ABI entry points.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -79,6 +80,9 @@ struct slse_ctx {
     int precision = 0;
   } pre;
   std::map<std::string, hipGraphExec_t> graphs;
+  // autotuned (grid blocks, lanes per row) of the residual-gradient pass, keyed
+  // by storage / accumulation / d / vector width / log2(rows)
+  std::map<std::string, std::pair<int, int>> rg_tune;
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
@@ -273,11 +277,13 @@ struct FactorBufs {
   double* Ad = nullptr;  // rows x d
   double* G = nullptr;   // d x d
   double* R = nullptr;   // d x d (ldr)
-  double* L = nullptr;   // d x d
+  double* L = nullptr;   // d x d: R^{-1}
   double* M = nullptr;   // d x d
   double* Q = nullptr;   // rows x d (QR route)
   double* R2 = nullptr;  // d x d (QR route)
   int* info = nullptr;   // 2 ints
+  double* part = nullptr;  // split-K scratch of the GEMMs
+  size_t part_n = 0;
 };
 
 FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_method method) {
@@ -292,6 +298,9 @@ FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_me
     f.R2 = ctx->arena.get_t<double>("f_R2", d * d);
   }
   f.info = ctx->arena.get_t<int>("f_info", 4, true);
+  f.part_n = std::max(gemm_scratch_doubles(d, d, rows), gemm_scratch_doubles(d, d, d));
+  if (method == SLSE_FACTOR_QR) f.part_n = std::max(f.part_n, gemm_scratch_doubles(rows, d, d));
+  f.part = ctx->arena.get_t<double>("f_part", f.part_n + 1);
   return f;
 }
 
@@ -299,19 +308,20 @@ FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_me
 void enqueue_factor(const FactorBufs& f, int64_t rows, int d, const void* A, int64_t lda,
                     slse_dtype at, double scale, slse_factor_method method, hipStream_t st) {
   launch_convert_scale(rows, d, A, lda, at, std::sqrt(scale), f.Ad, d, st);
-  launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st);
+  launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st, f.part, f.part_n);
   launch_cholesky(d, f.G, d, f.R, d, f.info, st);
   if (method == SLSE_FACTOR_QR) {
     // CholeskyQR2: Q1 = Ad R1^{-1}, R2 = chol(Q1^T Q1), R = R2 R1
-    launch_tri_inv_t(d, f.R, d, f.L, d, st);
-    launch_gemm_f64(rows, d, d, 1.0, f.Ad, d, false, f.L, d, true, 0.0, f.Q, d, st);
-    launch_gemm_f64(d, d, rows, 1.0, f.Q, d, true, f.Q, d, false, 0.0, f.G, d, st);
+    launch_tri_inv(d, f.R, d, f.L, d, st);
+    launch_gemm_f64(rows, d, d, 1.0, f.Ad, d, false, f.L, d, false, 0.0, f.Q, d, st, f.part, f.part_n);
+    launch_gemm_f64(d, d, rows, 1.0, f.Q, d, true, f.Q, d, false, 0.0, f.G, d, st, f.part, f.part_n);
     launch_cholesky(d, f.G, d, f.R2, d, f.info + 1, st);
-    launch_gemm_f64(d, d, d, 1.0, f.R2, d, false, f.R, d, false, 0.0, f.G, d, st);
+    launch_gemm_f64(d, d, d, 1.0, f.R2, d, false, f.R, d, false, 0.0, f.G, d, st, f.part, f.part_n);
     launch_copy_f64(f.G, f.R, (int64_t)d * d, st);
   }
-  launch_tri_inv_t(d, f.R, d, f.L, d, st);
-  launch_gemm_f64(d, d, d, 1.0, f.L, d, true, f.L, d, false, 0.0, f.M, d, st);
+  // M = R^{-1} R^{-T}
+  launch_tri_inv(d, f.R, d, f.L, d, st);
+  launch_gemm_f64(d, d, d, 1.0, f.L, d, false, f.L, d, true, 0.0, f.M, d, st, f.part, f.part_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +356,88 @@ IterBufs reserve_iter(slse_ctx* ctx, int64_t d, const char* tag) {
   return b;
 }
 
+std::string rg_key(int64_t n, int d, slse_dtype storage, slse_dtype accum, const void* X,
+                   int64_t ldx) {
+  const int es = (int)dtype_size(storage);
+  const bool vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * es) % 16 == 0);
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= n) ++lg;
+  return std::to_string((int)storage) + "/" + std::to_string((int)accum) + "/" +
+         std::to_string(d) + "/" + (vec ? "v" : "s") + "/" + std::to_string(lg);
+}
+
+ResidGradPlan rg_plan(const slse_ctx* ctx, const IterBufs& b, int64_t n, int d,
+                      slse_dtype storage, slse_dtype accum, const void* X, int64_t ldx) {
+  if (ctx) {
+    auto it = ctx->rg_tune.find(rg_key(n, d, storage, accum, X, ldx));
+    if (it != ctx->rg_tune.end())
+      return plan_resid_grad(n, d, storage, X, ldx, it->second.first, b.max_blocks,
+                             it->second.second);
+  }
+  return plan_resid_grad(n, d, storage, X, ldx, b.grid_blocks, b.max_blocks);
+}
+
+// Time a few (grid, lane-group) shapes of the residual-gradient pass on the
+// actual data and keep the fastest for this shape (never inside a capture).
+void tune_resid_grad(slse_ctx* ctx, const IterBufs& b, int64_t n, int d, slse_dtype storage,
+                     slse_dtype accum, const void* X, int64_t ldx, const void* Y, int64_t incy,
+                     hipStream_t st) {
+  if (n < (int64_t(1) << 16)) return;
+  if (const char* e = std::getenv("SLSE_AUTOTUNE"))
+    if (std::atoi(e) == 0) return;
+  const std::string key = rg_key(n, d, storage, accum, X, ldx);
+  if (ctx->rg_tune.count(key)) return;
+  const ResidGradPlan base = plan_resid_grad(n, d, storage, X, ldx, b.grid_blocks, b.max_blocks);
+  std::vector<int> lprs;
+  for (int l : {base.lpr / 2, base.lpr, base.lpr * 2})
+    if (l >= 1 && l <= 64) lprs.push_back(l);
+  std::vector<int> grids;
+  for (int g : {ctx->num_cus, 2 * ctx->num_cus, 4 * ctx->num_cus})
+    if (g <= b.max_blocks) grids.push_back(g);
+  hipEvent_t e0, e1;
+  SLSE_HIP(hipEventCreate(&e0));
+  SLSE_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, int> pick{base.blocks, base.lpr};
+  for (int g : grids)
+    for (int l : lprs) {
+      ResidGradPlan pl;
+      try {
+        pl = plan_resid_grad(n, d, storage, X, ldx, g, b.max_blocks, l);
+      } catch (const Error&) {
+        continue;
+      }
+      ResidGradArgs a;
+      a.n = n;
+      a.d = d;
+      a.X = X;
+      a.ldx = ldx;
+      a.Y = Y;
+      a.incy = incy;
+      a.storage = storage;
+      a.accum = accum;
+      a.beta = b.beta[0];
+      a.partial = b.partial;
+      a.gpart = b.gpart;
+      a.counters = b.counters;
+      a.capacity_blocks = b.max_blocks;
+      launch_resid_grad(pl, a, st);
+      SLSE_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) launch_resid_grad(pl, a, st);
+      SLSE_HIP(hipEventRecord(e1, st));
+      SLSE_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        pick = {g, pl.lpr};
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->rg_tune[key] = pick;
+}
+
 struct Stepper {
   IterBufs b;
   int d;
@@ -353,6 +445,7 @@ struct Stepper {
   int cur = 0, prev = 0;
   int t = 0;  // iterate index
   hipStream_t st;
+  const slse_ctx* ctx = nullptr;
 
   void start(const double* beta0, double* traj) {
     if (beta0)
@@ -370,7 +463,7 @@ struct Stepper {
   void step(int64_t n, const void* X, int64_t ldx, const void* Y, int64_t incy, slse_dtype storage,
             slse_dtype accum, double scale, const double* w, double mu, double eta, double* beta_out,
             double* traj, double* sur, double tol) {
-    const ResidGradPlan pl = plan_resid_grad(n, d, storage, X, ldx, b.grid_blocks, b.max_blocks);
+    const ResidGradPlan pl = rg_plan(ctx, b, n, d, storage, accum, X, ldx);
     ResidGradArgs a;
     a.n = n;
     a.d = d;
@@ -468,14 +561,14 @@ SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params*
   return pl;
 }
 
-void enqueue_solve(const SolvePlan& pl, const slse_problem* p, const slse_params* q,
-                   double* beta_out, hipStream_t st) {
+void enqueue_solve(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem* p,
+                   const slse_params* q, double* beta_out, hipStream_t st) {
   const int d = (int)p->d;
   const SketchShape& sk = pl.sk;
   enqueue_sketch(sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah, pl.srht,
                  pl.ga, pl.gh, st);
   enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
-  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st};
+  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx};
   S.start(q->beta0, q->trajectory);
   launch_copy_f64(S.b.beta[0], beta_out, d, st);
   const size_t es = dtype_size(pl.st_t);
@@ -571,6 +664,20 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
   }
   q = &qq;
   if (ctx->arena.grew) ctx->drop_graphs();
+  {
+    // shapes of the stage-2 sweeps and of the large stage-1 prefixes
+    const slse_dtype acc2 = q->precision == SLSE_PREC_MIXED && q->fp32_sweeps > 0 ? SLSE_F32
+                                                                                  : SLSE_F64;
+    tune_resid_grad(ctx, pl.it, p->N, (int)p->d, pl.st_t, SLSE_F64, p->X, p->ldx, p->Y, 1, st);
+    if (acc2 == SLSE_F32)
+      tune_resid_grad(ctx, pl.it, p->N, (int)p->d, pl.st_t, SLSE_F32, p->X, p->ldx, p->Y, 1, st);
+    const size_t es = dtype_size(pl.st_t);
+    for (int i = 0; i < pl.sk.K; ++i) {
+      const char* base = static_cast<const char*>(pl.A) + (size_t)pl.sk.offset[i] * pl.lda * es;
+      tune_resid_grad(ctx, pl.it, pl.sk.m[i], (int)p->d, pl.st_t, pl.acc1, base, pl.lda,
+                      base + (size_t)p->d * es, pl.lda, st);
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (rep) {
     SLSE_HIP(hipEventCreate(&e0));
@@ -584,7 +691,7 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
       hipGraph_t g = nullptr;
       SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
       try {
-        enqueue_solve(pl, p, q, beta_out, ctx->capture_stream);
+        enqueue_solve(ctx, pl, p, q, beta_out, ctx->capture_stream);
       } catch (...) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(ctx->capture_stream, &junk);
@@ -599,7 +706,7 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
     }
     SLSE_HIP(hipGraphLaunch(itg->second, st));
   } else {
-    enqueue_solve(pl, p, q, beta_out, st);
+    enqueue_solve(ctx, pl, p, q, beta_out, st);
   }
   ctx->pre.valid = true;
   ctx->pre.seed = q->seed;
@@ -656,7 +763,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     ctx->pre.valid = false;
   }
   // lambda_0 = M w: one update step with g = w from a zero gradient and beta = 0
-  Stepper S{ib, d, pl.f.M, 0, 0, 0, st};
+  Stepper S{ib, d, pl.f.M, 0, 0, 0, st, ctx};
   S.start(nullptr, nullptr);
   launch_fill_f64(zero, 0.0, d, st);
   {
@@ -862,7 +969,8 @@ slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const voi
     ctx->arena.grew = false;
     IterBufs b = reserve_iter(ctx, d, "rg");
     if (ctx->arena.grew) ctx->drop_graphs();
-    const ResidGradPlan pl = plan_resid_grad(n, (int)d, storage, X, ldx, b.grid_blocks, b.max_blocks);
+    if (n > 0) tune_resid_grad(ctx, b, n, (int)d, storage, accum, X, ldx, Y, 1, st);
+    const ResidGradPlan pl = rg_plan(ctx, b, n, (int)d, storage, accum, X, ldx);
     if (n == 0) {
       launch_fill_f64(g_out, 0.0, d, st);
       if (rnorm2_out) launch_fill_f64(rnorm2_out, 0.0, 1, st);
