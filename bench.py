@@ -101,12 +101,99 @@ def cpu_baseline(name, d, params_gpu, s_star, tol, n_sample):
     return t, rel_err(beta, bstar), threads
 
 
+def bench_batched(args, G, torch, dev):
+    """64 uneven FP32 regressions in one batched solve (one captured graph)."""
+    from slse_inputs import fingerprint, make_batched
+
+    ref = load_reference("batched")
+    t0 = time.perf_counter()
+    probs = make_batched()
+    log(f"generated {len(probs)} problems in {time.perf_counter() - t0:.1f}s")
+    for p, r in zip(probs, ref["problems"]):
+        if fingerprint(p.X, p.Y) != r["fingerprint"]:
+            print("regenerated batched data differ from the stored reference", file=sys.stderr)
+            sys.exit(3)
+    stars = [np.asarray(r["beta_star"]) for r in ref["problems"]]
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    Ys = [torch.from_numpy(p.Y).to(dev) for p in probs]
+    seed0 = 1005
+
+    def params(s):
+        out = []
+        for i, p in enumerate(probs):
+            m = G.paper_schedule(p.n, p.d)
+            out.append(G.Params(kind="srht", seed=seed0 + 100 * i, m=m, a=[2] * len(m), r=6 * p.d,
+                                s_max=s, precision="mixed"))
+        return out
+
+    s_star, worst = None, None
+    for s in range(15, args.s_cap + 1, 5):
+        betas, _ = G.solve_batched(Xs, Ys, params(s))
+        worst = max(rel_err(b.cpu().numpy(), st) for b, st in zip(betas, stars))
+        log(f"calibration: s={s} worst rel err {worst:.2e}")
+        if worst <= args.tol:
+            s_star = s
+            break
+    if s_star is None:
+        print("batched: tolerance not reached", file=sys.stderr)
+        sys.exit(4)
+    ps = params(s_star)
+    for _ in range(args.warmup):
+        G.solve_batched(Xs, Ys, ps, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        betas, _ = G.solve_batched(Xs, Ys, ps, report=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    worst = max(rel_err(b.cpu().numpy(), st) for b, st in zip(betas, stars))
+    rows = sum(p.n for p in probs)
+    sweep_bytes = sum(p.n * (p.d + 1) * 4 for p in probs)
+    stage1_bytes = sum(2 * sum(G.paper_schedule(p.n, p.d)) * (p.d + 1) * 4 for p in probs)
+    moved = s_star * sweep_bytes + stage1_bytes
+    gbs = moved / t / 1e9
+    log(f"batched solve: {t * 1e3:.2f} ms for {len(probs)} problems, worst rel err {worst:.2e}")
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_info
+
+        from oracle import slse as OS
+
+        sample = probs[:4]
+        t1 = time.perf_counter()
+        for i, p in enumerate(sample):
+            m = OS.paper_schedule(p.n, p.d)
+            OS.slse_frs(p.X, p.Y, seed0 + 100 * i, "srht", m, [2] * len(m), 6 * p.d, s=s_star)
+        tc = time.perf_counter() - t1
+        srows = sum(p.n * p.d for p in sample)
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        cpu = {"value": tc * sum(p.n * p.d for p in probs) / srows, "unit": "s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"oracle SLSE-FRS on the first 4 problems ({tc:.2f}s), scaled by total N*d"}
+    out = {
+        "metric": METRIC, "value": t, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage, f64 accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(probs)} problems, N_b in [2^14, 2^18], "
+                               "d_b in {16..256}, Student-t(3) rows, float32",
+                   "rows_total": rows, "stage2_steps": s_star, "worst_rel_err": worst,
+                   "tol": args.tol},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole batched solve: algorithmic sweep bytes / solve time",
+                     "algorithmic_bytes": moved},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond"])
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond", "batched"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--s-cap", type=int, default=60)
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
@@ -132,6 +219,8 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
     name = args.workload
+    if name == "batched":
+        return bench_batched(args, G, torch, dev)
     ref = load_reference(name)
     beta_star = np.asarray(ref["beta_star"])
 

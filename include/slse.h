@@ -106,7 +106,10 @@ slse_status slse_ctx_trim(slse_ctx* ctx);
  *               CountSketch: rows_A = m_1 + ... + m_K, levels back to back,
  *               c_i = 1.
  *  Ahat, ldah   device output, r x (d+1) in out_t, ldah >= d+1.
- *  out_t        SLSE_F32 or SLSE_F64; must equal in_t except F64 -> F32.
+ *  out_t        SLSE_F32 or SLSE_F64, equal to in_t; or SLSE_BF16 for a Gaussian
+ *               sketch of F32 data computed on the matrix cores with BF16 operands
+ *               (G and [X|Y] rounded to BF16) and FP32 accumulation: A and Ahat are
+ *               then written as F32.
  *  layout_out   host, filled with the level offsets and scales (may be NULL).
  * Errors: EINVAL for null pointers, sizes or orderings above; EUNSUPPORTED for
  * dtype pairs not listed; ENOMEM when scratch cannot grow.
@@ -173,15 +176,16 @@ typedef struct {
   int64_t r;                  /* Hessian sketch rows */
   double mu, eta;             /* step sizes; Sec. 5 uses eta = d/r, mu = (1-eta)^2 */
   int32_t s_max;              /* stage-2 (full-data) steps, or the cap when tol > 0 */
-  double tol;                 /* > 0: stop stage 2 once ||R^{-T} g_t|| <= tol * ||R^{-T} g_0||
-                                 with g_0 = X^T Y (the surrogate of the stop test) */
+  double tol;                 /* > 0: stop stage 2 at the first step whose estimate
+                                 ||H_hat^{-1} g_t|| / ||beta_{t+1}|| of the relative error of
+                                 beta_t (beta_hat - beta_t = H^{-1} g_t) is <= tol */
   slse_precision precision;
   int32_t fp32_sweeps;        /* MIXED only, see slse_precision */
   int32_t momentum_reset;     /* 1: beta_{t-1} := beta_t at each subproblem and stage start */
   slse_factor_method factor;
   const double* beta0;        /* device, d; NULL = 0 */
   double* trajectory;         /* device, (sum a_i + s_max + 1) x d, row t = beta_t; or NULL */
-  double* surrogate;          /* device, (sum a_i + s_max), ||R^{-T} g_t||^2 per step; or NULL */
+  double* surrogate;          /* device, (sum a_i + s_max): the estimate above, per step; or NULL */
   int32_t use_graph;          /* 1: capture the whole solve once and replay it as a hipGraph */
 } slse_params;
 
@@ -189,8 +193,8 @@ typedef struct {
   slse_status status;
   int32_t stage1_steps;
   int32_t stage2_steps; /* steps actually taken */
-  double surrogate0;    /* ||R^{-T} X^T Y|| */
-  double surrogate_final;
+  double surrogate0;    /* error estimate at the first stage-2 step */
+  double surrogate_final; /* error estimate at the last step taken */
   double ms_total;      /* device time of the call (hipEvents), when requested */
 } slse_report;
 

@@ -187,6 +187,99 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gaussian sketch on the matrix cores: G and [X|Y] rounded to BF16 (nearest
+// even), products accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  Block
+// tile 128 sketch rows x 128 columns, one wave per 32 rows, four 32 x 32
+// accumulators per wave; 16 data rows per step, G generated into LDS by the
+// block (one Philox block per thread per step), [X|Y] staged transposed so
+// that every lane reads its 8 consecutive k as one 16-byte load.
+// Lane layout (checked by an in-bounds probe): lane l holds A[l%32][8(l/32)+j]
+// and B[8(l/32)+j][l%32], j < 8; accumulator r of lane l is
+// C[(r%4) + 8(r/4) + 4(l/32)][l%32].
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kMT = 128;  // sketch rows per block
+constexpr int kNT = 128;  // columns per block
+constexpr int kKT = 16;   // data rows per step
+constexpr int kKP = kKT + 8;  // padded LDS row (bf16 elements)
+
+__device__ __forceinline__ __bf16 to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return __builtin_bit_cast(__bf16, (uint16_t)u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const T* __restrict__ X,
+                                                         int64_t ldx, const T* __restrict__ Y,
+                                                         uint64_t seed, uint64_t stream, int64_t m,
+                                                         int splits, float* __restrict__ part,
+                                                         int64_t ldp) {
+  __shared__ __attribute__((aligned(16))) __bf16 Gs[kMT][kKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Ws[kNT][kKP];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t k0 = (int64_t)blockIdx.y * kMT;
+  const int c0 = blockIdx.x * kNT;
+  const int split = blockIdx.z;
+  const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
+  const int64_t j_begin = (int64_t)split * per;
+  const int64_t j_end = min(N, j_begin + per);
+  f32x16_t acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  for (int64_t j0 = j_begin; j0 < j_end; j0 += kKT) {
+    {  // G tile: thread -> (row block of 8, data row)
+      const int kb = threadIdx.x / kKT;  // 0..15
+      const int jj = threadIdx.x % kKT;
+      const int64_t j = j0 + jj;
+      float z[8];
+      if (j < j_end) {
+        box_muller8(seed, stream, (uint64_t)j, (uint64_t)((k0 >> 3) + kb), z);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) z[q] = 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
+    }
+    for (int e = threadIdx.x; e < kKT * kNT; e += 256) {  // [X|Y] tile, stored transposed
+      const int jj = e / kNT, cc = e % kNT;
+      const int64_t j = j0 + jj;
+      const int col = c0 + cc;
+      float v = 0.0f;
+      if (j < j_end) {
+        if (col < d)
+          v = (float)X[j * ldx + col];
+        else if (col == d)
+          v = (float)Y[j];
+      }
+      Ws[cc][jj] = to_bf16_rne(v);
+    }
+    __syncthreads();
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[wave * 32 + (lane & 31)][8 * (lane >> 5)]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Ws[q * 32 + (lane & 31)][8 * (lane >> 5)]);
+      acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t k = k0 + wave * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
+      const int col = c0 + q * 32 + (lane & 31);
+      if (k < m && col <= d) part[((int64_t)split * m + k) * ldp + col] = acc[q][r];
+    }
+}
+
 __global__ void debug_gauss_kernel(uint64_t seed, uint64_t stream, int64_t k0, int64_t nk,
                                    int64_t j0, int64_t nj, double* __restrict__ out) {
   const int64_t n = nk * nj;
@@ -232,6 +325,20 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   }
 }
 
+template <typename T>
+void gaussian_mfma_t(const GaussianArgs& a, hipStream_t s) {
+  const int cols = a.d + 1;
+  const int64_t ldp = round_up(cols, 4);
+  dim3 grid((unsigned)ceil_div(cols, kNT), (unsigned)ceil_div(a.m, kMT), (unsigned)a.splits);
+  gauss_mfma_kernel<T><<<grid, 256, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
+                                            static_cast<const T*>(a.Y), a.seed, a.stream_id, a.m,
+                                            a.splits, a.partial, ldp);
+  SLSE_LAUNCH_CHECK();
+  gauss_reduce_kernel<float, float><<<grid1(a.m * cols), 256, 0, s>>>(
+      a.partial, a.splits, a.m, cols, ldp, static_cast<float*>(a.A), a.lda);
+  SLSE_LAUNCH_CHECK();
+}
+
 template <typename T, typename Acc>
 void gaussian_t(const GaussianArgs& a, hipStream_t s) {
   const int cols = a.d + 1;
@@ -260,7 +367,8 @@ void launch_countsketch(const CountSketchArgs& a, hipStream_t s) {
 }
 
 void gaussian_plan(GaussianArgs& a) {
-  const int64_t tiles = ceil_div(a.d + 1, kGT) * ceil_div(a.m, kGT);
+  const int64_t tiles = a.bf16 ? ceil_div(a.d + 1, kNT) * ceil_div(a.m, kMT)
+                               : ceil_div(a.d + 1, kGT) * ceil_div(a.m, kGT);
   // enough blocks to fill the chip, each split at least a few thousand rows
   int64_t splits = std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles, 1));
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, a.N / 4096));
@@ -268,11 +376,16 @@ void gaussian_plan(GaussianArgs& a) {
 }
 
 size_t gaussian_scratch_bytes(const GaussianArgs& a) {
-  const size_t es = a.t == SLSE_F64 ? 8 : 4;
+  const size_t es = (a.t == SLSE_F64 && !a.bf16) ? 8 : 4;
   return (size_t)a.splits * (size_t)a.m * (size_t)round_up(a.d + 1, 4) * es;
 }
 
 void launch_gaussian(const GaussianArgs& a, hipStream_t s) {
+  if (a.bf16) {
+    if (a.t != SLSE_F32) fail(SLSE_EUNSUPPORTED, "gaussian: BF16 products need F32 data");
+    gaussian_mfma_t<float>(a, s);
+    return;
+  }
   if (a.t == SLSE_F64)
     gaussian_t<double, double>(a, s);
   else if (a.t == SLSE_F32)

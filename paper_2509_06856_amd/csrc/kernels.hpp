@@ -162,6 +162,7 @@ struct GaussianArgs {
   float* partial = nullptr;   // split-K scratch
   double* partial64 = nullptr;
   int splits = 0;
+  bool bf16 = false;          // BF16 operands on the matrix cores, FP32 accumulation
 };
 size_t gaussian_scratch_bytes(const GaussianArgs& a);
 void gaussian_plan(GaussianArgs& a);
@@ -208,6 +209,36 @@ struct AdjointArgs {
   slse_dtype gt = SLSE_F64;
 };
 void launch_adjoint(const AdjointArgs& a, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// Batched M-IHS steps (many problems per launch).
+// --------------------------------------------------------------------------
+struct BatchStep {  // one problem at one global step
+  const void* X;
+  int64_t ldx;
+  const void* Y;
+  int64_t incy;
+  int64_t n;  // rows of this step (0: the problem is idle)
+  double scale;
+  const double* beta;
+  const double* beta_prev;
+  double* beta_next;
+  int ntiles;
+  int pad_;
+};
+struct BatchProblem {
+  int d;
+  int lpr;
+  int64_t part_off;  // first partial row of this problem in the pool
+  const double* M;
+  double* beta_out;
+  double mu, eta;
+};
+void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
+                               int B, int total_tiles, int tile_rows, int grid, double* pool,
+                               slse_dtype t, bool vec, int nch, hipStream_t s);
+void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
+                           const double* pool, int* flags, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Test hooks.

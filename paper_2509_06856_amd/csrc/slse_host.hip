@@ -191,7 +191,7 @@ void fill_layout(const SketchShape& s, slse_sketch_layout* L) {
 
 // Reserve every scratch buffer the sketch needs (no kernel launched).
 void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs* srht,
-                    GaussianArgs* ga, GaussianArgs* gh) {
+                    GaussianArgs* ga, GaussianArgs* gh, bool gauss_bf16 = false) {
   if (s.kind == SLSE_SRHT) {
     srht->t = t;
     srht->N = s.N;
@@ -210,6 +210,7 @@ void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs*
       g->t = t;
       g->N = s.N;
       g->d = (int)s.d;
+      g->bf16 = gauss_bf16;
     }
     ga->m = s.m[s.K - 1];
     ga->stream_id = 7;
@@ -555,7 +556,9 @@ SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params*
   pl.ldah = pl.lda;
   pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
   pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
-  reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh);
+  // a Gaussian sketch of FP32 data in the mixed form runs on the matrix cores (BF16 operands)
+  reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh,
+                 q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN);
   pl.f = reserve_factor(ctx, pl.sk.r, p->d, q->factor);
   pl.it = reserve_iter(ctx, p->d, "it");
   return pl;
@@ -750,7 +753,8 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     pl.lda = pl.ldah = round_up(p->d + 1, 16 / (int64_t)es);
     pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
     pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
-    reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh);
+    reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh,
+                   q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN);
   }
   IterBufs ib = reserve_iter(ctx, p->d, "adj");
   double* lam0 = ctx->arena.get_t<double>("adj_lam0", d);
@@ -820,6 +824,396 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     rep->stage2_steps = q->s_max;
   }
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: per-problem sketches and factors, then every M-IHS step of
+// every problem in two launches per global step.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  int B = 0;
+  slse_dtype t = SLSE_F32;
+  std::vector<SketchShape> sk;
+  std::vector<int64_t> lda, a_off, ah_off, m_off, beta_off, part_off, max_tiles;
+  std::vector<int> steps_of;  // total steps of each problem
+  int T = 0;                  // global steps (max over problems)
+  int tile_rows = 2048;
+  int grid = 512;
+  bool vec = true;
+  int nch = 4;
+  char* Apool = nullptr;
+  char* Ahpool = nullptr;
+  double* Mpool = nullptr;
+  double* Bpool = nullptr;  // 3 beta buffers per problem
+  double* part = nullptr;
+  int* flags = nullptr;     // per problem: non-finite
+  int* finfo = nullptr;     // per problem: 2 ints of factor info
+  BatchStep* d_steps = nullptr;
+  int* d_prefix = nullptr;
+  BatchProblem* d_probs = nullptr;
+  std::vector<BatchStep> h_steps;
+  std::vector<int> h_prefix;
+  std::vector<int> h_total;
+  std::vector<BatchProblem> h_probs;
+  SrhtArgs srht;
+  GaussianArgs ga, gh;
+  FactorBufs f;
+};
+
+int batch_lpr(int d, bool vec, slse_dtype t) {
+  const int v = vec ? 16 / (int)dtype_size(t) : 1;
+  const int nvec = (int)ceil_div(d, v);
+  int lpr = 1;
+  while (lpr < 64 && lpr * 4 < nvec) lpr *= 2;
+  return lpr;
+}
+
+// Per-(step, problem) descriptors and tile prefix sums for a tile size.
+void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params* qs,
+                        double* const* betas) {
+  const int B = bp.B;
+  bp.h_steps.assign((size_t)bp.T * B, BatchStep{});
+  bp.h_prefix.assign((size_t)bp.T * (B + 1), 0);
+  bp.h_total.assign(bp.T, 0);
+  bp.max_tiles.assign(B, 0);
+  for (int b = 0; b < B; ++b) {
+    const SketchShape& sk = bp.sk[b];
+    const int d = (int)ps[b].d;
+    const size_t es = dtype_size(bp.t);
+    double* ring[3] = {bp.Bpool + bp.beta_off[b], bp.Bpool + bp.beta_off[b] + d,
+                       bp.Bpool + bp.beta_off[b] + 2 * d};
+    int cur = 0, prev = 0, t = 0;
+    auto add = [&](const void* X, int64_t ldx, const void* Y, int64_t incy, int64_t n,
+                   double scale) {
+      const int next = (cur + 1) % 3 == prev ? (cur + 2) % 3 : (cur + 1) % 3;
+      BatchStep& st = bp.h_steps[(size_t)t * B + b];
+      st.X = X;
+      st.ldx = ldx;
+      st.Y = Y;
+      st.incy = incy;
+      st.n = n;
+      st.scale = scale;
+      st.beta = ring[cur];
+      st.beta_prev = ring[prev];
+      st.beta_next = ring[next];
+      st.ntiles = (int)ceil_div(n, bp.tile_rows);
+      bp.max_tiles[b] = std::max<int64_t>(bp.max_tiles[b], st.ntiles);
+      prev = cur;
+      cur = next;
+      ++t;
+    };
+    for (int i = 0; i < sk.K; ++i) {
+      if (qs[b].momentum_reset) prev = cur;
+      const char* base = bp.Apool + bp.a_off[b] + (size_t)sk.offset[i] * bp.lda[b] * es;
+      for (int j = 0; j < qs[b].a[i]; ++j)
+        add(base, bp.lda[b], base + (size_t)d * es, bp.lda[b], sk.m[i], sk.scale[i]);
+    }
+    if (qs[b].momentum_reset) prev = cur;
+    for (int j = 0; j < qs[b].s_max; ++j) add(ps[b].X, ps[b].ldx, ps[b].Y, 1, ps[b].N, 1.0);
+    (void)betas;
+  }
+  for (int t = 0; t < bp.T; ++t) {
+    int acc = 0;
+    for (int b = 0; b < B; ++b) {
+      bp.h_prefix[(size_t)t * (B + 1) + b] = acc;
+      acc += bp.h_steps[(size_t)t * B + b].ntiles;
+    }
+    bp.h_prefix[(size_t)t * (B + 1) + B] = acc;
+    bp.h_total[t] = acc;
+  }
+}
+
+void enqueue_batch_steps(const BatchPlan& bp, hipStream_t st) {
+  for (int t = 0; t < bp.T; ++t) {
+    launch_batched_resid_grad(bp.d_steps + (size_t)t * bp.B, bp.d_probs,
+                              bp.d_prefix + (size_t)t * (bp.B + 1), bp.B, bp.h_total[t],
+                              bp.tile_rows, bp.grid, bp.part, bp.t, bp.vec, bp.nch, st);
+    launch_batched_update(bp.d_steps + (size_t)t * bp.B, bp.d_probs, bp.B, bp.part, bp.flags, st);
+  }
+}
+
+void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_params* qs,
+                   double* const* betas, hipStream_t st) {
+  const size_t es = dtype_size(bp.t);
+  launch_fill_i32(bp.flags, 0, bp.B, st);
+  launch_fill_i32(bp.finfo, 0, 2 * (int64_t)bp.B, st);
+  for (int b = 0; b < bp.B; ++b) {
+    const SketchShape& sk = bp.sk[b];
+    const int d = (int)ps[b].d;
+    SrhtArgs sa = bp.srht;
+    if (sk.kind == SLSE_SRHT) {
+      sa.N = sk.N;
+      sa.d = d;
+      sa.p = sk.p;
+      sa.mK = sk.m[sk.K - 1];
+      sa.r = sk.r;
+      srht_plan(sa, 0);
+    }
+    GaussianArgs ga = bp.ga, gh = bp.gh;
+    ga.N = gh.N = sk.N;
+    ga.d = gh.d = d;
+    ga.m = sk.m[sk.K - 1];
+    gh.m = sk.r;
+    ga.bf16 = gh.bf16 = qs[b].precision == SLSE_PREC_MIXED && bp.t == SLSE_F32;
+    if (sk.kind == SLSE_GAUSSIAN) {
+      gaussian_plan(ga);
+      gaussian_plan(gh);
+    }
+    void* A = bp.Apool + bp.a_off[b];
+    void* Ah = bp.Ahpool + bp.ah_off[b];
+    enqueue_sketch(sk, qs[b].seed, ps[b].X, ps[b].ldx, ps[b].Y, bp.t, A, bp.lda[b], Ah, bp.lda[b],
+                   sa, ga, gh, st);
+    FactorBufs f = bp.f;
+    f.info = bp.finfo + 2 * b;
+    enqueue_factor(f, sk.r, d, Ah, bp.lda[b], bp.t, sk.hat_scale, qs[b].factor, st);
+    launch_copy_f64(f.M, bp.Mpool + bp.m_off[b], (int64_t)d * d, st);
+    double* b0 = bp.Bpool + bp.beta_off[b];
+    if (qs[b].beta0)
+      launch_copy_f64(qs[b].beta0, b0, d, st);
+    else
+      launch_fill_f64(b0, 0.0, d, st);
+    launch_copy_f64(b0, betas[b], d, st);
+  }
+  enqueue_batch_steps(bp, st);
+}
+
+slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const slse_params* qs,
+                         double* const* betas, slse_report* reps, hipStream_t st) {
+  BatchPlan bp;
+  bp.B = B;
+  bp.t = ps[0].dtype;
+  for (int b = 0; b < B; ++b) {
+    check_params(&ps[b], &qs[b]);
+    require(betas[b] != nullptr, "null beta pointer in the batch");
+    require(ps[b].dtype == bp.t, "every problem of a batch must share one storage dtype");
+    require(ps[b].d <= 512, "batched problems need d <= 512");
+  }
+  ctx->arena.grew = false;
+  const size_t es = dtype_size(bp.t);
+  const int64_t align = 16 / (int64_t)es;
+  int64_t a_bytes = 0, ah_bytes = 0, m_n = 0, beta_n = 0, max_npad = 0, max_rows = 0, max_d = 0;
+  int64_t max_r = 0;
+  size_t z_bytes = 0, g_bytes = 0;
+  bp.vec = true;
+  for (int b = 0; b < B; ++b) {
+    bp.sk.push_back(make_sketch_shape(qs[b].kind, ps[b].N, ps[b].d, qs[b].m, qs[b].K, qs[b].r));
+    const SketchShape& sk = bp.sk.back();
+    const int64_t d = ps[b].d;
+    const int64_t lda = round_up(d + 1, align);
+    bp.lda.push_back(lda);
+    bp.a_off.push_back(a_bytes);
+    a_bytes += round_up((int64_t)(sk.rows_A * lda * es), 256);
+    bp.ah_off.push_back(ah_bytes);
+    ah_bytes += round_up((int64_t)(sk.r * lda * es), 256);
+    bp.m_off.push_back(m_n);
+    m_n += d * d;
+    bp.beta_off.push_back(beta_n);
+    beta_n += 3 * d;
+    max_npad = std::max(max_npad, sk.n_pad);
+    max_r = std::max(max_r, sk.r);
+    max_d = std::max(max_d, d);
+    max_rows = std::max(max_rows, std::max<int64_t>(sk.rows_A, ps[b].N));
+    if (sk.kind == SLSE_SRHT) {
+      SrhtArgs sa;
+      sa.t = bp.t;
+      sa.d = (int)d;
+      sa.p = sk.p;
+      srht_plan(sa, 0);
+      z_bytes = std::max(z_bytes, srht_z_bytes(sa));
+    } else if (sk.kind == SLSE_GAUSSIAN) {
+      GaussianArgs g1, g2;
+      g1.t = g2.t = bp.t;
+      g1.bf16 = g2.bf16 = qs[b].precision == SLSE_PREC_MIXED && bp.t == SLSE_F32;
+      g1.N = g2.N = sk.N;
+      g1.d = g2.d = (int)d;
+      g1.m = sk.m[sk.K - 1];
+      g2.m = sk.r;
+      gaussian_plan(g1);
+      gaussian_plan(g2);
+      g_bytes = std::max({g_bytes, gaussian_scratch_bytes(g1), gaussian_scratch_bytes(g2)});
+    }
+    const int es_i = (int)es;
+    if ((reinterpret_cast<uintptr_t>(ps[b].X) % 16) || ((ps[b].ldx * es_i) % 16)) bp.vec = false;
+  }
+  bp.Apool = static_cast<char*>(ctx->arena.get("bA", (size_t)a_bytes));
+  bp.Ahpool = static_cast<char*>(ctx->arena.get("bAhat", (size_t)ah_bytes));
+  bp.Mpool = ctx->arena.get_t<double>("bM", (size_t)m_n);
+  bp.Bpool = ctx->arena.get_t<double>("bBeta", (size_t)beta_n);
+  bp.flags = ctx->arena.get_t<int>("bFlags", (size_t)B);
+  bp.finfo = ctx->arena.get_t<int>("bInfo", (size_t)2 * B);
+  bp.srht.pi_sgn = ctx->arena.get_t<int32_t>("srht_pi", (size_t)max_npad);
+  bp.srht.slotA = ctx->arena.get_t<int32_t>("srht_slotA", (size_t)max_npad);
+  bp.srht.slotH = ctx->arena.get_t<int32_t>("srht_slotH", (size_t)max_npad);
+  bp.srht.Z = z_bytes ? ctx->arena.get("srht_Z", z_bytes) : nullptr;
+  bp.srht.t = bp.t;
+  bp.ga.t = bp.gh.t = bp.t;
+  bp.ga.stream_id = 7;
+  bp.gh.stream_id = 8;
+  if (g_bytes) {
+    void* gp = ctx->arena.get("gauss_part", g_bytes);
+    bp.ga.partial = bp.gh.partial = static_cast<float*>(gp);
+    bp.ga.partial64 = bp.gh.partial64 = static_cast<double*>(gp);
+  }
+  slse_factor_method fm = SLSE_FACTOR_CHOL;
+  for (int b = 0; b < B; ++b)
+    if (qs[b].factor == SLSE_FACTOR_QR) fm = SLSE_FACTOR_QR;
+  bp.f = reserve_factor(ctx, max_r, max_d, fm);
+  // steps of every problem
+  for (int b = 0; b < B; ++b) {
+    int T = qs[b].s_max;
+    for (int i = 0; i < qs[b].K; ++i) T += qs[b].a[i];
+    bp.steps_of.push_back(T);
+    bp.T = std::max(bp.T, T);
+  }
+  // lane groups and chunk count (one kernel shape for the whole batch)
+  bp.h_probs.resize(B);
+  int nch = 1;
+  for (int b = 0; b < B; ++b) {
+    const int d = (int)ps[b].d;
+    const int lpr = batch_lpr(d, bp.vec, bp.t);
+    const int v = bp.vec ? 16 / (int)es : 1;
+    int c = (int)ceil_div(ceil_div(d, v), lpr);
+    int p2 = 1;
+    while (p2 < c) p2 *= 2;
+    require(p2 <= 4, "batched: d too large for the batched kernel");
+    nch = std::max(nch, p2);
+    BatchProblem& pr = bp.h_probs[b];
+    pr.d = d;
+    pr.lpr = lpr;
+    pr.M = bp.Mpool + bp.m_off[b];
+    pr.beta_out = betas[b];
+    const double eta = qs[b].eta, mu = qs[b].mu;
+    pr.mu = mu;
+    pr.eta = eta;
+  }
+  bp.nch = nch;
+  // tile size and grid: autotuned once per batch shape on a stage-2 step
+  int64_t rows_total = 0;
+  for (int b = 0; b < B; ++b) rows_total += ps[b].N;
+  const std::string key = "batched/" + std::to_string(B) + "/" + std::to_string(rows_total) + "/" +
+                          std::to_string((int)bp.t);
+  bool tuned = false;
+  if (auto it = ctx->rg_tune.find(key); it != ctx->rg_tune.end()) {
+    bp.grid = it->second.first;
+    bp.tile_rows = it->second.second;
+    tuned = true;
+  } else {
+    bp.grid = 2 * ctx->num_cus;
+    bp.tile_rows = 2048;
+  }
+  // partial pool sized for the smallest tile any tuning candidate may use
+  int64_t part_n = 0;
+  for (int b = 0; b < B; ++b) {
+    bp.part_off.push_back(part_n);
+    part_n += ceil_div(std::max<int64_t>(bp.sk[b].rows_A, ps[b].N), 1024) * (ps[b].d + 1);
+  }
+  bp.part = ctx->arena.get_t<double>("bPart", (size_t)part_n + 1);
+  bp.d_steps = ctx->arena.get_t<BatchStep>("bSteps", (size_t)bp.T * B);
+  bp.d_prefix = ctx->arena.get_t<int>("bPrefix", (size_t)bp.T * (B + 1));
+  bp.d_probs = ctx->arena.get_t<BatchProblem>("bProbs", (size_t)B);
+  for (int b = 0; b < B; ++b) bp.h_probs[b].part_off = bp.part_off[b];
+  if (ctx->arena.grew) ctx->drop_graphs();
+  SLSE_HIP(hipMemcpy(bp.d_probs, bp.h_probs.data(), sizeof(BatchProblem) * B, hipMemcpyHostToDevice));
+
+  auto upload = [&]() {
+    build_batch_tables(bp, ps, qs, betas);
+    SLSE_HIP(hipMemcpy(bp.d_steps, bp.h_steps.data(), sizeof(BatchStep) * bp.h_steps.size(),
+                       hipMemcpyHostToDevice));
+    SLSE_HIP(hipMemcpy(bp.d_prefix, bp.h_prefix.data(), sizeof(int) * bp.h_prefix.size(),
+                       hipMemcpyHostToDevice));
+  };
+  if (!tuned && bp.T > 0) {
+    // time the step with the most tiles for a few (tile, grid) shapes
+    const char* env = std::getenv("SLSE_AUTOTUNE");
+    const bool do_tune = !(env && std::atoi(env) == 0);
+    std::pair<int, int> best{bp.grid, bp.tile_rows};
+    if (do_tune) {
+      hipEvent_t e0, e1;
+      SLSE_HIP(hipEventCreate(&e0));
+      SLSE_HIP(hipEventCreate(&e1));
+      float best_ms = 1e30f;
+      for (int tr : {1024, 2048, 4096, 8192}) {
+        bp.tile_rows = tr;
+        upload();
+        const int tmax = (int)(std::max_element(bp.h_total.begin(), bp.h_total.end()) -
+                               bp.h_total.begin());
+        for (int g : {ctx->num_cus, 2 * ctx->num_cus, 4 * ctx->num_cus}) {
+          auto run = [&]() {
+            launch_batched_resid_grad(bp.d_steps + (size_t)tmax * B, bp.d_probs,
+                                      bp.d_prefix + (size_t)tmax * (B + 1), B, bp.h_total[tmax],
+                                      tr, g, bp.part, bp.t, bp.vec, bp.nch, st);
+          };
+          run();
+          SLSE_HIP(hipEventRecord(e0, st));
+          for (int r = 0; r < 3; ++r) run();
+          SLSE_HIP(hipEventRecord(e1, st));
+          SLSE_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = {g, tr};
+          }
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    ctx->rg_tune[key] = best;
+    bp.grid = best.first;
+    bp.tile_rows = best.second;
+  }
+  upload();
+  // one graph for the whole batch (sketches, factors, every step)
+  std::string gk = key;
+  auto add_key = [&gk](const void* v, size_t n) { gk.append(static_cast<const char*>(v), n); };
+  for (int b = 0; b < B; ++b) {
+    add_key(&ps[b], sizeof(slse_problem));
+    add_key(&qs[b], sizeof(slse_params));
+    add_key(&betas[b], sizeof(double*));
+  }
+  auto itg = ctx->graphs.find(gk);
+  if (itg == ctx->graphs.end()) {
+    hipGraph_t g = nullptr;
+    SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_batch(bp, ps, qs, betas, ctx->capture_stream);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(ctx->capture_stream, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    SLSE_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
+    hipGraphExec_t ge = nullptr;
+    SLSE_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    SLSE_HIP(hipGraphDestroy(g));
+    itg = ctx->graphs.emplace(gk, ge).first;
+  }
+  SLSE_HIP(hipGraphLaunch(itg->second, st));
+  ctx->pre.valid = false;
+  slse_status worst = SLSE_OK;
+  if (reps) {
+    std::vector<int> flags(B), info(2 * B);
+    SLSE_HIP(hipMemcpyAsync(flags.data(), bp.flags, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipMemcpyAsync(info.data(), bp.finfo, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+      slse_status sb = SLSE_OK;
+      if (info[2 * b] || info[2 * b + 1])
+        sb = SLSE_ESINGULAR;
+      else if (flags[b])
+        sb = SLSE_ENONFINITE;
+      std::memset(&reps[b], 0, sizeof(slse_report));
+      reps[b].status = sb;
+      int s1 = 0;
+      for (int i = 0; i < qs[b].K; ++i) s1 += qs[b].a[i];
+      reps[b].stage1_steps = s1;
+      reps[b].stage2_steps = qs[b].s_max;
+      if (sb < worst) worst = sb;
+    }
+  }
+  return worst;
 }
 
 template <typename F>
@@ -902,13 +1296,16 @@ slse_status slse_sketch_apply(slse_ctx* ctx, slse_sketch_kind kind, uint64_t see
     require(X && Y && A && Ahat, "null pointer");
     require(ldx >= d && lda >= d + 1 && ldah >= d + 1, "leading dimension too small");
     require(in_t == SLSE_F32 || in_t == SLSE_F64, "in dtype must be F32 or F64");
-    if (out_t != in_t) fail(SLSE_EUNSUPPORTED, "out dtype must equal in dtype in this build");
+    const bool bf16 = out_t == SLSE_BF16;
+    if (bf16 && !(kind == SLSE_GAUSSIAN && in_t == SLSE_F32))
+      fail(SLSE_EUNSUPPORTED, "BF16 products are offered for the Gaussian sketch of F32 data");
+    if (!bf16 && out_t != in_t) fail(SLSE_EUNSUPPORTED, "out dtype must equal in dtype in this build");
     DeviceGuard g(ctx->device);
     SketchShape s = make_sketch_shape(kind, N, d, m, K, r);
     SrhtArgs srht;
     GaussianArgs ga, gh;
     ctx->arena.grew = false;
-    reserve_sketch(ctx, s, in_t, &srht, &ga, &gh);
+    reserve_sketch(ctx, s, in_t, &srht, &ga, &gh, bf16);
     if (ctx->arena.grew) ctx->drop_graphs();
     ctx->pre.valid = false;
     enqueue_sketch(s, seed, X, ldx, Y, in_t, A, lda, Ahat, ldah, srht, ga, gh, as_stream(stream));
@@ -1023,7 +1420,9 @@ slse_status slse_solve_batched(slse_ctx* ctx, int32_t B, const slse_problem* ps,
   return guarded([&]() -> slse_status {
     require(ctx != nullptr, "null ctx");
     require(B >= 0 && (B == 0 || (ps && qs && betas)), "bad batch arguments");
-    fail(SLSE_EUNSUPPORTED, "batched solve not built yet");
+    if (B == 0) return SLSE_OK;
+    DeviceGuard g(ctx->device);
+    return batched_impl(ctx, B, ps, qs, betas, reps, as_stream(stream));
   });
 }
 

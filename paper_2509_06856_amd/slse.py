@@ -170,8 +170,12 @@ def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True)
     return beta, info
 
 
-def sketch_apply(X, Y, kind, seed, m, r, ctx=None):
-    """slse_sketch_apply: returns (A, Ahat, layout dict)."""
+def sketch_apply(X, Y, kind, seed, m, r, ctx=None, bf16=False):
+    """slse_sketch_apply: returns (A, Ahat, layout dict).
+
+    bf16=True asks for the Gaussian sketch of FP32 data on the matrix cores
+    (BF16 operands, FP32 accumulation); A and Ahat are FP32.
+    """
     ctx = ctx or default_context(X.device.index)
     p = _problem(X, Y)
     N, d = X.shape
@@ -183,9 +187,10 @@ def sketch_apply(X, Y, kind, seed, m, r, ctx=None):
     Ah = torch.empty((r, ld), dtype=X.dtype, device=X.device)
     marr = (ctypes.c_int64 * len(mK))(*mK)
     lay = L.slse_sketch_layout()
+    out_t = L.SLSE_BF16 if bf16 else p.dtype
     L.check(ctx.lib.slse_sketch_apply(ctx.h, _KIND[kind], seed, N, d, _ptr(X), p.ldx, _ptr(Y),
                                       p.dtype, marr, len(mK), r, _ptr(A), ld, _ptr(Ah), ld,
-                                      p.dtype, ctypes.byref(lay), _stream(X.device)))
+                                      out_t, ctypes.byref(lay), _stream(X.device)))
     layout = dict(K=lay.K, m=list(lay.m[:lay.K]), offset=list(lay.offset[:lay.K]),
                   scale=list(lay.scale[:lay.K]), rows_A=lay.rows_A, r=lay.r,
                   hat_scale=lay.hat_scale, n_pad=lay.n_pad)
@@ -274,3 +279,29 @@ class SLSEFunction(torch.autograd.Function):
         dX, dY, _ = backward(X, Y, ctx.params, beta, w, want_dX=ctx.needs_input_grad[0],
                              want_dY=ctx.needs_input_grad[1])
         return dX, dY, None
+
+
+def solve_batched(Xs, Ys, params_list, ctx=None, report=True):
+    """slse_solve_batched: returns (list of betas, list of report dicts)."""
+    B = len(Xs)
+    if not (len(Ys) == B == len(params_list)):
+        raise ValueError("Xs, Ys and params_list must have the same length")
+    if B == 0:
+        return [], []
+    ctx = ctx or default_context(Xs[0].device.index)
+    probs = (L.slse_problem * B)()
+    qs = (L.slse_params * B)()
+    betas = []
+    for b in range(B):
+        probs[b] = _problem(Xs[b], Ys[b])
+        qs[b] = params_list[b].to_c(Xs[b].shape[1])
+        betas.append(torch.empty(Xs[b].shape[1], dtype=torch.float64, device=Xs[b].device))
+    ptrs = (ctypes.c_void_p * B)(*[b.data_ptr() for b in betas])
+    reps = (L.slse_report * B)()
+    st = ctx.lib.slse_solve_batched(ctx.h, B, probs, qs, ptrs, reps if report else None,
+                                    _stream(Xs[0].device))
+    if st not in (L.SLSE_OK, L.SLSE_ENOTCONV):
+        L.check(st)
+    infos = [dict(status=L.STATUS_NAMES.get(r.status, r.status), stage1_steps=r.stage1_steps,
+                  stage2_steps=r.stage2_steps) for r in reps] if report else []
+    return betas, infos

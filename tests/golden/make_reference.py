@@ -22,14 +22,35 @@ sys.path.insert(0, ROOT)
 from oracle import ols as O  # noqa: E402
 from oracle import slse as OS  # noqa: E402
 from scipy.linalg import solve_triangular  # noqa: E402
-from slse_inputs import fingerprint, make_problem  # noqa: E402
+from slse_inputs import fingerprint, make_batched, make_problem  # noqa: E402
 from slse_inputs.generators import loss_vector  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def batched():
+    t0 = time.time()
+    probs = make_batched()
+    out = dict(workload="batched",
+               provenance="written by tests/golden/make_reference.py from oracle.ols.ols_refined",
+               problems=[])
+    for p in probs:
+        bstar, bqr, _ = O.ols_refined(p.X, p.Y)
+        out["problems"].append(dict(N=int(p.n), d=int(p.d), fingerprint=fingerprint(p.X, p.Y),
+                                    beta_star=[float(v) for v in bstar],
+                                    fp64_floor=OS.rel_err(bqr, bstar)))
+    out["seconds"] = time.time() - t0
+    path = os.path.join(HERE, "ref_batched.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"batched: {len(probs)} problems, {out['seconds']:.0f}s -> {path}", flush=True)
+
+
 def main(names):
     for name in names:
+        if name == "batched":
+            batched()
+            continue
         t0 = time.time()
         p = make_problem(name)
         t1 = time.time()

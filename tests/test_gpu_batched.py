@@ -1,0 +1,78 @@
+"""GPU parity of the batched solve (slse_solve_batched) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ols as O
+from oracle import slse as OS
+from slse_inputs import make_batched, make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_06856_amd import slse
+
+    return slse
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _params(G, n, d, seed, s_max, kind="srht", precision="f64"):
+    m = G.paper_schedule(n, d)
+    return G.Params(kind=kind, seed=seed, m=m, a=[2] * len(m), r=6 * d, s_max=s_max,
+                    precision=precision)
+
+
+def test_batched_f64_matches_oracle_iteration(G):
+    shapes = [(5000, 8), (20000, 16), (3000, 24), (70000, 32), (9000, 5)]
+    Xs, Ys, ps, refs = [], [], [], []
+    for k, (n, d) in enumerate(shapes):
+        p = make_problem("plain_small", n=n, d=d, seed=77 + k)
+        prm = _params(G, n, d, 500 + k, s_max=12)
+        Xs.append(dev(p.X))
+        Ys.append(dev(p.Y))
+        ps.append(prm)
+        beta, _, _ = OS.slse_frs(p.X, p.Y, prm.seed, "srht", prm.m, prm.a, prm.r, s=12)
+        refs.append(beta)
+    betas, infos = G.solve_batched(Xs, Ys, ps)
+    for b in range(len(shapes)):
+        assert infos[b]["status"] == "SLSE_OK"
+        assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-12, b
+
+
+def test_batched_equals_single_solves(G):
+    shapes = [(6000, 16), (11000, 8)]
+    Xs, Ys, ps, singles = [], [], [], []
+    for k, (n, d) in enumerate(shapes):
+        p = make_problem("plain_small", n=n, d=d, seed=9 + k)
+        prm = _params(G, n, d, 40 + k, s_max=10)
+        Xs.append(dev(p.X))
+        Ys.append(dev(p.Y))
+        ps.append(prm)
+        b, _ = G.solve(Xs[-1], Ys[-1], prm)
+        singles.append(b.cpu().numpy())
+    betas, _ = G.solve_batched(Xs, Ys, ps)
+    for b in range(len(shapes)):
+        assert OS.rel_err(betas[b].cpu().numpy(), singles[b]) < 1e-13
+
+
+def test_batched_workload_sample_reaches_ols(G):
+    probs = make_batched(count=6, n_range=(1 << 14, 1 << 15))
+    Xs = [dev(p.X) for p in probs]
+    Ys = [dev(p.Y) for p in probs]
+    # heavy-tailed rows converge more slowly for some problems (the oracle
+    # iteration needs ~40 stage-2 steps for 1e-10 on problem 2 of this sample)
+    ps = [_params(G, p.n, p.d, 2000 + i, s_max=45, precision="mixed") for i, p in enumerate(probs)]
+    for replay in range(3):
+        betas, infos = G.solve_batched(Xs, Ys, ps)
+        torch.cuda.synchronize()
+        for b, p in enumerate(probs):
+            bstar, _, _ = O.ols_refined(p.X, p.Y)
+            assert infos[b]["status"] == "SLSE_OK"
+            assert OS.rel_err(betas[b].cpu().numpy(), bstar) < 1e-10, (replay, b)

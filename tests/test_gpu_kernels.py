@@ -225,6 +225,29 @@ def test_gaussian_sketch_parity(G, dtype):
     assert np.all(np.abs(Ah.cpu().numpy() - ref["Ahat"]) <= tol)
 
 
+def test_gaussian_sketch_bf16_mfma_parity(G):
+    # BF16 operands (G and [X|Y] rounded to nearest even), FP32 accumulation on
+    # the matrix cores; compared with the oracle on the same rounded operands
+    N, d = 3000, 37
+    g = np.random.default_rng(6)
+    X = g.standard_normal((N, d)).astype(np.float32)
+    Y = g.standard_normal(N).astype(np.float32)
+    m, r = [32, 200], 130
+    A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "gaussian", 88, m, r, bf16=True)
+    Xb = S.round_to(X, "bf16")
+    Yb = S.round_to(Y, "bf16")
+    ref = S.gaussian(Xb, Yb, 88, m, r, g_round="bf16")
+    W = np.abs(S.joint(Xb, Yb))
+    for out, stream, rows in ((A, R.STREAM_G, 200), (Ah, R.STREAM_GHAT, r)):
+        Gabs = np.abs(R.gaussian_block(88, stream, np.arange(rows), np.arange(N)))
+        bound = Gabs @ W
+        # FP32 accumulation (N terms) plus rare one-ulp BF16 flips of G entries
+        # whose FP32 and FP64 Box-Muller values straddle a rounding boundary
+        tol = (N * U32 + 2.0 ** -7 * 0.01) * bound + 1e-6
+        want = ref["A"] if stream == R.STREAM_G else ref["Ahat"]
+        assert np.all(np.abs(out.cpu().numpy() - want) <= tol)
+
+
 # ---------------------------------------------------------------------------
 # factorization
 # ---------------------------------------------------------------------------
