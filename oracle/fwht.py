@@ -37,13 +37,10 @@ def hadamard_dense(n):
     return np.where(pop % 2 == 0, 1.0, -1.0)
 
 
-def hadamard_rows(rows, n):
-    """Rows `rows` of H_n (popcount formula), as a float64 [len(rows), n] array."""
+def hadamard_rows(rows, n, cols=None):
+    """Entries H_n[rows, cols] (popcount formula) as a float64 array; all n
+    columns when `cols` is None."""
     j = np.asarray(rows, dtype=np.int64)[:, None]
-    k = np.arange(n, dtype=np.int64)[None, :]
-    bits = j & k
-    pop = np.zeros(bits.shape, dtype=np.int64)
-    while np.any(bits):
-        pop += bits & 1
-        bits >>= 1
+    k = (np.arange(n, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64))[None, :]
+    pop = np.bitwise_count(j & k)
     return np.where(pop % 2 == 0, 1.0, -1.0)

@@ -97,7 +97,7 @@ def srht_rows(X, Y, seed, rows):
         V = np.zeros((len(k), W.shape[1]))
         V[ok] = W[src[ok]]
         V *= D[k][:, None]
-        Hs = hadamard_rows(rows, n_pad)[:, k0:k0 + len(k)]
+        Hs = hadamard_rows(rows, n_pad, k)
         out += Hs @ V
     return out
 

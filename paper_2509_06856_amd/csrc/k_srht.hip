@@ -26,7 +26,6 @@
 namespace slse {
 namespace {
 
-constexpr int kPassThreads = 512;
 enum { kFirst = 1, kLast = 2 };
 
 template <typename T>
@@ -47,33 +46,58 @@ struct PassParams {
   int64_t ldah;
   int s0;
   int n_ct;
+  int64_t xcd_q;  // > 0: blocks [0, 8 xcd_q) are remapped so that each XCD walks a contiguous range
 };
 
-template <typename T, int CT, int BA, int BB, int MODE>
-__global__ __launch_bounds__(kPassThreads) void fwht_pass_kernel(PassParams<T> P) {
+// Threads per block: one phase-A item (a column of 2^BA rows) per thread when
+// the group is small, at most 512 (up to 256 registers per thread).
+template <int CT, int BB, int ROUNDS>
+constexpr int pass_threads() {
+  return (CT << BB) < 64 ? 64 : ((CT << BB) > 512 ? 512 : (CT << BB));
+}
+
+// ROUNDS > 1 exchanges the tile through LDS in ROUNDS slices of the high
+// (phase-A) index, so a group of 2^B rows x CT columns needs only 1/ROUNDS of
+// it in LDS; every thread keeps all its phase-A values in registers meanwhile.
+template <typename T, int CT, int BA, int BB, int MODE, int ROUNDS>
+__global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_kernel(PassParams<T> P) {
+  constexpr int NT = pass_threads<CT, BB, ROUNDS>();
   constexpr int RA = 1 << BA;
   constexpr int RB = 1 << BB;
   constexpr int B = BA + BB;
+  constexpr int RA_R = RA / ROUNDS;                  // phase-B row blocks per round
+  constexpr int NA = RB * CT;                        // phase-A items
+  constexpr int NB = RA_R * CT;                      // phase-B items per round
+  constexpr int IA = (NA + NT - 1) / NT;
+  constexpr int IB = (NB + NT - 1) / NT;
   constexpr int PAD = CT;  // one padded row per 2^BB rows spreads phase-B reads over the banks
-  __shared__ T tile[(1 << B) * CT + RA * PAD];
+  static_assert(RA_R * ROUNDS == RA, "rounds must divide 2^BA");
+  __shared__ T tile[(RA_R << BB) * CT + RA_R * PAD];
 
   // index maps of this group, fetched once (contiguous: the first pass has
   // s0 = 0 and the slot maps are stored in the last pass's group order)
   __shared__ int32_t s_pi[(MODE & kFirst) ? (1 << B) : 1];
   __shared__ int32_t s_slot[(MODE & kLast) ? 2 * (1 << B) : 1];
 
-  const int ct = blockIdx.x % P.n_ct;
-  const int64_t g = blockIdx.x / P.n_ct;
+  // Workgroups are dealt to the 8 XCDs round-robin.  Remapping block b to
+  // (b % 8) q + b / 8 hands each XCD a contiguous run of work items, so the
+  // column tiles of one row group run back to back on the same XCD: the
+  // partial cache lines they write meet in that XCD's L2 and the DRAM pages
+  // of the rows they touch are reused while open.
+  int64_t bid = blockIdx.x;
+  if (P.xcd_q > 0 && bid < 8 * P.xcd_q) bid = (bid & 7) * P.xcd_q + (bid >> 3);
+  const int ct = (int)(bid % P.n_ct);
+  const int64_t g = bid / P.n_ct;
   const int64_t lo = g & ((int64_t(1) << P.s0) - 1);
   const int64_t hi = g >> P.s0;
   const int64_t hi_part = hi << (P.s0 + B);
   const int col_base = ct * CT;
   if constexpr ((MODE & kFirst) != 0) {
-    for (int k = threadIdx.x; k < (1 << B); k += kPassThreads) s_pi[k] = P.pi_sgn[hi_part | k];
+    for (int k = threadIdx.x; k < (1 << B); k += NT) s_pi[k] = P.pi_sgn[hi_part | k];
   }
   if constexpr ((MODE & kLast) != 0) {
     const int64_t gb = g << B;
-    for (int k = threadIdx.x; k < (1 << B); k += kPassThreads) {
+    for (int k = threadIdx.x; k < (1 << B); k += NT) {
       s_slot[k] = P.slotA[gb + k];
       s_slot[(1 << B) + k] = P.slotH[gb + k];
     }
@@ -81,42 +105,55 @@ __global__ __launch_bounds__(kPassThreads) void fwht_pass_kernel(PassParams<T> P
   if constexpr ((MODE & (kFirst | kLast)) != 0) __syncthreads();
 
   // phase A: 2^BA rows {q + k 2^BB} of one column per item; stages on the high BA bits
-  for (int it = threadIdx.x; it < RB * CT; it += kPassThreads) {
+  T v[IA][RA];
+#pragma unroll
+  for (int ia = 0; ia < IA; ++ia) {
+    const int it = ia * NT + threadIdx.x;
+    if (NA % NT != 0 && it >= NA) break;
     const int c = it % CT;
     const int q = it / CT;
     const int col = col_base + c;
-    T v[RA];
     if constexpr ((MODE & kFirst) != 0) {
       // gather through P with D applied; branch-free so that all 2^BA loads
       // are in flight together (out-of-range rows and padding columns read a
       // valid address and are zeroed afterwards)
-      int32_t ps[RA];
-#pragma unroll
-      for (int k = 0; k < RA; ++k) ps[k] = s_pi[q + (k << BB)];
+      // The sign and keep flags of the 2^BA rows are packed into two
+      // per-thread bit masks, so that no per-load state pins registers and
+      // every load is issued before the first one is consumed.
+      static_assert(RA <= 64, "flag masks hold 64 rows");
+      using U = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
+      uint64_t negm = 0, keepm = 0;
+      U raw[RA];
 #pragma unroll
       for (int k = 0; k < RA; ++k) {
-        const bool neg = ps[k] < 0;
-        const int64_t src = neg ? (int64_t)(~ps[k]) : (int64_t)ps[k];
+        const int32_t ps = s_pi[q + (k << BB)];
+        const bool neg = ps < 0;
+        const int64_t src = neg ? (int64_t)(~ps) : (int64_t)ps;
         const bool in_rows = src < P.N;
         const int64_t srow = in_rows ? src : 0;
         // select the address as an integer so that the load stays unconditional
         const uintptr_t ax = reinterpret_cast<uintptr_t>(P.X + srow * P.ldx + col);
         const uintptr_t ay = reinterpret_cast<uintptr_t>(P.Y + srow);
         const T* addr = reinterpret_cast<const T*>(col < P.d ? ax : ay);
-        const T val = __builtin_nontemporal_load(addr);
-        // zero / negate with bit masks: a select here would let the compiler
-        // move the load under a branch and wait for it
-        using U = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
-        const U keep = (in_rows && col <= P.d) ? ~U(0) : U(0);
-        const U sgn = neg ? (U(1) << (8 * sizeof(T) - 1)) : U(0);
-        v[k] = __builtin_bit_cast(T, (U)((__builtin_bit_cast(U, val) ^ sgn) & keep));
+        raw[k] = __builtin_bit_cast(U, __builtin_nontemporal_load(addr));
+        negm |= (uint64_t)neg << k;
+        keepm |= (uint64_t)(in_rows && col <= P.d) << k;
+      }
+      // keep the scheduler from consuming early loads while later ones are
+      // still to be issued (it would cap the loads in flight at a handful)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < RA; ++k) {
+        const U sgn = (U)((negm >> k) & 1) << (8 * sizeof(T) - 1);
+        const U keep = (U)0 - (U)((keepm >> k) & 1);
+        v[ia][k] = __builtin_bit_cast(T, (U)((raw[k] ^ sgn) & keep));
       }
     } else {
 #pragma unroll
       for (int k = 0; k < RA; ++k) {
         const int64_t pos = q + (k << BB);
         const int64_t j = hi_part | (pos << P.s0) | lo;
-        v[k] = __builtin_nontemporal_load(P.Z + j * P.ldz + col);
+        v[ia][k] = __builtin_nontemporal_load(P.Z + j * P.ldz + col);
       }
     }
 #pragma unroll
@@ -124,54 +161,67 @@ __global__ __launch_bounds__(kPassThreads) void fwht_pass_kernel(PassParams<T> P
 #pragma unroll
       for (int k = 0; k < RA; ++k)
         if ((k & h) == 0) {
-          const T a0 = v[k], a1 = v[k + h];
-          v[k] = a0 + a1;
-          v[k + h] = a0 - a1;
+          const T a0 = v[ia][k], a1 = v[ia][k + h];
+          v[ia][k] = a0 + a1;
+          v[ia][k + h] = a0 - a1;
         }
-#pragma unroll
-    for (int k = 0; k < RA; ++k) tile[(q + (k << BB)) * CT + c + k * PAD] = v[k];
   }
-  __syncthreads();
 
-  // phase B: 2^BB consecutive rows {qq 2^BB + k} per item; stages on the low BB bits
-  for (int it = threadIdx.x; it < RA * CT; it += kPassThreads) {
-    const int c = it % CT;
-    const int qq = it / CT;
-    const int col = col_base + c;
-    T v[RB];
-    int32_t sa[RB], sh[RB];
-    if constexpr ((MODE & kLast) != 0) {
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        sa[k] = s_slot[(qq << BB) + k];
-        sh[k] = s_slot[(1 << B) + (qq << BB) + k];
-      }
+  for (int rho = 0; rho < ROUNDS; ++rho) {
+    if (rho > 0) __syncthreads();  // the previous round's phase-B reads are done
+    // rows q + k 2^BB with k in this round's slice go to LDS (local k)
+#pragma unroll
+    for (int ia = 0; ia < IA; ++ia) {
+      const int it = ia * NT + threadIdx.x;
+      if (NA % NT != 0 && it >= NA) break;
+      const int c = it % CT;
+      const int q = it / CT;
+#pragma unroll
+      for (int kl = 0; kl < RA_R; ++kl)
+        tile[(q + (kl << BB)) * CT + c + kl * PAD] = v[ia][rho * RA_R + kl];
     }
+    __syncthreads();
+
+    // phase B: 2^BB consecutive rows {qq 2^BB + k} per item; stages on the low BB bits
 #pragma unroll
-    for (int k = 0; k < RB; ++k) v[k] = tile[((qq << BB) + k) * CT + c + qq * PAD];
+    for (int ib = 0; ib < IB; ++ib) {
+      const int it = ib * NT + threadIdx.x;
+      if (NB % NT != 0 && it >= NB) break;
+      const int c = it % CT;
+      const int ql = it / CT;
+      const int qq = rho * RA_R + ql;
+      const int col = col_base + c;
+      T w[RB];
 #pragma unroll
-    for (int h = 1; h < RB; h <<= 1)
+      for (int k = 0; k < RB; ++k) w[k] = tile[((ql << BB) + k) * CT + c + ql * PAD];
 #pragma unroll
-      for (int k = 0; k < RB; ++k)
-        if ((k & h) == 0) {
-          const T a0 = v[k], a1 = v[k + h];
-          v[k] = a0 + a1;
-          v[k + h] = a0 - a1;
+      for (int h = 1; h < RB; h <<= 1)
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+          if ((k & h) == 0) {
+            const T a0 = w[k], a1 = w[k + h];
+            w[k] = a0 + a1;
+            w[k + h] = a0 - a1;
+          }
+      if constexpr ((MODE & kLast) != 0) {
+        if (col <= P.d) {
+          // slots are read from LDS at the store, not held in registers
+#pragma unroll
+          for (int k = 0; k < RB; ++k) {
+            const int32_t sa = s_slot[(qq << BB) + k];
+            const int32_t sh = s_slot[(1 << B) + (qq << BB) + k];
+            if (sa >= 0) __builtin_nontemporal_store(w[k], P.A + (int64_t)sa * P.lda + col);
+            if (sh >= 0) P.Ahat[(int64_t)sh * P.ldah + col] = w[k];
+          }
         }
-    if constexpr ((MODE & kLast) != 0) {
-      if (col <= P.d) {
+      } else {
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
-          if (sa[k] >= 0) __builtin_nontemporal_store(v[k], P.A + (int64_t)sa[k] * P.lda + col);
-          if (sh[k] >= 0) P.Ahat[(int64_t)sh[k] * P.ldah + col] = v[k];
+          const int64_t pos = ((int64_t)qq << BB) + k;
+          const int64_t j = hi_part | (pos << P.s0) | lo;
+          __builtin_nontemporal_store(w[k], P.Z + j * P.ldz + col);
         }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        const int64_t pos = ((int64_t)qq << BB) + k;
-        const int64_t j = hi_part | (pos << P.s0) | lo;
-        __builtin_nontemporal_store(v[k], P.Z + j * P.ldz + col);
       }
     }
   }
@@ -211,35 +261,33 @@ __global__ void srht_hat_kernel(int64_t r, int p, uint64_t seed, int s0_last, in
 }
 
 template <typename T>
-constexpr int ct_max() {
-  return 128 / (int)sizeof(T);
+constexpr int ct_of() {
+  return 128 / (int)sizeof(T);  // 128-byte row segments
 }
 
-// Column tile: 128 B row segments while the tile fits 128 KB of LDS; the
-// narrow variant halves the tile so that two blocks share a CU.
-template <typename T, bool NARROW>
-constexpr int ct_for(int b) {
-  return (b <= 10 ? ct_max<T>() : ct_max<T>() / 2) / (NARROW ? 2 : 1);
-}
-
-template <typename T, int B, int MODE, bool NARROW>
+// Passes of up to 10 stages exchange the whole 2^B x CT tile through LDS at
+// once (128 KB at B = 10); an 11-stage pass does it in two rounds.
+template <typename T, int B, int MODE>
 void launch_pass(PassParams<T> P, int64_t npad, hipStream_t s) {
   constexpr int BA = (B + 1) / 2;
   constexpr int BB = B / 2;
-  constexpr int CT = ct_for<T, NARROW>(B);
+  constexpr int CT = ct_of<T>();
+  constexpr int ROUNDS = B > 10 ? 2 : 1;
   const int64_t groups = npad >> B;
   P.n_ct = (int)(P.ldz / CT);
   const int64_t blocks = groups * P.n_ct;
   if (blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "srht: grid too large");
-  fwht_pass_kernel<T, CT, BA, BB, MODE><<<(unsigned)blocks, kPassThreads, 0, s>>>(P);
+  P.xcd_q = P.xcd_q != 0 ? blocks / 8 : 0;
+  fwht_pass_kernel<T, CT, BA, BB, MODE, ROUNDS>
+      <<<(unsigned)blocks, pass_threads<CT, BB, ROUNDS>(), 0, s>>>(P);
   SLSE_LAUNCH_CHECK();
 }
 
-template <typename T, int MODE, bool NARROW>
+template <typename T, int MODE>
 void dispatch_b(int b, PassParams<T> P, int64_t npad, hipStream_t s) {
   switch (b) {
 #define SLSE_CASE(BV) \
-  case BV: launch_pass<T, BV, MODE, NARROW>(P, npad, s); break;
+  case BV: launch_pass<T, BV, MODE>(P, npad, s); break;
     SLSE_CASE(1)
     SLSE_CASE(2)
     SLSE_CASE(3)
@@ -256,13 +304,13 @@ void dispatch_b(int b, PassParams<T> P, int64_t npad, hipStream_t s) {
   }
 }
 
-template <typename T, bool NARROW>
+template <typename T>
 void dispatch_mode(int mode, int b, PassParams<T> P, int64_t npad, hipStream_t s) {
   switch (mode) {
-    case 0: dispatch_b<T, 0, NARROW>(b, P, npad, s); break;
-    case kFirst: dispatch_b<T, kFirst, NARROW>(b, P, npad, s); break;
-    case kLast: dispatch_b<T, kLast, NARROW>(b, P, npad, s); break;
-    default: dispatch_b<T, kFirst | kLast, NARROW>(b, P, npad, s); break;
+    case 0: dispatch_b<T, 0>(b, P, npad, s); break;
+    case kFirst: dispatch_b<T, kFirst>(b, P, npad, s); break;
+    case kLast: dispatch_b<T, kLast>(b, P, npad, s); break;
+    default: dispatch_b<T, kFirst | kLast>(b, P, npad, s); break;
   }
 }
 
@@ -291,15 +339,13 @@ void run_passes(const SrhtArgs& a, hipStream_t s) {
   P.lda = a.lda;
   P.Ahat = static_cast<T*>(a.Ahat);
   P.ldah = a.ldah;
+  P.xcd_q = a.xcd_swizzle ? 1 : 0;
   const std::vector<int> bs = pass_sizes(a.p, a.bmax);
   int s0 = 0;
   for (size_t i = 0; i < bs.size(); ++i) {
     int mode = (i == 0 ? kFirst : 0) | (i + 1 == bs.size() ? kLast : 0);
     P.s0 = s0;
-    if (a.narrow)
-      dispatch_mode<T, true>(mode, bs[i], P, npad, s);
-    else
-      dispatch_mode<T, false>(mode, bs[i], P, npad, s);
+    dispatch_mode<T>(mode, bs[i], P, npad, s);
     s0 += bs[i];
   }
 }
@@ -311,11 +357,12 @@ void srht_plan(SrhtArgs& a, int prefer_bmax) {
   const int ctm = 128 / es;
   a.ct = ctm;
   a.ldz = round_up(a.d + 1, ctm);
-  int bmax = prefer_bmax > 0 ? prefer_bmax : 10;
+  // 11-stage passes (two LDS rounds) keep FP32 in registers; FP64 would spill
+  int bmax = prefer_bmax > 0 ? prefer_bmax : (es == 4 ? 11 : 10);
   if (const char* e = std::getenv("SLSE_SRHT_BMAX")) bmax = std::atoi(e);
   a.bmax = std::min(11, std::max(1, bmax));
-  a.narrow = false;
-  if (const char* e = std::getenv("SLSE_SRHT_NARROW")) a.narrow = std::atoi(e) != 0;
+  a.xcd_swizzle = true;
+  if (const char* e = std::getenv("SLSE_SRHT_XCD")) a.xcd_swizzle = std::atoi(e) != 0;
 }
 
 size_t srht_z_bytes(const SrhtArgs& a) {

@@ -120,6 +120,7 @@ struct SrhtArgs {
   int ct = 0;                 // column tile (chosen by srht_plan)
   int bmax = 0;               // stages per pass cap
   bool narrow = false;        // half-width column tiles (two blocks per CU)
+  bool xcd_swizzle = true;    // contiguous work runs per XCD
 };
 
 void srht_plan(SrhtArgs& a, int prefer_ct);

@@ -545,14 +545,21 @@ void check_params(const slse_problem* p, const slse_params* q) {
   require(q->factor == SLSE_FACTOR_CHOL || q->factor == SLSE_FACTOR_QR, "unknown factor method");
 }
 
+// Row stride of the internal sketch buffers: rows of at least one 128-byte
+// line start on a line boundary, so the SRHT's scattered row segments are
+// whole-line writes; shorter rows are packed at 16-byte alignment.
+int64_t sketch_ld(int64_t d, size_t es) {
+  const int64_t line = 128 / (int64_t)es;
+  return (d + 1) >= line ? round_up(d + 1, line) : round_up(d + 1, 16 / (int64_t)es);
+}
+
 SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* q) {
   SolvePlan pl;
   pl.sk = make_sketch_shape(q->kind, p->N, p->d, q->m, q->K, q->r);
   pl.st_t = p->dtype;
   pl.acc1 = q->precision == SLSE_PREC_MIXED ? SLSE_F32 : SLSE_F64;
   const size_t es = dtype_size(pl.st_t);
-  const int64_t align = 16 / (int64_t)es;
-  pl.lda = round_up(p->d + 1, align);
+  pl.lda = sketch_ld(p->d, es);
   pl.ldah = pl.lda;
   pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
   pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
@@ -750,7 +757,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
   if (!reuse) {
     // sketch only what H_hat needs (the smallest level keeps the sketch cheap)
     const size_t es = dtype_size(pl.st_t);
-    pl.lda = pl.ldah = round_up(p->d + 1, 16 / (int64_t)es);
+    pl.lda = pl.ldah = sketch_ld(p->d, es);
     pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
     pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
     reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh,
@@ -990,7 +997,6 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   }
   ctx->arena.grew = false;
   const size_t es = dtype_size(bp.t);
-  const int64_t align = 16 / (int64_t)es;
   int64_t a_bytes = 0, ah_bytes = 0, m_n = 0, beta_n = 0, max_npad = 0, max_rows = 0, max_d = 0;
   int64_t max_r = 0;
   size_t z_bytes = 0, g_bytes = 0;
@@ -999,7 +1005,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     bp.sk.push_back(make_sketch_shape(qs[b].kind, ps[b].N, ps[b].d, qs[b].m, qs[b].K, qs[b].r));
     const SketchShape& sk = bp.sk.back();
     const int64_t d = ps[b].d;
-    const int64_t lda = round_up(d + 1, align);
+    const int64_t lda = sketch_ld(d, es);
     bp.lda.push_back(lda);
     bp.a_off.push_back(a_bytes);
     a_bytes += round_up((int64_t)(sk.rows_A * lda * es), 256);

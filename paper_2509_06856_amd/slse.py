@@ -181,7 +181,8 @@ def sketch_apply(X, Y, kind, seed, m, r, ctx=None, bf16=False):
     N, d = X.shape
     mK = list(m)
     rows_A = sum(mK) if kind == "countsketch" else mK[-1]
-    align = 16 // X.element_size()
+    es = X.element_size()
+    align = 128 // es if d + 1 >= 128 // es else 16 // es  # rows of a full line start on a line
     ld = ((d + 1 + align - 1) // align) * align
     A = torch.empty((rows_A, ld), dtype=X.dtype, device=X.device)
     Ah = torch.empty((r, ld), dtype=X.dtype, device=X.device)

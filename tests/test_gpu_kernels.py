@@ -155,8 +155,11 @@ def _srht_bound(X, Y, p, u):
     (16384, 32, np.float64, [64, 128, 256, 512, 1024], 192, None),  # two passes
     (5000, 7, np.float32, [64, 128], 48, None),
     (70000, 63, np.float64, [1024, 2048, 4096], 400, None),
-    (70000, 63, np.float64, [1024, 2048, 4096], 400, 11),  # half-width tiles
+    (70000, 63, np.float64, [1024, 2048, 4096], 400, 11),  # two passes of 9 and 8 stages
     (3, 1, np.float64, [2, 4], 3, None),                   # tiny: N' = 4
+    (2000, 40, np.float32, [256, 512], 90, None),          # one 11-stage pass, two LDS rounds
+    (2000, 20, np.float64, [256, 512], 60, 11),            # the same for FP64
+    (5000, 33, np.float32, [512, 1024], 80, 7),            # three passes of 5, 4, 4 stages
 ])
 def test_srht_parity(G, N, d, dtype, m, r, bmax, monkeypatch):
     if bmax:
@@ -184,11 +187,27 @@ def test_srht_three_passes(G):
     A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "srht", 77, [4096, 8192], 64)
     rows = [0, 1, 777, 8191]
     sigma, sigma_hat = S.srht_orders(77, 21, 8192, 64)
-    ref = S.srht_rows(X, Y, 77, sigma[rows])
+    ref = S.srht_rows(X, Y, 77, np.concatenate([sigma[rows], sigma_hat[[0, 63]]]))
     bound = _srht_bound(X, Y, 21, U64)
-    assert np.all(np.abs(A.cpu().numpy()[rows] - ref) <= bound)
-    refh = S.srht_rows(X, Y, 77, sigma_hat[[0, 63]])
-    assert np.all(np.abs(Ah.cpu().numpy()[[0, 63]] - refh) <= bound)
+    assert np.all(np.abs(A.cpu().numpy()[rows] - ref[:4]) <= bound)
+    assert np.all(np.abs(Ah.cpu().numpy()[[0, 63]] - ref[4:]) <= bound)
+
+
+@pytest.mark.slow
+def test_srht_two_eleven_stage_passes(G):
+    # FP32 with N' = 2^22: two passes of 11 stages, each exchanging its tile in two LDS rounds
+    N, d = (1 << 22) - 9, 2
+    g = np.random.default_rng(5)
+    X = g.standard_normal((N, d)).astype(np.float32)
+    Y = g.standard_normal(N).astype(np.float32)
+    A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "srht", 91, [1 << 20, 1 << 21], 40)
+    rows, hrows = [0, 5, 1 << 20, (1 << 21) - 1], [0, 39]
+    sigma, sigma_hat = S.srht_orders(91, 22, 1 << 21, 40)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    ref = S.srht_rows(X64, Y64, 91, np.concatenate([sigma[rows], sigma_hat[hrows]]))
+    bound = _srht_bound(X64, Y64, 22, U32)
+    assert np.all(np.abs(A.cpu().numpy()[rows] - ref[:4]) <= bound)
+    assert np.all(np.abs(Ah.cpu().numpy()[hrows] - ref[4:]) <= bound)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
