@@ -160,12 +160,19 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
   }
 }
 
-// One block per problem: g = scale * sum_tiles partial (tile order), p = M g,
-// beta' = beta + mu p + eta (beta - beta_prev).
-__global__ __launch_bounds__(kThreads) void batched_update_kernel(
+// One block per problem: g = scale * sum_tiles partial, p = M g,
+// beta' = beta + mu p + eta (beta - beta_prev).  The tile sum is split over
+// (column, tile residue class) pairs and the classes are combined in a fixed
+// order, so the result does not depend on timing; the GEMV runs four rows per
+// wave at once so that their loads overlap.
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdWaves = kUpdThreads / 64;
+
+__global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
     const BatchStep* __restrict__ steps, const BatchProblem* __restrict__ probs,
     const double* __restrict__ pool, int* __restrict__ flags) {
   __shared__ double s_g[kMaxD];
+  __shared__ double s_part[kUpdThreads];
   const int b = blockIdx.x;
   const BatchStep st = steps[b];
   if (st.n <= 0) return;  // this problem has finished its schedule
@@ -173,37 +180,67 @@ __global__ __launch_bounds__(kThreads) void batched_update_kernel(
   const int d = pr.d;
   const int ntiles = st.ntiles;
   const double* part = pool + pr.part_off;
-  for (int k = threadIdx.x; k < d; k += kThreads) {
-    double t = 0.0;
-    int q = 0;
-    for (; q + 8 <= ntiles; q += 8) {
-      double v[8];
+  // classes of tiles per column: nq = 1024 / d rounded down to a power of 2
+  int nq = 1;
+  while (nq * 2 * d <= kUpdThreads) nq *= 2;
+  {
+    const int k = threadIdx.x % d;
+    const int q = threadIdx.x / d;
+    if (q < nq) {
+      double t = 0.0;
+      int j = q;
+      for (; j + 7 * nq < ntiles; j += 8 * nq) {
+        double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * (d + 1) + k];
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(j + u * nq) * (d + 1) + k];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t += v[u];
+        for (int u = 0; u < 8; ++u) t += v[u];
+      }
+      for (; j < ntiles; j += nq) t += part[(int64_t)j * (d + 1) + k];
+      s_part[q * d + k] = t;
     }
-    for (; q < ntiles; ++q) t += part[(int64_t)q * (d + 1) + k];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < d; k += kUpdThreads) {
+    double t = 0.0;
+    for (int q = 0; q < nq; ++q) t += s_part[q * d + k];
     s_g[k] = st.scale * t;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   bool bad = false;
-  for (int i = wave; i < d; i += kWaves) {
-    const double* Mi = pr.M + (int64_t)i * d;
-    double p = 0.0;
-    for (int k = lane; k < d; k += 64) p = fma(Mi[k], s_g[k], p);
-    for (int m = 32; m > 0; m >>= 1) p += wave_xor(p, m);
-    if (lane == 0) {
+  for (int i0 = 4 * wave; i0 < d; i0 += 4 * kUpdWaves) {
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = lane; k < d; k += 64) {
+      const double gk = s_g[k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u < d) p[u] = fma(pr.M[(int64_t)(i0 + u) * d + k], gk, p[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      for (int m = 32; m > 0; m >>= 1) p[u] += wave_xor(p[u], m);
+    if (lane < 4 && i0 + lane < d) {
+      const int i = i0 + lane;
+      const double pi = lane == 0 ? p[0] : lane == 1 ? p[1] : lane == 2 ? p[2] : p[3];
       const double bi = st.beta[i];
-      const double bn = bi + pr.mu * p + pr.eta * (bi - st.beta_prev[i]);
+      const double bn = bi + pr.mu * pi + pr.eta * (bi - st.beta_prev[i]);
       st.beta_next[i] = bn;
       pr.beta_out[i] = bn;
       bad |= !isfinite(bn);
     }
   }
   if (bad && flags) atomicExch(flags + b, 1);
+}
+
+__global__ void batched_init_kernel(const BatchProblem* __restrict__ probs) {
+  const BatchProblem pr = probs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pr.d) return;
+  const double v = pr.beta0 ? pr.beta0[i] : 0.0;
+  if (pr.beta_init) pr.beta_init[i] = v;
+  pr.beta_out[i] = v;
 }
 
 template <typename T, int VEC>
@@ -246,10 +283,16 @@ void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs
   SLSE_LAUNCH_CHECK();
 }
 
+void launch_batched_init(const BatchProblem* probs, int B, int dmax, hipStream_t s) {
+  if (B <= 0 || dmax <= 0) return;
+  batched_init_kernel<<<dim3((unsigned)ceil_div(dmax, 256), (unsigned)B), 256, 0, s>>>(probs);
+  SLSE_LAUNCH_CHECK();
+}
+
 void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
                            const double* pool, int* flags, hipStream_t s) {
   if (B <= 0) return;
-  batched_update_kernel<<<B, kThreads, 0, s>>>(steps, probs, pool, flags);
+  batched_update_kernel<<<B, kUpdThreads, 0, s>>>(steps, probs, pool, flags);
   SLSE_LAUNCH_CHECK();
 }
 

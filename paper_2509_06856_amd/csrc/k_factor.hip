@@ -26,21 +26,19 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                   const double* __restrict__ A, int64_t lda,
-                                                   int transA, const double* __restrict__ B,
-                                                   int64_t ldb, int transB, double beta,
-                                                   double* __restrict__ C, int64_t ldc,
-                                                   double* __restrict__ part, int64_t kper) {
+// One 64 x 64 output tile of C = alpha op(A) op(B) + beta C over k in
+// [kb0, kend); with `part` the raw sums go to split slot `zpart` instead.
+__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha,
+                                          const double* __restrict__ A, int64_t lda, int transA,
+                                          const double* __restrict__ B, int64_t ldb, int transB,
+                                          double beta, double* __restrict__ C, int64_t ldc,
+                                          double* __restrict__ part, int zpart, int64_t i0,
+                                          int64_t j0, int64_t kb0, int64_t kend) {
   __shared__ double As[kKStep][kTile + 1];
   __shared__ double Bs[kKStep][kTile + 1];
   const int tx = threadIdx.x % 16;
   const int ty = threadIdx.x / 16;
-  const int64_t i0 = (int64_t)blockIdx.y * kTile;
-  const int64_t j0 = (int64_t)blockIdx.x * kTile;
   double acc[4][4] = {};
-  const int64_t kb0 = (int64_t)blockIdx.z * kper;
-  const int64_t kend = min(K, kb0 + kper);
   for (int64_t k0 = kb0; k0 < kend; k0 += kKStep) {
     for (int e = threadIdx.x; e < kKStep * kTile; e += 256) {
       int kk, ii;
@@ -91,7 +89,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
       if (gi < M && gj < N) {
         if (part) {
-          part[((int64_t)blockIdx.z * M + gi) * N + gj] = acc[u][v];
+          part[((int64_t)zpart * M + gi) * N + gj] = acc[u][v];
         } else {
           double c = alpha * acc[u][v];
           if (beta != 0.0) c += beta * C[gi * ldc + gj];
@@ -99,6 +97,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
         }
       }
     }
+}
+
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                   const double* __restrict__ A, int64_t lda,
+                                                   int transA, const double* __restrict__ B,
+                                                   int64_t ldb, int transB, double beta,
+                                                   double* __restrict__ C, int64_t ldc,
+                                                   double* __restrict__ part, int64_t kper) {
+  const int64_t kb0 = (int64_t)blockIdx.z * kper;
+  gemm_tile(M, N, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc, part, (int)blockIdx.z,
+            (int64_t)blockIdx.y * kTile, (int64_t)blockIdx.x * kTile, kb0, min(K, kb0 + kper));
+}
+
+// Batched products of the factor jobs (blockIdx.z = job):
+//   which = 0: G = Ad^T Ad    which = 1: M = L L^T
+__global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJob* __restrict__ jobs,
+                                                                  int which) {
+  const FactorJob jb = jobs[blockIdx.z];
+  const int64_t d = jb.d;
+  const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
+  if (i0 >= d || j0 >= d) return;
+  if (which == 0)
+    gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, nullptr, 0, i0, j0, 0, jb.rows);
+  else
+    gemm_tile(d, d, 1.0, jb.L, d, 0, jb.L, d, 1, 0.0, jb.M, d, nullptr, 0, i0, j0, 0, d);
 }
 
 // C = alpha * sum_s part[s] + beta * C (splits summed in order)
@@ -138,9 +161,9 @@ constexpr int kCholKC = 32;       // rows of R staged per update step
 // the rows of R above it (a GEMM against rows staged through LDS), its 32 x 32
 // diagonal block is then factored in LDS by the whole block, and the rest of
 // the panel is a triangular solve with that block, one column per thread.
-__global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const double* __restrict__ G,
-                                                                int64_t ldg, double* __restrict__ R,
-                                                                int64_t ldr, int* __restrict__ info) {
+__device__ __forceinline__ void cholesky_block(int d, const double* __restrict__ G, int64_t ldg,
+                                               double* __restrict__ R, int64_t ldr,
+                                               int* __restrict__ info) {
   __shared__ double Kb[kCholKC][kCholNB];
   __shared__ double D[kCholNB][kCholNB + 1];
   __shared__ int s_bad;
@@ -235,6 +258,19 @@ __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const dou
   if (t == 0) info[0] = s_bad;
 }
 
+__global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const double* __restrict__ G,
+                                                                int64_t ldg, double* __restrict__ R,
+                                                                int64_t ldr, int* __restrict__ info) {
+  cholesky_block(d, G, ldg, R, ldr, info);
+}
+
+// one job per block
+__global__ __launch_bounds__(kCholThreads) void cholesky_batched_kernel(
+    const FactorJob* __restrict__ jobs) {
+  const FactorJob jb = jobs[blockIdx.x];
+  cholesky_block(jb.d, jb.G, jb.d, jb.R, jb.d, jb.info);
+}
+
 // Rinv = R^{-1} row by row: row i solves x^T R = e_i^T by forward
 // substitution over j with running sums s_l = -sum_{k<j} x_k R_kl, so each
 // step reads one row of R (contiguous).  Lane l keeps s for the columns
@@ -244,14 +280,12 @@ constexpr int kInvRows = 16;
 constexpr int kInvMaxD = 512;
 constexpr int kInvPer = kInvMaxD / 64;
 
-__global__ __launch_bounds__(256) void tri_inv_kernel(int d, const double* __restrict__ R,
-                                                      int64_t ldr, double* __restrict__ Rinv,
-                                                      int64_t ldi) {
+__device__ __forceinline__ void tri_inv_rows(int d, const double* __restrict__ R, int64_t ldr,
+                                             double* __restrict__ Rinv, int64_t ldi, int i0) {
   __shared__ double Rs[kInvRows][kInvMaxD];
   __shared__ double rdiag[kInvMaxD];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * 4;
   const int i = i0 + wave;
   for (int l = threadIdx.x; l < d; l += 256) rdiag[l] = 1.0 / R[(int64_t)l * ldr + l];
   double s[kInvPer];
@@ -293,6 +327,33 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(int d, const double* __res
       const int l = lane + 64 * k;
       if (l < d) Rinv[(int64_t)i * ldi + l] = (l < i) ? 0.0 : s[k];
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void tri_inv_kernel(int d, const double* __restrict__ R,
+                                                      int64_t ldr, double* __restrict__ Rinv,
+                                                      int64_t ldi) {
+  tri_inv_rows(d, R, ldr, Rinv, ldi, blockIdx.x * 4);
+}
+
+// blockIdx.y = job; blocks past a job's rows exit
+__global__ __launch_bounds__(256) void tri_inv_batched_kernel(const FactorJob* __restrict__ jobs) {
+  const FactorJob jb = jobs[blockIdx.y];
+  const int i0 = blockIdx.x * 4;
+  if (i0 >= jb.d) return;
+  tri_inv_rows(jb.d, jb.R, jb.d, jb.L, jb.d, i0);
+}
+
+// Ad = scale * A[:, :d] of every job (blockIdx.y = job)
+__global__ void convert_scale_batched_kernel(const FactorJob* __restrict__ jobs, int is_f32) {
+  const FactorJob jb = jobs[blockIdx.y];
+  const int64_t n = jb.rows * jb.d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / jb.d, k = e % jb.d;
+    const double v = is_f32 ? (double)static_cast<const float*>(jb.A)[i * jb.lda + k]
+                            : static_cast<const double*>(jb.A)[i * jb.lda + k];
+    jb.Ad[e] = jb.scale * v;
   }
 }
 
@@ -343,6 +404,24 @@ void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr
                      hipStream_t s) {
   if (d > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this build");
   cholesky_kernel<<<1, kCholThreads, 0, s>>>(d, G, ldg, R, ldr, info);
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_max,
+                           slse_dtype at, hipStream_t s) {
+  if (B <= 0) return;
+  if (dmax > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this build");
+  const unsigned cb = (unsigned)std::min<int64_t>(ceil_div(rows_max * dmax, 256), 1024);
+  convert_scale_batched_kernel<<<dim3(cb, (unsigned)B), 256, 0, s>>>(jobs, at == SLSE_F32 ? 1 : 0);
+  SLSE_LAUNCH_CHECK();
+  const unsigned tiles = (unsigned)ceil_div(dmax, kTile);
+  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs, 0);
+  SLSE_LAUNCH_CHECK();
+  cholesky_batched_kernel<<<(unsigned)B, kCholThreads, 0, s>>>(jobs);
+  SLSE_LAUNCH_CHECK();
+  tri_inv_batched_kernel<<<dim3((unsigned)ceil_div(dmax, 4), (unsigned)B), 256, 0, s>>>(jobs);
+  SLSE_LAUNCH_CHECK();
+  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs, 1);
   SLSE_LAUNCH_CHECK();
 }
 

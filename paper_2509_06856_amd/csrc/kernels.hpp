@@ -192,6 +192,26 @@ void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr
 // Rinv = R^{-1} (upper triangular, row-major d x d) for upper triangular R.
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s);
 
+// One Cholesky-route factorization of a batch: Ad = scale * A[:, :d] (FP64),
+// G = Ad^T Ad, R^T R = G, L = R^{-1}, M = L L^T.  Every buffer is the job's
+// own, row-major with leading dimension d (A: lda).
+struct FactorJob {
+  const void* A = nullptr;
+  int64_t lda = 0;
+  int64_t rows = 0;
+  int d = 0;
+  double scale = 1.0;
+  double* Ad = nullptr;
+  double* G = nullptr;
+  double* R = nullptr;
+  double* L = nullptr;
+  double* M = nullptr;
+  int* info = nullptr;
+};
+// All jobs at once (jobs in device memory; dmax, rows_max bound every job).
+void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_max,
+                           slse_dtype at, hipStream_t s);
+
 // --------------------------------------------------------------------------
 // Adjoint rank-2 pass: dY = X lambda, dX = r lambda^T - (X lambda) beta^T.
 // --------------------------------------------------------------------------
@@ -234,12 +254,16 @@ struct BatchProblem {
   const double* M;
   double* beta_out;
   double mu, eta;
+  const double* beta0;  // initial iterate (device) or null for 0
+  double* beta_init;    // the iterate buffer the first step reads
 };
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
                                int B, int total_tiles, int tile_rows, int grid, double* pool,
                                slse_dtype t, bool vec, int nch, hipStream_t s);
 void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
                            const double* pool, int* flags, hipStream_t s);
+// beta_init = beta_out = beta0 (or 0) for every problem
+void launch_batched_init(const BatchProblem* probs, int B, int dmax, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Test hooks.

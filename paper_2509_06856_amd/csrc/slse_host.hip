@@ -865,6 +865,12 @@ struct BatchPlan {
   SrhtArgs srht;
   GaussianArgs ga, gh;
   FactorBufs f;
+  // Cholesky route for every problem: one batched factorization
+  bool batched_factor = false;
+  int dmax = 0;
+  int64_t rmax = 0;
+  FactorJob* d_jobs = nullptr;
+  std::vector<FactorJob> h_jobs;
 };
 
 int batch_lpr(int d, bool vec, slse_dtype t) {
@@ -939,48 +945,60 @@ void enqueue_batch_steps(const BatchPlan& bp, hipStream_t st) {
   }
 }
 
+// Sketch of problem b into its A / Ahat.
+void enqueue_batch_sketch(const BatchPlan& bp, int b, const slse_problem* ps,
+                          const slse_params* qs, hipStream_t st) {
+  const SketchShape& sk = bp.sk[b];
+  const int d = (int)ps[b].d;
+  SrhtArgs sa = bp.srht;
+  if (sk.kind == SLSE_SRHT) {
+    sa.N = sk.N;
+    sa.d = d;
+    sa.p = sk.p;
+    sa.mK = sk.m[sk.K - 1];
+    sa.r = sk.r;
+    srht_plan(sa, 0);
+  }
+  GaussianArgs ga = bp.ga, gh = bp.gh;
+  ga.N = gh.N = sk.N;
+  ga.d = gh.d = d;
+  ga.m = sk.m[sk.K - 1];
+  gh.m = sk.r;
+  ga.bf16 = gh.bf16 = qs[b].precision == SLSE_PREC_MIXED && bp.t == SLSE_F32;
+  if (sk.kind == SLSE_GAUSSIAN) {
+    gaussian_plan(ga);
+    gaussian_plan(gh);
+  }
+  void* A = bp.Apool + bp.a_off[b];
+  void* Ah = bp.Ahpool + bp.ah_off[b];
+  enqueue_sketch(sk, qs[b].seed, ps[b].X, ps[b].ldx, ps[b].Y, bp.t, A, bp.lda[b], Ah, bp.lda[b],
+                 sa, ga, gh, st);
+}
+
+// Factor of problem b through the shared scratch (the QR route).
+void enqueue_batch_factor(const BatchPlan& bp, int b, const slse_problem* ps,
+                          const slse_params* qs, hipStream_t st) {
+  const SketchShape& sk = bp.sk[b];
+  const int d = (int)ps[b].d;
+  FactorBufs f = bp.f;
+  f.info = bp.finfo + 2 * b;
+  enqueue_factor(f, sk.r, d, bp.Ahpool + bp.ah_off[b], bp.lda[b], bp.t, sk.hat_scale, qs[b].factor,
+                 st);
+  launch_copy_f64(f.M, bp.Mpool + bp.m_off[b], (int64_t)d * d, st);
+}
+
+// Sketches one problem after another, the factorizations (one batched launch
+// sequence on the Cholesky route), the initial iterates, then the batched steps.
 void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_params* qs,
-                   double* const* betas, hipStream_t st) {
-  const size_t es = dtype_size(bp.t);
+                   hipStream_t st) {
   launch_fill_i32(bp.flags, 0, bp.B, st);
   launch_fill_i32(bp.finfo, 0, 2 * (int64_t)bp.B, st);
-  for (int b = 0; b < bp.B; ++b) {
-    const SketchShape& sk = bp.sk[b];
-    const int d = (int)ps[b].d;
-    SrhtArgs sa = bp.srht;
-    if (sk.kind == SLSE_SRHT) {
-      sa.N = sk.N;
-      sa.d = d;
-      sa.p = sk.p;
-      sa.mK = sk.m[sk.K - 1];
-      sa.r = sk.r;
-      srht_plan(sa, 0);
-    }
-    GaussianArgs ga = bp.ga, gh = bp.gh;
-    ga.N = gh.N = sk.N;
-    ga.d = gh.d = d;
-    ga.m = sk.m[sk.K - 1];
-    gh.m = sk.r;
-    ga.bf16 = gh.bf16 = qs[b].precision == SLSE_PREC_MIXED && bp.t == SLSE_F32;
-    if (sk.kind == SLSE_GAUSSIAN) {
-      gaussian_plan(ga);
-      gaussian_plan(gh);
-    }
-    void* A = bp.Apool + bp.a_off[b];
-    void* Ah = bp.Ahpool + bp.ah_off[b];
-    enqueue_sketch(sk, qs[b].seed, ps[b].X, ps[b].ldx, ps[b].Y, bp.t, A, bp.lda[b], Ah, bp.lda[b],
-                   sa, ga, gh, st);
-    FactorBufs f = bp.f;
-    f.info = bp.finfo + 2 * b;
-    enqueue_factor(f, sk.r, d, Ah, bp.lda[b], bp.t, sk.hat_scale, qs[b].factor, st);
-    launch_copy_f64(f.M, bp.Mpool + bp.m_off[b], (int64_t)d * d, st);
-    double* b0 = bp.Bpool + bp.beta_off[b];
-    if (qs[b].beta0)
-      launch_copy_f64(qs[b].beta0, b0, d, st);
-    else
-      launch_fill_f64(b0, 0.0, d, st);
-    launch_copy_f64(b0, betas[b], d, st);
-  }
+  for (int b = 0; b < bp.B; ++b) enqueue_batch_sketch(bp, b, ps, qs, st);
+  if (bp.batched_factor)
+    launch_factor_batched(bp.d_jobs, bp.B, bp.dmax, bp.rmax, bp.t, st);
+  else
+    for (int b = 0; b < bp.B; ++b) enqueue_batch_factor(bp, b, ps, qs, st);
+  launch_batched_init(bp.d_probs, bp.B, bp.dmax, st);
   enqueue_batch_steps(bp, st);
 }
 
@@ -1063,7 +1081,43 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   slse_factor_method fm = SLSE_FACTOR_CHOL;
   for (int b = 0; b < B; ++b)
     if (qs[b].factor == SLSE_FACTOR_QR) fm = SLSE_FACTOR_QR;
-  bp.f = reserve_factor(ctx, max_r, max_d, fm);
+  bp.dmax = (int)max_d;
+  bp.rmax = max_r;
+  bp.batched_factor = fm == SLSE_FACTOR_CHOL;
+  if (bp.batched_factor) {
+    // each problem owns its Ad, G, R and L; M goes straight into the M pool
+    int64_t ad_n = 0, sq_n = 0;
+    for (int b = 0; b < B; ++b) {
+      ad_n += bp.sk[b].r * ps[b].d;
+      sq_n += ps[b].d * ps[b].d;
+    }
+    double* adp = ctx->arena.get_t<double>("bfAd", (size_t)ad_n);
+    double* gp = ctx->arena.get_t<double>("bfG", (size_t)sq_n);
+    double* rp = ctx->arena.get_t<double>("bfR", (size_t)sq_n);
+    double* lp = ctx->arena.get_t<double>("bfL", (size_t)sq_n);
+    bp.h_jobs.resize(B);
+    int64_t ao = 0, so = 0;
+    for (int b = 0; b < B; ++b) {
+      FactorJob& j = bp.h_jobs[b];
+      const int64_t d = ps[b].d;
+      j.A = bp.Ahpool + bp.ah_off[b];
+      j.lda = bp.lda[b];
+      j.rows = bp.sk[b].r;
+      j.d = (int)d;
+      j.scale = std::sqrt(bp.sk[b].hat_scale);
+      j.Ad = adp + ao;
+      j.G = gp + so;
+      j.R = rp + so;
+      j.L = lp + so;
+      j.M = bp.Mpool + bp.m_off[b];
+      j.info = bp.finfo + 2 * b;
+      ao += j.rows * d;
+      so += d * d;
+    }
+    bp.d_jobs = ctx->arena.get_t<FactorJob>("bJobs", (size_t)B);
+  } else {
+    bp.f = reserve_factor(ctx, max_r, max_d, fm);
+  }
   // steps of every problem
   for (int b = 0; b < B; ++b) {
     int T = qs[b].s_max;
@@ -1091,6 +1145,9 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     const double eta = qs[b].eta, mu = qs[b].mu;
     pr.mu = mu;
     pr.eta = eta;
+    pr.beta0 = qs[b].beta0;
+    // the first step of every problem reads beta slot 0 of its ring
+    pr.beta_init = bp.steps_of[b] > 0 ? bp.Bpool + bp.beta_off[b] : nullptr;
   }
   bp.nch = nch;
   // tile size and grid: autotuned once per batch shape on a stage-2 step
@@ -1120,6 +1177,8 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   for (int b = 0; b < B; ++b) bp.h_probs[b].part_off = bp.part_off[b];
   if (ctx->arena.grew) ctx->drop_graphs();
   SLSE_HIP(hipMemcpy(bp.d_probs, bp.h_probs.data(), sizeof(BatchProblem) * B, hipMemcpyHostToDevice));
+  if (bp.batched_factor)
+    SLSE_HIP(hipMemcpy(bp.d_jobs, bp.h_jobs.data(), sizeof(FactorJob) * B, hipMemcpyHostToDevice));
 
   auto upload = [&]() {
     build_batch_tables(bp, ps, qs, betas);
@@ -1183,7 +1242,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     hipGraph_t g = nullptr;
     SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_batch(bp, ps, qs, betas, ctx->capture_stream);
+      enqueue_batch(bp, ps, qs, ctx->capture_stream);
     } catch (...) {
       hipGraph_t junk = nullptr;
       (void)hipStreamEndCapture(ctx->capture_stream, &junk);

@@ -218,8 +218,8 @@ def make_batched(count=64, seed=None, n_range=(1 << 14, 1 << 18), d_choices=(16,
         beta = g.standard_normal(d)
         sigma = 1e-2
         Y = _matvec(Xb, beta) + sigma * g.standard_normal(n)
-        probs.append(Problem("batched", np.ascontiguousarray(Xb, dtype=np.float32), Y.astype(np.float32), beta, sigma,
-                             dict(seed=seed, index=b)))
+        probs.append(Problem("batched", np.ascontiguousarray(Xb, dtype=np.float32),
+                             Y.astype(np.float32), beta, sigma, dict(seed=seed, index=b)))
     return probs
 
 
