@@ -357,7 +357,145 @@ __global__ void convert_scale_batched_kernel(const FactorJob* __restrict__ jobs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// M = G^{-1} for SPD G by blocked Gauss-Jordan elimination in place, 32 rows
+// per step (no pivoting: the pivots of an SPD matrix are positive).  Step k
+// with pivot block P = G[K, K], K = [k0, k0 + 32):
+//   panel  : Pinv = P^{-1} (every block; block 0 stores it in colp rows K);
+//            G[K, j] = Pinv G[K, j] (j outside K); the old column panel
+//            G[i, K] (i outside K) is saved to colp rows i
+//   update : G[i, j] -= colp[i, :] G[K, j]   (i, j outside K)
+//            G[i, K]  = -colp[i, :] Pinv      (i outside K)
+//            G[K, K]  = Pinv
+// G[K, K] is written only in the update, after every panel block has read P.
+// ---------------------------------------------------------------------------
+constexpr int kGJ = 32;
+constexpr int kGJChunk = 64;  // columns (and saved rows) per panel block
+
+// In-place inverse of the 32 x 32 block held by one wave: lane c (< 32) owns
+// column c in col[0..31].  A non-positive or non-finite pivot sets *bad.
+__device__ __forceinline__ void gj_invert32(double (&col)[kGJ], int lane, bool* bad) {
+#pragma unroll
+  for (int s = 0; s < kGJ; ++s) {
+    double piv = readlane_f64(col[s], s);
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      *bad = true;
+      piv = 1.0;
+    }
+    const double inv = 1.0 / piv;
+    const double rs = (lane == s) ? inv : col[s] * inv;  // new row s in column `lane`
+#pragma unroll
+    for (int i = 0; i < kGJ; ++i) {
+      if (i == s) continue;
+      const double f = readlane_f64(col[i], s);  // old P[i][s]
+      col[i] = (lane == s) ? -f * inv : fma(-f, rs, col[i]);
+    }
+    col[s] = rs;
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_panel_kernel(int d, int k0, double* __restrict__ G,
+                                                       double* __restrict__ colp,
+                                                       int* __restrict__ info) {
+  __shared__ double Pinv[kGJ][kGJ + 1];
+  __shared__ double Rp[kGJ][kGJChunk + 1];
+  const int t = threadIdx.x;
+  const int kw = min(kGJ, d - k0);
+  // 1. pivot block inverse (wave 0), padded with the identity past d
+  if (t < 64) {
+    double col[kGJ];
+    const int c = t;
+#pragma unroll
+    for (int a = 0; a < kGJ; ++a)
+      col[a] = (c < kGJ && a < kw && c < kw) ? G[(int64_t)(k0 + a) * d + k0 + c]
+                                             : (a == c ? 1.0 : 0.0);
+    bool bad = false;
+    gj_invert32(col, c, &bad);
+    if (c < kGJ) {
+#pragma unroll
+      for (int a = 0; a < kGJ; ++a) {
+        Pinv[a][c] = col[a];
+        if (blockIdx.x == 0 && a < kw && c < kw) colp[(int64_t)(k0 + a) * kGJ + c] = col[a];
+      }
+    }
+    if (bad && t == 0) atomicCAS(info, 0, k0 + 1);
+  }
+  // 2. save the old column panel for rows [64 b, 64 b + 64) outside K
+  const int r0 = blockIdx.x * kGJChunk;
+  for (int e = t; e < kGJChunk * kGJ; e += 256) {
+    const int i = r0 + e / kGJ, a = e % kGJ;
+    if (i < d && (i < k0 || i >= k0 + kw) && a < kw) colp[(int64_t)i * kGJ + a] = G[(int64_t)i * d + k0 + a];
+  }
+  // 3. row panel of this block's columns [64 b, 64 b + 64)
+  const int c0 = blockIdx.x * kGJChunk;
+  for (int e = t; e < kGJ * kGJChunk; e += 256) {
+    const int a = e / kGJChunk, j = c0 + e % kGJChunk;
+    Rp[a][e % kGJChunk] = (a < kw && j < d) ? G[(int64_t)(k0 + a) * d + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < kGJ * kGJChunk; e += 256) {
+    const int a = e / kGJChunk, jj = e % kGJChunk, j = c0 + jj;
+    if (a >= kw || j >= d || (j >= k0 && j < k0 + kw)) continue;
+    double v = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGJ; ++q) v = fma(Pinv[a][q], Rp[q][jj], v);
+    G[(int64_t)(k0 + a) * d + j] = v;
+  }
+}
+
+// one 32 x 32 output tile per block (blockIdx.y = row tile, blockIdx.x = column tile)
+__global__ __launch_bounds__(256) void gj_update_kernel(int d, int k0, double* __restrict__ G,
+                                                        const double* __restrict__ colp) {
+  __shared__ double Cp[kGJ][kGJ + 1];  // colp rows of this tile
+  __shared__ double Rw[kGJ][kGJ + 1];  // new row panel columns of this tile
+  const int kw = min(kGJ, d - k0);
+  const int i0 = blockIdx.y * kGJ, j0 = blockIdx.x * kGJ;
+  const int t = threadIdx.x;
+  const bool pivcols = j0 == k0;
+  if (i0 == k0) {  // the pivot rows were finished by the panel step, but for G[K, K]
+    if (pivcols)
+      for (int e = t; e < kGJ * kGJ; e += 256) {
+        const int r = e / kGJ, c = e % kGJ;
+        if (r < kw && c < kw) G[(int64_t)(k0 + r) * d + k0 + c] = colp[(int64_t)(k0 + r) * kGJ + c];
+      }
+    return;
+  }
+  for (int e = t; e < kGJ * kGJ; e += 256) {
+    const int r = e / kGJ, c = e % kGJ;
+    Cp[r][c] = (i0 + r < d && c < kw) ? colp[(int64_t)(i0 + r) * kGJ + c] : 0.0;
+    // Pinv (colp rows K) for the pivot columns, else the new row panel
+    const bool in = r < kw && j0 + c < d;
+    Rw[r][c] = !in ? 0.0
+               : pivcols ? colp[(int64_t)(k0 + r) * kGJ + c]
+                         : G[(int64_t)(k0 + r) * d + j0 + c];
+  }
+  __syncthreads();
+  for (int e = t; e < kGJ * kGJ; e += 256) {
+    const int r = e / kGJ, c = e % kGJ;
+    const int i = i0 + r, j = j0 + c;
+    if (i >= d || j >= d) continue;
+    double v = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGJ; ++q) v = fma(Cp[r][q], Rw[q][c], v);
+    if (pivcols)
+      G[(int64_t)i * d + j] = -v;  // Rw holds Pinv here
+    else
+      G[(int64_t)i * d + j] -= v;
+  }
+}
+
 }  // namespace
+
+void launch_spd_inverse(int d, double* G, double* colp, int* info, hipStream_t s) {
+  if (d <= 0) return;
+  const unsigned nt = (unsigned)ceil_div(d, kGJ);
+  for (int k0 = 0; k0 < d; k0 += kGJ) {
+    gj_panel_kernel<<<(unsigned)ceil_div(d, kGJChunk), 256, 0, s>>>(d, k0, G, colp, info);
+    SLSE_LAUNCH_CHECK();
+    gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(d, k0, G, colp);
+    SLSE_LAUNCH_CHECK();
+  }
+}
 
 int gemm_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ceil_div(M, kTile) * ceil_div(N, kTile);

@@ -189,6 +189,10 @@ void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_
 // first bad pivot.  G is read only.
 void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr, int* info,
                      hipStream_t s);
+// G = G^{-1} in place for SPD G (d x d, ld = d) by blocked Gauss-Jordan; colp
+// is d x 32 scratch.  info[0] (zero on entry) becomes k0 + 1 of the first
+// pivot block with a non-positive or non-finite pivot.
+void launch_spd_inverse(int d, double* G, double* colp, int* info, hipStream_t s);
 // Rinv = R^{-1} (upper triangular, row-major d x d) for upper triangular R.
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s);
 

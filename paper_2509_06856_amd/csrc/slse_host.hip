@@ -285,6 +285,7 @@ struct FactorBufs {
   int* info = nullptr;   // 2 ints
   double* part = nullptr;  // split-K scratch of the GEMMs
   size_t part_n = 0;
+  double* colp = nullptr;  // d x 32 panel scratch of the Gauss-Jordan inverse
 };
 
 FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_method method) {
@@ -302,13 +303,24 @@ FactorBufs reserve_factor(slse_ctx* ctx, int64_t rows, int64_t d, slse_factor_me
   f.part_n = std::max(gemm_scratch_doubles(d, d, rows), gemm_scratch_doubles(d, d, d));
   if (method == SLSE_FACTOR_QR) f.part_n = std::max(f.part_n, gemm_scratch_doubles(rows, d, d));
   f.part = ctx->arena.get_t<double>("f_part", f.part_n + 1);
+  f.colp = ctx->arena.get_t<double>("f_colp", d * 32);
   return f;
 }
 
-// R (ldr = d) and M (ldm = d) into f.R / f.M.
+// M (ldm = d) into f.M, and R (ldr = d) into f.R when need_R or on the QR
+// route.  Without R the Cholesky route inverts the Gram matrix directly
+// (M = G^{-1}, blocked Gauss-Jordan): the iteration needs only M.
 void enqueue_factor(const FactorBufs& f, int64_t rows, int d, const void* A, int64_t lda,
-                    slse_dtype at, double scale, slse_factor_method method, hipStream_t st) {
+                    slse_dtype at, double scale, slse_factor_method method, hipStream_t st,
+                    bool need_R = false) {
   launch_convert_scale(rows, d, A, lda, at, std::sqrt(scale), f.Ad, d, st);
+  if (method == SLSE_FACTOR_CHOL && !need_R) {
+    launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.M, d, st, f.part,
+                    f.part_n);
+    launch_fill_i32(f.info, 0, 2, st);
+    launch_spd_inverse(d, f.M, f.colp, f.info, st);
+    return;
+  }
   launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st, f.part, f.part_n);
   launch_cholesky(d, f.G, d, f.R, d, f.info, st);
   if (method == SLSE_FACTOR_QR) {
@@ -1397,7 +1409,7 @@ slse_status slse_factor(slse_ctx* ctx, int64_t rows, int64_t d, const void* A, i
     if (ctx->arena.grew) ctx->drop_graphs();
     ctx->pre.valid = false;
     launch_fill_i32(f.info, 0, 2, st);
-    enqueue_factor(f, rows, (int)d, A, lda, a_t, scale, method, st);
+    enqueue_factor(f, rows, (int)d, A, lda, a_t, scale, method, st, true);
     SLSE_HIP(hipMemcpy2DAsync(R, ldr * sizeof(double), f.R, d * sizeof(double), d * sizeof(double),
                               d, hipMemcpyDeviceToDevice, st));
     if (M)

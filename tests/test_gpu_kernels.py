@@ -320,6 +320,20 @@ def test_solve_trajectory_matches_oracle(G, kind):
     assert OS.rel_err(beta.cpu().numpy(), bstar) < 1e-12
 
 
+@pytest.mark.parametrize("factor", ["chol", "qr"])
+def test_solve_trajectory_ragged_d(G, factor):
+    # d = 70: the Gram inverse takes pivot blocks of 32, 32 and 6 rows
+    prob = make_problem("plain_small", n=20000, d=70)
+    m = [1024, 2048, 4096]
+    params = G.Params(kind="srht", seed=77, m=m, a=[2] * 3, r=420, s_max=25, factor=factor)
+    beta, info, traj, sur = G.solve(dev(prob.X), dev(prob.Y), params, record=True)
+    ref_beta, ref_traj, _ = OS.slse_frs(prob.X, prob.Y, 77, "srht", m, [2] * 3, 420, s=25)
+    tg = traj.cpu().numpy()
+    for t in range(len(ref_traj)):
+        den = max(np.linalg.norm(ref_traj[t]), 1e-300)
+        assert np.linalg.norm(tg[t] - ref_traj[t]) / den <= 1e-12, t
+
+
 def test_solve_graph_replays_match_eager(G):
     prob = make_problem("plain_small", n=8192, d=24)
     m = [64, 128, 256, 512]
