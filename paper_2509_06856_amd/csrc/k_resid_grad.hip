@@ -19,7 +19,15 @@
 namespace slse {
 namespace {
 
-constexpr int kThreads = 256;
+// Build-time launch shape: threads per block and bytes in flight per lane (in
+// units of 256 B) of the fully vectorised main loop.
+#ifndef SLSE_RG_THREADS
+#define SLSE_RG_THREADS 256
+#endif
+#ifndef SLSE_RG_DEPTH
+#define SLSE_RG_DEPTH 1
+#endif
+constexpr int kThreads = SLSE_RG_THREADS;
 constexpr int kWaves = kThreads / 64;
 constexpr int kGroupSize = 32;  // blocks summed by the last block of each group
 
@@ -57,20 +65,54 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
   }
 }
 
-template <typename T, int VEC, int NCH>
-constexpr int unroll_for() {
-  constexpr int bytes = NCH * VEC * (int)sizeof(T);
-  constexpr int u = 256 / bytes;
-  return u < 1 ? 1 : (u > 16 ? 16 : u);
+// x widened to the accumulation type
+template <typename Acc, typename T>
+__device__ __forceinline__ Acc widen(T x) {
+  return (Acc)x;
 }
 
-template <typename T, typename Acc, int VEC, int NCH, bool HAS_Y>
+// The same, as a separate instruction the compiler cannot merge with `widen`:
+// the widened row is then not kept alive from the dot to the update.
+template <typename Acc, typename T>
+__device__ __forceinline__ Acc widen_again(T x) {
+  if constexpr (sizeof(Acc) == 8 && sizeof(T) == 4) {
+    double r;
+    asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+  } else {
+    return (Acc)x;
+  }
+}
+
+// value of lane (lane ^ m) for 32- or 64-bit values (m < 64, no width clamp)
+template <typename V>
+__device__ __forceinline__ V lane_xor(V v, int m, int lane) {
+  const int addr = (lane ^ m) << 2;
+  if constexpr (sizeof(V) == 8) {
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(u & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(u >> 32));
+    return __builtin_bit_cast(V, ((long long)hi << 32) | (unsigned int)lo);
+  } else {
+    return __builtin_bit_cast(V, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+  }
+}
+
+template <typename T, int VEC, int NCH, int DEPTH = 1>
+constexpr int unroll_for() {
+  constexpr int bytes = NCH * VEC * (int)sizeof(T);
+  constexpr int u = 256 * DEPTH / bytes;
+  return u < 1 ? 1 : (u > 16 * DEPTH ? 16 * DEPTH : u);
+}
+
+// FULL: d = NCH * lpr * VEC, so every chunk is a whole vector inside the row.
+template <typename T, typename Acc, int VEC, int NCH, bool HAS_Y, bool FULL>
 __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
     int64_t n, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t incy,
     const double* __restrict__ beta, int lpr, double* __restrict__ partial,
     double* __restrict__ gpart, int* __restrict__ counters, int ldp,
     const int* __restrict__ done) {
-  constexpr int UNROLL = unroll_for<T, VEC, NCH>();
+  constexpr int UNROLL = unroll_for<T, VEC, NCH, FULL ? SLSE_RG_DEPTH : 1>();
   if (done && *done) return;
   __shared__ double s_red[kWaves][1025];
   __shared__ int s_ticket;
@@ -106,7 +148,91 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(n, r0 + chunk);
 
-  for (int64_t base = r0 + wave * gpw + grp; base < r1; base += (int64_t)rs * UNROLL) {
+  int64_t base = r0 + wave * gpw + grp;
+  if constexpr (FULL) {
+    // main loop: every row of the step is in range for the whole wave (the
+    // bound is wave-uniform), so the loads carry no guards and no branches
+    const int64_t wave_base0 = r0 + wave * gpw;
+    const int64_t last_off = (int64_t)(gpw - 1) + (int64_t)(UNROLL - 1) * rs;
+    int64_t wb = wave_base0;
+    for (; wb + last_off < r1; wb += (int64_t)rs * UNROLL) {
+      const int64_t row0 = wb + grp;
+      T x[UNROLL][NCH][VEC];
+      T y[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const T* xr = X + (row0 + (int64_t)u * rs) * ldx;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) load_vec<T, VEC>(xr + (c * lpr + l) * VEC, x[u][c]);
+        if constexpr (HAS_Y) {
+          y[u] = __builtin_nontemporal_load(Y + (row0 + (int64_t)u * rs) * incy);
+        } else {
+          y[u] = 0;
+        }
+      }
+      // partial dots row by row (the widened values of a row die with its dot)
+      Acc dot[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        __builtin_amdgcn_sched_barrier(0);
+        Acc p0 = 0, p1 = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            if ((c * VEC + v) & 1)
+              p1 = fma(widen<Acc>(x[u][c][v]), b[c][v], p1);
+            else
+              p0 = fma(widen<Acc>(x[u][c][v]), b[c][v], p0);
+          }
+        dot[u] = p0 + p1;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // all-reduce the rows' dots inside each lane group, the rows interleaved
+      for (int m = lpr >> 1; m > 0; m >>= 1) {
+        Acc o[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) o[u] = lane_xor(dot[u], m, lane);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) dot[u] += o[u];
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const Acc r = (Acc)y[u] - dot[u];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, widen_again<Acc>(x[u][c][v]), acc[c][v]);
+        rr = fma(r, r, rr);
+      }
+    }
+    // tail: one row per lane group at a time, whole vectors, row guard only
+    for (int64_t row = wb + grp; row < r1; row += rs) {
+      const T* xr = X + row * ldx;
+      T x[NCH][VEC];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) load_vec<T, VEC>(xr + (c * lpr + l) * VEC, x[c]);
+      T y0 = 0;
+      if constexpr (HAS_Y) y0 = Y[row * incy];
+      Acc dot = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) dot = fma((Acc)x[c][v], b[c][v], dot);
+      // lanes of a group share the row, so the group's shuffles stay inside
+      // lanes that are all active
+      dot = lane_group_sum(dot, lpr);
+      const Acc r = (Acc)y0 - dot;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, (Acc)x[c][v], acc[c][v]);
+      rr = fma(r, r, rr);
+    }
+    base = r1;  // nothing left for the guarded loop
+  }
+  // guarded loop (every row when not FULL)
+  for (; base < r1; base += (int64_t)rs * UNROLL) {
     T x[UNROLL][NCH][VEC];
     T y[UNROLL];
 #pragma unroll
@@ -221,29 +347,29 @@ __global__ void finalize_grad_kernel(const double* __restrict__ gpart, int group
   }
 }
 
-template <typename T, typename Acc, int VEC, int NCH>
+template <typename T, typename Acc, int VEC, int NCH, bool FULL>
 void launch_t(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
   const T* X = static_cast<const T*>(a.X);
   const T* Y = static_cast<const T*>(a.Y);
   if (Y) {
-    resid_grad_kernel<T, Acc, VEC, NCH, true><<<pl.blocks, kThreads, 0, s>>>(
+    resid_grad_kernel<T, Acc, VEC, NCH, true, FULL><<<pl.blocks, kThreads, 0, s>>>(
         a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters, pl.ldp,
         a.done);
   } else {
-    resid_grad_kernel<T, Acc, VEC, NCH, false><<<pl.blocks, kThreads, 0, s>>>(
+    resid_grad_kernel<T, Acc, VEC, NCH, false, FULL><<<pl.blocks, kThreads, 0, s>>>(
         a.n, a.d, X, a.ldx, Y, a.incy, a.beta, pl.lpr, a.partial, a.gpart, a.counters, pl.ldp,
         a.done);
   }
 }
 
-template <typename T, typename Acc, int VEC>
+template <typename T, typename Acc, int VEC, bool FULL>
 void launch_nch(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
   switch (pl.nch) {
-    case 1: launch_t<T, Acc, VEC, 1>(pl, a, s); break;
-    case 2: launch_t<T, Acc, VEC, 2>(pl, a, s); break;
-    case 4: launch_t<T, Acc, VEC, 4>(pl, a, s); break;
-    case 8: launch_t<T, Acc, VEC, 8>(pl, a, s); break;
-    case 16: launch_t<T, Acc, VEC, 16>(pl, a, s); break;
+    case 1: launch_t<T, Acc, VEC, 1, FULL>(pl, a, s); break;
+    case 2: launch_t<T, Acc, VEC, 2, FULL>(pl, a, s); break;
+    case 4: launch_t<T, Acc, VEC, 4, FULL>(pl, a, s); break;
+    case 8: launch_t<T, Acc, VEC, 8, FULL>(pl, a, s); break;
+    case 16: launch_t<T, Acc, VEC, 16, FULL>(pl, a, s); break;
     default: fail(SLSE_EUNSUPPORTED, "resid_grad: unsupported chunk count");
   }
 }
@@ -252,9 +378,12 @@ template <typename T, typename Acc>
 void launch_vec(const ResidGradPlan& pl, const ResidGradArgs& a, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
   if (pl.vec == V) {
-    launch_nch<T, Acc, V>(pl, a, s);
+    if (pl.full)
+      launch_nch<T, Acc, V, true>(pl, a, s);
+    else
+      launch_nch<T, Acc, V, false>(pl, a, s);
   } else {
-    launch_nch<T, Acc, 1>(pl, a, s);
+    launch_nch<T, Acc, 1, false>(pl, a, s);
   }
 }
 
@@ -288,6 +417,8 @@ ResidGradPlan plan_resid_grad(int64_t n, int d, slse_dtype storage, const void* 
   if (p2 > 16) fail(SLSE_EUNSUPPORTED, "resid_grad: d too large for this build");
   pl.lpr = lpr;
   pl.nch = p2;
+  pl.full = pl.vec > 1 && d % pl.vec == 0 && (int64_t)p2 * lpr * pl.vec == d;
+  if (const char* e = std::getenv("SLSE_RG_FULL")) pl.full = pl.full && std::atoi(e) != 0;
   pl.ldp = (int)round_up(d + 1, 8);
   const int rows_per_block_step = kWaves * (64 / lpr);
   const int bytes_per_vec = pl.vec * es;

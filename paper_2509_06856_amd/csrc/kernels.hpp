@@ -21,6 +21,7 @@ struct ResidGradPlan {
   int vec = 0;   // elements per vector load
   int nch = 0;   // vector chunks per lane
   int ldp = 0;   // leading dimension of partial rows (>= d + 1)
+  bool full = false;  // d = nch * lpr * vec: every lane's chunks are whole vectors
 };
 
 // lpr_hint > 0 picks the lane-group width (else a default); grid_blocks is the

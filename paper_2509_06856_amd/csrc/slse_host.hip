@@ -402,7 +402,7 @@ void tune_resid_grad(slse_ctx* ctx, const IterBufs& b, int64_t n, int d, slse_dt
   if (ctx->rg_tune.count(key)) return;
   const ResidGradPlan base = plan_resid_grad(n, d, storage, X, ldx, b.grid_blocks, b.max_blocks);
   std::vector<int> lprs;
-  for (int l : {base.lpr / 2, base.lpr, base.lpr * 2})
+  for (int l : {base.lpr / 2, base.lpr, base.lpr * 2, base.lpr * 4})
     if (l >= 1 && l <= 64) lprs.push_back(l);
   std::vector<int> grids;
   for (int g : {ctx->num_cus, 2 * ctx->num_cus, 4 * ctx->num_cus})

@@ -120,6 +120,31 @@ def test_fused_resid_grad_parity(G, n, d, dtype, accum):
     assert abs(rn.item() - 0.5 * r @ r) <= (d + n / 4096 + 64) * u * 0.5 * ((np.abs(Yd) + np.abs(Xd) @ np.abs(beta)) ** 2).sum()
 
 
+@pytest.mark.parametrize("dtype,d,lpr", [(np.float32, 512, 16), (np.float32, 512, 64),
+                                         (np.float32, 128, 32), (np.float64, 256, 8),
+                                         (np.float64, 64, 32)])
+@pytest.mark.parametrize("blocks", [7, 256])
+def test_fused_resid_grad_whole_vector_path(G, dtype, d, lpr, blocks, monkeypatch):
+    # rows that split into whole vectors take the unguarded main loop; the row
+    # count leaves a ragged tail in every block, and the result matches both
+    # the oracle and the guarded path
+    monkeypatch.setenv("SLSE_RG_LPR", str(lpr))
+    monkeypatch.setenv("SLSE_RG_BLOCKS", str(blocks))
+    n = 30011
+    g = np.random.default_rng(d + lpr)
+    X = g.standard_normal((n, d)).astype(dtype)
+    Y = g.standard_normal(n).astype(dtype)
+    beta = g.standard_normal(d)
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    ref = OS.full_grad(Xd, Yd, beta)
+    bound = _grad_bound(Xd, Yd, beta, U64, 1.0)
+    g_full, _ = G.fused_resid_grad(dev(X), dev(Y), dev(beta))
+    monkeypatch.setenv("SLSE_RG_FULL", "0")
+    g_guard, _ = G.fused_resid_grad(dev(X), dev(Y), dev(beta))
+    assert np.all(np.abs(g_full.cpu().numpy() - ref) <= bound)
+    assert np.all(np.abs(g_guard.cpu().numpy() - ref) <= bound)
+
+
 def test_fused_resid_grad_padded_ld_null_y_and_empty(G):
     g = np.random.default_rng(5)
     Xw = g.standard_normal((9000, 40))
