@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "seconds to 1e-10 rel. error vs FP64 OLS; resid-grad HBM GB/s; mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -103,6 +104,55 @@ def time_resid_grad(G, torch, X, Y, beta, reps=20):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
+def time_calls(torch, fn, reps=3):
+    """Average device seconds of fn() over reps calls (HIP events, current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def measure_kernels(G, torch, X, Y, m, r, seed):
+    """Sketch kernels and a device copy on the workload's own data (each sketch
+    call is one slse_sketch_apply, index maps included)."""
+    N, d = X.shape
+    row = (d + 1) * X.element_size()
+    out = {}
+    t = time_calls(torch, lambda: G.sketch_apply(X, Y, "srht", seed, [m[-1]], r))
+    alg = (N + m[-1] + r) * row
+    out["srht"] = {"ms": t * 1e3, "GBs": alg / t / 1e9, "frac_of_peak": alg / t / 1e9 / HBM_PEAK_GBS,
+                   "algorithmic_bytes": alg,
+                   "note": "read [X|Y] once, write m_K + r sampled rows; two passes over a padded workspace"}
+    t = time_calls(torch, lambda: G.sketch_apply(X, Y, "countsketch", seed, m, r))
+    alg = (N + sum(m) + r) * row
+    out["countsketch"] = {"ms": t * 1e3, "GBs": alg / t / 1e9,
+                          "frac_of_peak": alg / t / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg,
+                          "note": "read [X|Y] once, write every level and the r Hessian buckets"}
+    if X.dtype == torch.float32:
+        # the Gaussian sketch is a dense contraction: report it against the BF16 MFMA peak
+        mg = [r]
+        t = time_calls(torch, lambda: G.sketch_apply(X, Y, "gaussian", seed, mg, r, bf16=True), reps=2)
+        flops = 2.0 * (mg[-1] + r) * N * (d + 1)
+        out["gaussian_bf16"] = {"ms": t * 1e3, "TFLOPs": flops / t / 1e12,
+                                "frac_of_peak": flops / t / 1e12 / BF16_PEAK_TFLOPS,
+                                "flops": flops, "sketch_rows": mg[-1] + r,
+                                "note": "G generated on the fly (Philox + Box-Muller), BF16 MFMA, FP32 accumulation"}
+    Z = torch.empty_like(X)
+    t = time_calls(torch, lambda: Z.copy_(X))
+    out["device_copy_GBs"] = 2 * X.numel() * X.element_size() / t / 1e9
+    del Z
+    torch.cuda.empty_cache()
+    for k in ("srht", "countsketch"):
+        out[k]["frac_of_copy"] = out[k]["GBs"] / out["device_copy_GBs"]
+    return out
+
+
 def cpu_baseline(name, d, params_gpu, s_star, tol, n_sample):
     """The oracle's SLSE-FRS, timed on a same-recipe sample of n_sample rows."""
     from threadpoolctl import threadpool_info
@@ -119,6 +169,83 @@ def cpu_baseline(name, d, params_gpu, s_star, tol, n_sample):
     t = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return t, rel_err(beta, bstar), threads
+
+
+def bench_backward(args, G, torch, dev):
+    """Adjoint of beta_hat for L = w^T beta_hat on the backward workload (2^20 x 256,
+    float32): lambda by the sketch-preconditioned iteration, then the fused
+    rank-2 pass; errors against the stored FP64 oracle lambda and beta_star."""
+    from slse_inputs import fingerprint, make_problem, sketch_seed
+
+    ref = load_reference("backward")
+    prob = make_problem("backward")
+    if fingerprint(prob.X, prob.Y) != ref["fingerprint"]:
+        print("regenerated backward data differ from the stored reference", file=sys.stderr)
+        sys.exit(3)
+    N, d = prob.n, prob.d
+    X = torch.from_numpy(prob.X).to(dev)
+    Y = torch.from_numpy(prob.Y).to(dev)
+    bstar = np.asarray(ref["beta_star"])
+    lam_ref = np.asarray(ref["lambda"])
+    w = torch.from_numpy(np.asarray(ref["w"])).to(dev)
+    m = G.paper_schedule(N, d)
+    params = G.Params(kind="srht", seed=sketch_seed("backward"), m=m, a=[2] * len(m), r=6 * d,
+                      precision="mixed")
+    s_star, _ = calibrate(G, torch, X, Y, params, bstar, args.tol, args.s_cap)
+    if s_star is None:
+        print("forward solve did not reach the tolerance", file=sys.stderr)
+        sys.exit(4)
+    params.s_max = s_star
+    beta, _ = G.solve(X, Y, params)
+    # lambda uses the same preconditioned iteration: the forward count, doubled
+    # until the adjoint reaches 1e-9 against the oracle lambda
+    for s_lam in (s_star, 2 * s_star, 4 * s_star):
+        params.s_max = s_lam
+        dX, dY, lam = G.backward(X, Y, params, beta, w, grad_dtype=torch.float64)
+        e_lam = rel_err(lam.cpu().numpy(), lam_ref)
+        if e_lam < 1e-9:
+            break
+    Xd = prob.X.astype(np.float64)
+    u = Xd @ lam_ref
+    r = prob.Y.astype(np.float64) - Xd @ bstar
+    e_dY = float(np.linalg.norm(dY.cpu().numpy() - u) / np.linalg.norm(u))
+    dXg = dX.cpu().numpy()
+    ref_dX = np.outer(r, lam_ref)
+    ref_dX -= np.outer(u, bstar)
+    e_dX = float(np.linalg.norm(dXg - ref_dX) / np.linalg.norm(ref_dX))
+    e_max = float(np.abs(dXg - ref_dX).max())
+    del dX, dY, dXg, ref_dX, Xd
+    log(f"adjoint: {s_lam} steps, lambda err {e_lam:.2e}, dX err {e_dX:.2e}, dY err {e_dY:.2e}")
+    # timed: the production call (float32 gradients)
+    t_bw = time_calls(torch, lambda: G.backward(X, Y, params, beta, w), reps=args.steps)
+    # the rank-2 pass alone: lambda_0 = M w and one read of [X|Y], one write of [dX|dY]
+    p0 = G.Params(**{**params.__dict__, "s_max": 0})
+    t_k9 = time_calls(torch, lambda: G.backward(X, Y, p0, beta, w), reps=args.steps)
+    k9_bytes = 2 * N * (d + 1) * 4
+    nb = N * d * 4
+    t_k = time_resid_grad(G, torch, X, None, beta)
+    gbs = nb / t_k / 1e9
+    log(f"backward: {t_bw * 1e3:.2f} ms; rank-2 pass {t_k9 * 1e3:.3f} ms "
+        f"({k9_bytes / t_k9 / 1e9:.0f} GB/s); lambda sweep {t_k * 1e3:.3f} ms ({gbs:.0f} GB/s)")
+    out = {
+        "metric": METRIC, "value": t_bw, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_bw * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage, f64 accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"backward: N={N}, d={d}, X iid N(0,1) float32, L = w^T beta_hat",
+                   "adjoint_steps": s_lam, "lambda_rel_err": e_lam, "dX_rel_err_fro": e_dX,
+                   "dX_max_abs_err": e_max, "dY_rel_err": e_dY, "forward_stage2_steps": s_star},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "resid_grad_kernel with Y = 0 (the lambda sweeps)",
+                     "algorithmic_bytes": nb},
+        "cpu_baseline": None,
+        "kernels": {"adjoint_rank2_pass": {"ms": t_k9 * 1e3, "GBs": k9_bytes / t_k9 / 1e9,
+                                           "frac_of_peak": k9_bytes / t_k9 / 1e9 / HBM_PEAK_GBS,
+                                           "algorithmic_bytes": k9_bytes,
+                                           "note": "s_max = 0 backward: lambda_0 = M w plus the fused pass"}},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(args, G, torch, dev):
@@ -221,11 +348,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond", "batched"])
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond", "batched", "backward"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--s-cap", type=int, default=60)
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sketches", action="store_true",
+                    help="skip the sketch-kernel and device-copy measurements")
     ap.add_argument("--cpu-rows", type=int, default=1 << 17)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only loop the fused residual-gradient kernel (for counter runs)")
@@ -249,6 +378,8 @@ def main():
     name = args.workload
     if name == "batched":
         return bench_batched(args, G, torch, dev)
+    if name == "backward":
+        return bench_backward(args, G, torch, dev)
     ref = load_reference(name)
     beta_star = np.asarray(ref["beta_star"])
 
@@ -319,6 +450,15 @@ def main():
         del X64, Y64
         torch.cuda.empty_cache()
 
+    kernels = None
+    if not args.no_sketches:
+        kernels = measure_kernels(G, torch, X, Y, m, 6 * d, params.seed)
+        kernels["resid_grad"] = {"ms": t_k * 1e3, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+                                 "frac_of_copy": gbs / kernels["device_copy_GBs"]}
+        log("kernels: " + ", ".join(
+            f"{k} {v['ms']:.2f} ms" + (f" {v['GBs']:.0f} GB/s" if "GBs" in v else f" {v['TFLOPs']:.0f} TFLOP/s")
+            for k, v in kernels.items() if isinstance(v, dict)) + f"; device copy {kernels['device_copy_GBs']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu:
         n_s = min(args.cpu_rows, N)
@@ -364,6 +504,7 @@ def main():
             "algorithmic_bytes": bytes_per_sweep,
         },
         "cpu_baseline": cpu,
+        "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
 
