@@ -2,12 +2,16 @@
 // alternative sketching matrix of Sec. 5.4).
 //
 // CountSketch: column j of S_K has the single entry s(j) in row h(j), so
-// S_K [X|Y] adds s(j) [x_j | y_j] into bucket h(j).  One lane group per row
-// reads the row once and scatters it with float atomics into the largest
-// level (m_K buckets) and into the Hessian sketch (r buckets).  Smaller levels
-// use the bucket h(j) mod m_i, so level i is level i+1 folded in halves:
-// A_i[k] = sum_{t = k mod m_i} A_{i+1}[t].  Sums land in an order set by the
-// atomics: results agree with any other order to rounding, not bit for bit.
+// S_K [X|Y] adds s(j) [x_j | y_j] into bucket h(j).  Instead of scattering
+// rows with float atomics, the rows are first listed per bucket (integer
+// counts, an exclusive scan, a fill that writes each row's index with its
+// sign folded in), and each output row is then gathered: one wave per bucket
+// of the largest level (m_K buckets, a few rows each) and several waves per
+// bucket of the Hessian sketch (r buckets, about N/r rows each; their partial
+// rows are added in a fixed order).  Smaller levels use the bucket h(j) mod
+// m_i, so level i is level i+1 folded in halves: A_i[k] = sum_{t = k mod m_i}
+// A_{i+1}[t].  The order of the rows inside a bucket list is set by the fill's
+// atomics, so sums agree with any other order to rounding, not bit for bit.
 //
 // Gaussian: A = G [X|Y] with G_kj iid N(0, 1) drawn on the fly (Philox block
 // (j, k >> 3) -> four Box-Muller pairs).  Tiled 64 (sketch rows) x 64
@@ -35,31 +39,212 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void cs_scatter_kernel(int64_t n, int d, const T* __restrict__ X,
-                                                              int64_t ldx, const T* __restrict__ Y,
-                                                              uint64_t seed, uint64_t mK_mask,
-                                                              T* __restrict__ AK, int64_t lda,
-                                                              int64_t r, T* __restrict__ Ahat,
-                                                              int64_t ldah, int lpr) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int gpw = 64 / lpr;
-  const int grp = lane / lpr;
-  const int l = lane - grp * lpr;
-  const int64_t stride = (int64_t)gridDim.x * kWaves * gpw;
-  for (int64_t row = ((int64_t)blockIdx.x * kWaves + wave) * gpw + grp; row < n; row += stride) {
+constexpr int kHistLds = 8192;  // Hessian buckets counted in LDS up to this many
+
+// bucket sizes of the largest level and of S_hat
+template <bool LDS_H>
+__global__ __launch_bounds__(kThreads) void cs_count_kernel(int64_t n, uint64_t seed,
+                                                            uint64_t mK_mask, int64_t r,
+                                                            int* __restrict__ cntK,
+                                                            int* __restrict__ cntH) {
+  __shared__ int hist[LDS_H ? kHistLds : 1];
+  if constexpr (LDS_H) {
+    for (int k = threadIdx.x; k < r; k += kThreads) hist[k] = 0;
+    __syncthreads();
+  }
+  for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * kThreads) {
     uint64_t h, hh;
     int sg, sh;
-    rng::cs_hash(seed, (uint64_t)row, mK_mask, h, sg);
-    rng::cs_hash_hat(seed, (uint64_t)row, (uint64_t)r, hh, sh);
-    T* a = AK + (int64_t)h * lda;
-    T* b = Ahat + (int64_t)hh * ldah;
-    for (int col = l; col <= d; col += lpr) {
-      const T v = col < d ? X[row * ldx + col] : Y[row];
-      atomicAdd(a + col, sg > 0 ? v : -v);
-      atomicAdd(b + col, sh > 0 ? v : -v);
+    rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+    atomicAdd(cntK + h, 1);
+    if constexpr (LDS_H)
+      atomicAdd(hist + hh, 1);
+    else
+      atomicAdd(cntH + hh, 1);
+  }
+  if constexpr (LDS_H) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < r; k += kThreads)
+      if (hist[k]) atomicAdd(cntH + k, hist[k]);
+  }
+}
+
+// exclusive scan of n ints in three steps: per-block scans of kScanTile
+// elements with block totals, one block scanning the totals, then the carry
+constexpr int kScanTile = kThreads * 8;
+
+__global__ __launch_bounds__(kThreads) void scan_tiles_kernel(const int* __restrict__ in,
+                                                              int* __restrict__ out, int64_t n,
+                                                              int* __restrict__ totals) {
+  __shared__ int s_w[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  int v[8];
+  int run = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    const int t = v[q];
+    v[q] = run;  // exclusive inside the thread
+    run += t;
+  }
+  // inclusive scan of the thread totals across the block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int wave_off = 0;
+  for (int w = 0; w < wave; ++w) wave_off += s_w[w];
+  const int excl = x - run + wave_off;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (base + q < n) out[base + q] = v[q] + excl;
+  if (threadIdx.x == kThreads - 1) totals[blockIdx.x] = excl + run;
+}
+
+// one block: exclusive scan of the tile totals in place, grand total to *total
+__global__ __launch_bounds__(kThreads) void scan_totals_kernel(int* __restrict__ totals, int64_t nt,
+                                                               int* __restrict__ total) {
+  __shared__ int s_w[kWaves];
+  __shared__ int s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t b0 = 0; b0 < nt; b0 += kThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const int v = i < nt ? totals[i] : 0;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    int wave_off = 0;
+    for (int w = 0; w < wave; ++w) wave_off += s_w[w];
+    const int carry = s_carry;
+    if (i < nt) totals[i] = carry + wave_off + x - v;
+    __syncthreads();
+    if (threadIdx.x == kThreads - 1) s_carry = carry + wave_off + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ void scan_carry_kernel(int* __restrict__ out, int64_t n, const int* __restrict__ totals) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += totals[i / kScanTile];
+}
+
+// list every row in its two buckets: entry = j, or ~j when the sign is -1
+__global__ __launch_bounds__(kThreads) void cs_fill_kernel(int64_t n, uint64_t seed, uint64_t mK_mask,
+                                                           int64_t r, int* __restrict__ curK,
+                                                           int* __restrict__ listK,
+                                                           int* __restrict__ curH,
+                                                           int* __restrict__ listH) {
+  for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * kThreads) {
+    uint64_t h, hh;
+    int sg, sh;
+    rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+    listK[atomicAdd(curK + h, 1)] = sg > 0 ? (int)j : ~(int)j;
+    listH[atomicAdd(curH + hh, 1)] = sh > 0 ? (int)j : ~(int)j;
+  }
+}
+
+// out row (bucket b, part p of P): sum of s(j) [x_j | y_j] over list entries
+// [off[b] + p len / P, off[b] + (p + 1) len / P), len = off[b+1] - off[b].
+// One wave per (bucket, part); a lane holds VEC columns of a 64 VEC-column
+// chunk, eight list entries in flight.
+template <typename T, int VEC>
+__global__ __launch_bounds__(kThreads) void cs_gather_kernel(int64_t nb, int parts, int d,
+                                                             const T* __restrict__ X, int64_t ldx,
+                                                             const T* __restrict__ Y,
+                                                             const int* __restrict__ off,
+                                                             const int* __restrict__ list,
+                                                             T* __restrict__ out, int64_t ldo) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = nb * parts;
+  for (int64_t w = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); w < nw;
+       w += (int64_t)gridDim.x * kWaves) {
+    const int64_t b = w / parts;
+    const int p = (int)(w % parts);
+    const int o0 = off[b], len = off[b + 1] - o0;
+    const int e0 = o0 + (int)((int64_t)len * p / parts);
+    const int e1 = o0 + (int)((int64_t)len * (p + 1) / parts);
+    T* orow = out + w * ldo;
+    for (int c0 = 0; c0 < d; c0 += 64 * VEC) {
+      const int col = c0 + lane * VEC;
+      T acc[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] = 0;
+      const bool whole = col + VEC <= d;
+      for (int e = e0; e < e1; e += 8) {
+        T x[8][VEC];
+        int neg = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int ent = e + u < e1 ? list[e + u] : 0;
+          const bool ok = e + u < e1;
+          const int64_t j = ent < 0 ? (int64_t)~ent : (int64_t)ent;
+          neg |= (ent < 0 ? 1 : 0) << u;
+          const T* xr = X + j * ldx + col;
+          if (ok && whole) {
+            if constexpr (VEC > 1) {
+              typedef T V __attribute__((ext_vector_type(VEC)));
+              const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) x[u][v] = t[v];
+            } else {
+              x[u][0] = __builtin_nontemporal_load(xr);
+            }
+          } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) x[u][v] = (ok && col + v < d) ? xr[v] : (T)0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] += ((neg >> u) & 1) ? -x[u][v] : x[u][v];
+      }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        if (col + v < d) orow[col + v] = acc[v];
+    }
+    // the Y column: lanes split the list, then a wave sum in lane order
+    T yacc = 0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const int ent = list[e];
+      const int64_t j = ent < 0 ? (int64_t)~ent : (int64_t)ent;
+      const T y = Y[j];
+      yacc += ent < 0 ? -y : y;
+    }
+    for (int m = 32; m > 0; m >>= 1) yacc += __shfl_xor(yacc, m, 64);
+    if (lane == 0) orow[d] = yacc;
+  }
+}
+
+// dst[b] = sum over the parts of bucket b in part order
+template <typename T>
+__global__ void cs_parts_kernel(const T* __restrict__ part, int parts, int64_t nb, int cols,
+                                int64_t ldp, T* __restrict__ dst, int64_t ldd) {
+  const int64_t n = nb * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / cols;
+    const int c = (int)(e % cols);
+    T t = 0;
+    for (int q = 0; q < parts; ++q) t += part[(b * parts + q) * ldp + c];
+    dst[b * ldd + c] = t;
   }
 }
 
@@ -295,25 +480,121 @@ __global__ void debug_gauss_kernel(uint64_t seed, uint64_t stream, int64_t k0, i
 
 int grid1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 8192)); }
 
+// parts of each Hessian bucket: about 1024 listed rows per wave
+int cs_hat_parts(int64_t N, int64_t r) {
+  const int64_t per = ceil_div(std::max<int64_t>(N, 1), std::max<int64_t>(r, 1));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(per, 1024)));
+}
+
+__global__ void copy_i32_kernel(const int* __restrict__ src, int* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void copy_i32(const int* src, int* dst, int64_t n, hipStream_t s) {
+  copy_i32_kernel<<<grid1(n), 256, 0, s>>>(src, dst, n);
+  SLSE_LAUNCH_CHECK();
+}
+
+// Scratch of the bucket lists, carved from CountSketchArgs::scratch.
+struct CsScratch {
+  int *cntK, *offK, *listK, *cntH, *offH, *listH, *totals;
+  void* partH;
+  size_t bytes;
+};
+
+CsScratch cs_scratch(const CountSketchArgs& a) {
+  const int64_t mK = a.m[a.K - 1];
+  const int parts = cs_hat_parts(a.N, a.r);
+  const int64_t ntiles = ceil_div(std::max<int64_t>({mK, a.r, 1}), (int64_t)kScanTile);
+  const size_t es = dtype_size(a.t);
+  char* p = static_cast<char*>(a.scratch);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + o : nullptr;
+    o += (size_t)round_up((int64_t)bytes, 256);
+    return q;
+  };
+  CsScratch c;
+  c.cntK = reinterpret_cast<int*>(take(sizeof(int) * mK));
+  c.offK = reinterpret_cast<int*>(take(sizeof(int) * (mK + 1)));
+  c.listK = reinterpret_cast<int*>(take(sizeof(int) * a.N));
+  c.cntH = reinterpret_cast<int*>(take(sizeof(int) * a.r));
+  c.offH = reinterpret_cast<int*>(take(sizeof(int) * (a.r + 1)));
+  c.listH = reinterpret_cast<int*>(take(sizeof(int) * a.N));
+  c.totals = reinterpret_cast<int*>(take(sizeof(int) * ntiles));
+  c.partH = parts > 1 ? take(es * (size_t)a.r * parts * (a.d + 1)) : nullptr;
+  c.bytes = o;
+  return c;
+}
+
+void scan_exclusive(const int* in, int* out, int64_t n, int* totals, hipStream_t s) {
+  const int64_t nt = ceil_div(std::max<int64_t>(n, 1), (int64_t)kScanTile);
+  scan_tiles_kernel<<<(unsigned)nt, kThreads, 0, s>>>(in, out, n, totals);
+  scan_totals_kernel<<<1, kThreads, 0, s>>>(totals, nt, out + n);
+  scan_carry_kernel<<<(unsigned)ceil_div(std::max<int64_t>(n, 1), 256), 256, 0, s>>>(out, n, totals);
+  SLSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void gather(int64_t nb, int parts, const CountSketchArgs& a, const int* off, const int* list, T* out,
+            int64_t ldo, hipStream_t s) {
+  const int64_t waves = nb * parts;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(waves, kWaves), 65536));
+  const T* X = static_cast<const T*>(a.X);
+  const T* Y = static_cast<const T*>(a.Y);
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((a.ldx * (int64_t)sizeof(T)) % 16 == 0);
+  if (vec)
+    cs_gather_kernel<T, V><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
+  else
+    cs_gather_kernel<T, 1><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
+  SLSE_LAUNCH_CHECK();
+}
+
 template <typename T>
 void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
+  if (a.N >= (int64_t(1) << 31)) fail(SLSE_EUNSUPPORTED, "countsketch: N >= 2^31 rows");
   T* A = static_cast<T*>(a.A);
   T* Ah = static_cast<T*>(a.Ahat);
   int64_t rows_A = 0;
   for (int i = 0; i < a.K; ++i) rows_A += a.m[i];
-  fill_kernel<T><<<grid1(rows_A * (a.d + 1)), 256, 0, s>>>(A, rows_A, a.d + 1, a.lda);
-  fill_kernel<T><<<grid1(a.r * (a.d + 1)), 256, 0, s>>>(Ah, a.r, a.d + 1, a.ldah);
+  const int64_t mK = a.m[a.K - 1];
+  const CsScratch sc = cs_scratch(a);
+  // 1. bucket sizes
+  fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
+  fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
+  const unsigned rb = (unsigned)grid1(a.N);
+  if (a.r <= kHistLds)
+    cs_count_kernel<true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.cntH);
+  else
+    cs_count_kernel<false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.cntH);
   SLSE_LAUNCH_CHECK();
-  const int64_t offK = rows_A - a.m[a.K - 1];
-  int lpr = 1;
-  while (lpr < 64 && lpr * 4 <= a.d + 1) lpr *= 2;
-  const int rows_per_block = kWaves * (64 / lpr);
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.N, rows_per_block), 8192));
-  cs_scatter_kernel<T><<<blocks, kThreads, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
-                                                   static_cast<const T*>(a.Y), a.seed,
-                                                   (uint64_t)a.m[a.K - 1] - 1, A + offK * a.lda,
-                                                   a.lda, a.r, Ah, a.ldah, lpr);
+  // 2. offsets; the counts become the fill cursors
+  scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
+  scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
+  copy_i32(sc.offK, sc.cntK, mK, s);
+  copy_i32(sc.offH, sc.cntH, a.r, s);
+  // 3. lists
+  cs_fill_kernel<<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.listK,
+                                         sc.cntH, sc.listH);
   SLSE_LAUNCH_CHECK();
+  // 4. gathers: the largest level straight into A, S_hat through its parts
+  const int64_t offK = rows_A - mK;
+  gather<T>(mK, 1, a, sc.offK, sc.listK, A + offK * a.lda, a.lda, s);
+  const int parts = cs_hat_parts(a.N, a.r);
+  if (parts == 1) {
+    gather<T>(a.r, 1, a, sc.offH, sc.listH, Ah, a.ldah, s);
+  } else {
+    T* part = static_cast<T*>(sc.partH);
+    const int64_t ldp = a.d + 1;
+    gather<T>(a.r, parts, a, sc.offH, sc.listH, part, ldp, s);
+    cs_parts_kernel<T><<<grid1(a.r * (a.d + 1)), 256, 0, s>>>(part, parts, a.r, a.d + 1, ldp, Ah,
+                                                             a.ldah);
+    SLSE_LAUNCH_CHECK();
+  }
+  // 5. smaller levels by folding
   int64_t off_hi = offK;
   for (int i = a.K - 2; i >= 0; --i) {
     const int64_t off_lo = off_hi - a.m[i];
@@ -357,7 +638,10 @@ void gaussian_t(const GaussianArgs& a, hipStream_t s) {
 
 }  // namespace
 
+size_t countsketch_scratch_bytes(const CountSketchArgs& a) { return cs_scratch(a).bytes; }
+
 void launch_countsketch(const CountSketchArgs& a, hipStream_t s) {
+  if (!a.scratch) fail(SLSE_EINVAL, "countsketch: no scratch buffer");
   if (a.t == SLSE_F64)
     countsketch_t<double>(a, s);
   else if (a.t == SLSE_F32)

@@ -146,7 +146,9 @@ struct CountSketchArgs {
   int64_t lda = 0;
   void* Ahat = nullptr;
   int64_t ldah = 0;
+  void* scratch = nullptr;  // countsketch_scratch_bytes(*this) bytes: the bucket lists
 };
+size_t countsketch_scratch_bytes(const CountSketchArgs& a);
 void launch_countsketch(const CountSketchArgs& a, hipStream_t s);
 
 struct GaussianArgs {

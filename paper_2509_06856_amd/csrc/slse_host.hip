@@ -191,7 +191,8 @@ void fill_layout(const SketchShape& s, slse_sketch_layout* L) {
 
 // Reserve every scratch buffer the sketch needs (no kernel launched).
 void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs* srht,
-                    GaussianArgs* ga, GaussianArgs* gh, bool gauss_bf16 = false) {
+                    GaussianArgs* ga, GaussianArgs* gh, bool gauss_bf16 = false,
+                    void** cs_scratch = nullptr) {
   if (s.kind == SLSE_SRHT) {
     srht->t = t;
     srht->N = s.N;
@@ -205,6 +206,16 @@ void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs*
     srht->slotH = ctx->arena.get_t<int32_t>("srht_slotH", s.n_pad);
     const size_t zb = srht_z_bytes(*srht);
     srht->Z = zb ? ctx->arena.get("srht_Z", zb) : nullptr;
+  } else if (s.kind == SLSE_COUNTSKETCH) {
+    CountSketchArgs c;
+    c.t = t;
+    c.N = s.N;
+    c.d = (int)s.d;
+    c.m = s.m.data();
+    c.K = s.K;
+    c.r = s.r;
+    void* p = ctx->arena.get("cs_lists", countsketch_scratch_bytes(c));
+    if (cs_scratch) *cs_scratch = p;
   } else if (s.kind == SLSE_GAUSSIAN) {
     for (GaussianArgs* g : {ga, gh}) {
       g->t = t;
@@ -227,7 +238,7 @@ void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs*
 
 void enqueue_sketch(const SketchShape& s, uint64_t seed, const void* X, int64_t ldx, const void* Y,
                     slse_dtype t, void* A, int64_t lda, void* Ahat, int64_t ldah, SrhtArgs srht,
-                    GaussianArgs ga, GaussianArgs gh, hipStream_t st) {
+                    GaussianArgs ga, GaussianArgs gh, hipStream_t st, void* cs_scratch = nullptr) {
   if (s.kind == SLSE_SRHT) {
     srht.X = X;
     srht.ldx = ldx;
@@ -254,6 +265,7 @@ void enqueue_sketch(const SketchShape& s, uint64_t seed, const void* X, int64_t 
     c.lda = lda;
     c.Ahat = Ahat;
     c.ldah = ldah;
+    c.scratch = cs_scratch;
     launch_countsketch(c, st);
   } else {
     for (GaussianArgs* g : {&ga, &gh}) {
@@ -536,6 +548,7 @@ struct SolvePlan {
   int64_t ldah = 0;
   SrhtArgs srht;
   GaussianArgs ga, gh;
+  void* cs = nullptr;  // CountSketch bucket lists
   FactorBufs f;
   IterBufs it;
 };
@@ -577,7 +590,7 @@ SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params*
   pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
   // a Gaussian sketch of FP32 data in the mixed form runs on the matrix cores (BF16 operands)
   reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh,
-                 q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN);
+                 q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN, &pl.cs);
   pl.f = reserve_factor(ctx, pl.sk.r, p->d, q->factor);
   pl.it = reserve_iter(ctx, p->d, "it");
   return pl;
@@ -588,7 +601,7 @@ void enqueue_solve(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem*
   const int d = (int)p->d;
   const SketchShape& sk = pl.sk;
   enqueue_sketch(sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah, pl.srht,
-                 pl.ga, pl.gh, st);
+                 pl.ga, pl.gh, st, pl.cs);
   enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
   Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx};
   S.start(q->beta0, q->trajectory);
@@ -773,7 +786,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     pl.A = ctx->arena.get("A", (size_t)pl.sk.rows_A * pl.lda * es);
     pl.Ahat = ctx->arena.get("Ahat", (size_t)pl.sk.r * pl.ldah * es);
     reserve_sketch(ctx, pl.sk, pl.st_t, &pl.srht, &pl.ga, &pl.gh,
-                   q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN);
+                   q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN, &pl.cs);
   }
   IterBufs ib = reserve_iter(ctx, p->d, "adj");
   double* lam0 = ctx->arena.get_t<double>("adj_lam0", d);
@@ -781,7 +794,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
   if (ctx->arena.grew) ctx->drop_graphs();
   if (!reuse) {
     enqueue_sketch(pl.sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah,
-                   pl.srht, pl.ga, pl.gh, st);
+                   pl.srht, pl.ga, pl.gh, st, pl.cs);
     enqueue_factor(pl.f, pl.sk.r, d, pl.Ahat, pl.ldah, pl.st_t, pl.sk.hat_scale, q->factor, st);
     ctx->pre.valid = false;
   }
@@ -876,6 +889,7 @@ struct BatchPlan {
   std::vector<BatchProblem> h_probs;
   SrhtArgs srht;
   GaussianArgs ga, gh;
+  void* cs = nullptr;  // CountSketch bucket lists (sized for the largest problem)
   FactorBufs f;
   // Cholesky route for every problem: one batched factorization
   bool batched_factor = false;
@@ -984,7 +998,7 @@ void enqueue_batch_sketch(const BatchPlan& bp, int b, const slse_problem* ps,
   void* A = bp.Apool + bp.a_off[b];
   void* Ah = bp.Ahpool + bp.ah_off[b];
   enqueue_sketch(sk, qs[b].seed, ps[b].X, ps[b].ldx, ps[b].Y, bp.t, A, bp.lda[b], Ah, bp.lda[b],
-                 sa, ga, gh, st);
+                 sa, ga, gh, st, bp.cs);
 }
 
 // Factor of problem b through the shared scratch (the QR route).
@@ -1029,7 +1043,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   const size_t es = dtype_size(bp.t);
   int64_t a_bytes = 0, ah_bytes = 0, m_n = 0, beta_n = 0, max_npad = 0, max_rows = 0, max_d = 0;
   int64_t max_r = 0;
-  size_t z_bytes = 0, g_bytes = 0;
+  size_t z_bytes = 0, g_bytes = 0, cs_bytes = 0;
   bp.vec = true;
   for (int b = 0; b < B; ++b) {
     bp.sk.push_back(make_sketch_shape(qs[b].kind, ps[b].N, ps[b].d, qs[b].m, qs[b].K, qs[b].r));
@@ -1056,6 +1070,15 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
       sa.p = sk.p;
       srht_plan(sa, 0);
       z_bytes = std::max(z_bytes, srht_z_bytes(sa));
+    } else if (sk.kind == SLSE_COUNTSKETCH) {
+      CountSketchArgs c;
+      c.t = bp.t;
+      c.N = sk.N;
+      c.d = (int)d;
+      c.m = sk.m.data();
+      c.K = sk.K;
+      c.r = sk.r;
+      cs_bytes = std::max(cs_bytes, countsketch_scratch_bytes(c));
     } else if (sk.kind == SLSE_GAUSSIAN) {
       GaussianArgs g1, g2;
       g1.t = g2.t = bp.t;
@@ -1081,6 +1104,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bp.srht.slotA = ctx->arena.get_t<int32_t>("srht_slotA", (size_t)max_npad);
   bp.srht.slotH = ctx->arena.get_t<int32_t>("srht_slotH", (size_t)max_npad);
   bp.srht.Z = z_bytes ? ctx->arena.get("srht_Z", z_bytes) : nullptr;
+  bp.cs = cs_bytes ? ctx->arena.get("cs_lists", cs_bytes) : nullptr;
   bp.srht.t = bp.t;
   bp.ga.t = bp.gh.t = bp.t;
   bp.ga.stream_id = 7;
@@ -1381,11 +1405,12 @@ slse_status slse_sketch_apply(slse_ctx* ctx, slse_sketch_kind kind, uint64_t see
     SketchShape s = make_sketch_shape(kind, N, d, m, K, r);
     SrhtArgs srht;
     GaussianArgs ga, gh;
+    void* cs = nullptr;
     ctx->arena.grew = false;
-    reserve_sketch(ctx, s, in_t, &srht, &ga, &gh, bf16);
+    reserve_sketch(ctx, s, in_t, &srht, &ga, &gh, bf16, &cs);
     if (ctx->arena.grew) ctx->drop_graphs();
     ctx->pre.valid = false;
-    enqueue_sketch(s, seed, X, ldx, Y, in_t, A, lda, Ahat, ldah, srht, ga, gh, as_stream(stream));
+    enqueue_sketch(s, seed, X, ldx, Y, in_t, A, lda, Ahat, ldah, srht, ga, gh, as_stream(stream), cs);
     fill_layout(s, layout_out);
     return SLSE_OK;
   });

@@ -236,12 +236,17 @@ def test_srht_two_eleven_stage_passes(G):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_countsketch_parity(G, dtype):
-    N, d = 20000, 19
-    g = np.random.default_rng(3)
+@pytest.mark.parametrize("N,d,m,r", [
+    (20000, 19, [128, 256, 512], 120),
+    (300000, 5, [1024, 2048], 24),        # ~12500 rows per S_hat bucket: 13 parts per bucket
+    (60000, 3, [16384, 32768], 9000),     # S_hat counted with global atomics (r > 8192)
+    (5000, 33, [2048, 4096], 40),         # many empty buckets in the largest level
+    (7, 2, [2, 4], 3),                    # tiny
+])
+def test_countsketch_parity(G, dtype, N, d, m, r):
+    g = np.random.default_rng(N + d)
     X = g.standard_normal((N, d)).astype(dtype)
     Y = g.standard_normal(N).astype(dtype)
-    m, r = [128, 256, 512], 120
     A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "countsketch", 55, m, r)
     ref = S.countsketch(X.astype(np.float64), Y.astype(np.float64), 55, m, r)
     u = U64 if dtype == np.float64 else U32
