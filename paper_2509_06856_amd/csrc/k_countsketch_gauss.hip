@@ -248,18 +248,17 @@ __global__ void cs_parts_kernel(const T* __restrict__ part, int parts, int64_t n
   }
 }
 
-// dst[k][c] = sum_{q < ratio} src[k + q*m][c], k < m
+// dst[k][c] = sum_{q < ratio} src[k + q*m][c], k < m: rows over blocks,
+// columns over threads (every access coalesced along the row)
 template <typename T>
 __global__ void cs_fold_kernel(const T* __restrict__ src, T* __restrict__ dst, int64_t m, int ratio,
                                int cols, int64_t ld) {
-  const int64_t n = m * cols;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = e / cols;
-    const int c = (int)(e % cols);
-    T t = 0;
-    for (int q = 0; q < ratio; ++q) t += src[(k + q * m) * ld + c];
-    dst[k * ld + c] = t;
+  for (int64_t k = blockIdx.x; k < m; k += gridDim.x) {
+    for (int c = threadIdx.x; c < cols; c += blockDim.x) {
+      T t = 0;
+      for (int q = 0; q < ratio; ++q) t += src[(k + (int64_t)q * m) * ld + c];
+      dst[k * ld + c] = t;
+    }
   }
 }
 
@@ -280,6 +279,24 @@ __device__ __forceinline__ void box_muller8(uint64_t seed, uint64_t stream, uint
     sincosf(6.283185307179586f * u2, &sn, &cs);
     z[2 * q] = rad * cs;
     z[2 * q + 1] = rad * sn;
+  }
+}
+
+// Box-Muller with the hardware transcendentals (v_log_f32 is log2, v_sin_f32
+// and v_cos_f32 take revolutions): about 1e-6 relative, far below the BF16
+// rounding the matrix-core path applies to G afterwards.
+__device__ __forceinline__ void box_muller8_fast(uint64_t seed, uint64_t stream, uint64_t j,
+                                                 uint64_t kblk, float (&z)[8]) {
+  const rng::Words w = rng::philox(j, kblk, 0, 0, seed, stream);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (uint32_t)(w.w[q] & 0xffffffffu);
+    const uint32_t hi = (uint32_t)(w.w[q] >> 32);
+    const float u1 = fmaf((float)lo, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+    const float u2 = fmaf((float)hi, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    z[2 * q] = rad * __builtin_amdgcn_cosf(u2);
+    z[2 * q + 1] = rad * __builtin_amdgcn_sinf(u2);
   }
 }
 
@@ -407,8 +424,8 @@ __global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const
   __shared__ __attribute__((aligned(16))) __bf16 Ws[kNT][kKP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t k0 = (int64_t)blockIdx.y * kMT;
-  const int c0 = blockIdx.x * kNT;
+  const int64_t k0 = (int64_t)blockIdx.x * kMT;
+  const int c0 = blockIdx.y * kNT;
   const int split = blockIdx.z;
   const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
   const int64_t j_begin = (int64_t)split * per;
@@ -425,7 +442,7 @@ __global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const
       const int64_t j = j0 + jj;
       float z[8];
       if (j < j_end) {
-        box_muller8(seed, stream, (uint64_t)j, (uint64_t)((k0 >> 3) + kb), z);
+        box_muller8_fast(seed, stream, (uint64_t)j, (uint64_t)((k0 >> 3) + kb), z);
       } else {
 #pragma unroll
         for (int q = 0; q < 8; ++q) z[q] = 0.0f;
@@ -599,7 +616,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   for (int i = a.K - 2; i >= 0; --i) {
     const int64_t off_lo = off_hi - a.m[i];
     const int ratio = (int)(a.m[i + 1] / a.m[i]);
-    cs_fold_kernel<T><<<grid1(a.m[i] * (a.d + 1)), 256, 0, s>>>(
+    cs_fold_kernel<T><<<(unsigned)std::min<int64_t>(a.m[i], 65536), 256, 0, s>>>(
         A + off_hi * a.lda, A + off_lo * a.lda, a.m[i], ratio, a.d + 1, a.lda);
     SLSE_LAUNCH_CHECK();
     off_hi = off_lo;
@@ -610,7 +627,9 @@ template <typename T>
 void gaussian_mfma_t(const GaussianArgs& a, hipStream_t s) {
   const int cols = a.d + 1;
   const int64_t ldp = round_up(cols, 4);
-  dim3 grid((unsigned)ceil_div(cols, kNT), (unsigned)ceil_div(a.m, kMT), (unsigned)a.splits);
+  // blockIdx.x is the sketch-row block: the blocks that read the same data
+  // rows and columns run side by side and share them through the caches
+  dim3 grid((unsigned)ceil_div(a.m, kMT), (unsigned)ceil_div(cols, kNT), (unsigned)a.splits);
   gauss_mfma_kernel<T><<<grid, 256, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
                                             static_cast<const T*>(a.Y), a.seed, a.stream_id, a.m,
                                             a.splits, a.partial, ldp);

@@ -274,14 +274,15 @@ def test_gaussian_sketch_parity(G, dtype):
     assert np.all(np.abs(Ah.cpu().numpy() - ref["Ahat"]) <= tol)
 
 
-def test_gaussian_sketch_bf16_mfma_parity(G):
+@pytest.mark.parametrize("N,d", [(3000, 37), (2500, 200), (1500, 520)])
+def test_gaussian_sketch_bf16_mfma_parity(G, N, d):
     # BF16 operands (G and [X|Y] rounded to nearest even), FP32 accumulation on
-    # the matrix cores; compared with the oracle on the same rounded operands
-    N, d = 3000, 37
-    g = np.random.default_rng(6)
+    # the matrix cores; compared with the oracle on the same rounded operands.
+    # d = 200 and 520 take the wide tiles (every column in one block)
+    g = np.random.default_rng(6 + d)
     X = g.standard_normal((N, d)).astype(np.float32)
     Y = g.standard_normal(N).astype(np.float32)
-    m, r = [32, 200], 130
+    m, r = [32, 200], max(130, d + 40)
     A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "gaussian", 88, m, r, bf16=True)
     Xb = S.round_to(X, "bf16")
     Yb = S.round_to(Y, "bf16")
