@@ -46,8 +46,13 @@ typedef enum { SLSE_F32 = 0, SLSE_F64 = 1, SLSE_BF16 = 2 } slse_dtype;
 /* Sketch families (Sec. 1.2; SRHT of Sec. 3; CountSketch of Sec. 5.4). */
 typedef enum { SLSE_SRHT = 0, SLSE_COUNTSKETCH = 1, SLSE_GAUSSIAN = 2 } slse_sketch_kind;
 
-/* Factorization of the Hessian sketch: Gram + Cholesky, or a QR
- * (CholeskyQR2, the R factor of the QR of the sketch). */
+/* Factorization of the Hessian sketch (implementation-details appendix):
+ *  SLSE_FACTOR_CHOL  through the Gram matrix (Cholesky; inside the solve the
+ *                    Gram matrix is inverted directly).  Fine while the
+ *                    sketch's condition number is well below u^{-1/2} ~ 1e8.
+ *  SLSE_FACTOR_QR    the R factor of the QR of the sketch by shifted
+ *                    CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput. 2020),
+ *                    for condition numbers up to about u^{-1}. */
 typedef enum { SLSE_FACTOR_CHOL = 0, SLSE_FACTOR_QR = 1 } slse_factor_method;
 
 /* SLSE_PREC_F64: everything in FP64.  SLSE_PREC_MIXED: data stored, sketched

@@ -19,6 +19,8 @@ Readings where the paper is silent:
 The gradient is formed in residual form g = c X^T (Y - X beta) = -c grad f and
 added with +mu.
 """
+import math
+
 import numpy as np
 from scipy.linalg import solve_triangular
 
@@ -97,6 +99,18 @@ def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
         beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
         traj.append(beta.copy())
     return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta)
+
+
+def iteration_lower_bounds(m, d, omega):
+    """Real lower bounds of the stage-1 counts a_2..a_K (Thm lowerBoundai, Sec. 4):
+    a_i >= log_3[((1 + omega) r(i-1, i) + 1) / omega] with
+    r(i-1, i) = sqrt((m_i - d) / (m_{i-1} - d)).  Entry 0 (a_1) is None: its
+    bound (Thm a1, Appendix) needs the unknown errors of the first subproblem."""
+    out = [None]
+    for i in range(1, len(m)):
+        ratio = math.sqrt((m[i] - d) / (m[i - 1] - d))
+        out.append(math.log(((1.0 + omega) * ratio + 1.0) / omega) / math.log(3.0))
+    return out
 
 
 def paper_schedule(n, d, m1_factor=8):

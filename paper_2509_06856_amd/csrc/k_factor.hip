@@ -484,7 +484,27 @@ __global__ __launch_bounds__(256) void gj_update_kernel(int d, int k0, double* _
   }
 }
 
+// G += coef trace(G) I (one block): the diagonal shift of shifted CholeskyQR
+__global__ __launch_bounds__(256) void shift_diag_kernel(int d, double* __restrict__ G, double coef) {
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) t += G[(int64_t)i * d + i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double shift = coef * red[0];
+  for (int i = threadIdx.x; i < d; i += 256) G[(int64_t)i * d + i] += shift;
+}
+
 }  // namespace
+
+void launch_shift_diag(int d, double* G, double coef, hipStream_t s) {
+  shift_diag_kernel<<<1, 256, 0, s>>>(d, G, coef);
+  SLSE_LAUNCH_CHECK();
+}
 
 void launch_spd_inverse(int d, double* G, double* colp, int* info, hipStream_t s) {
   if (d <= 0) return;

@@ -196,6 +196,8 @@ void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr
 // is d x 32 scratch.  info[0] (zero on entry) becomes k0 + 1 of the first
 // pivot block with a non-positive or non-finite pivot.
 void launch_spd_inverse(int d, double* G, double* colp, int* info, hipStream_t s);
+// G += coef * trace(G) * I (d x d, ld = d).
+void launch_shift_diag(int d, double* G, double coef, hipStream_t s);
 // Rinv = R^{-1} (upper triangular, row-major d x d) for upper triangular R.
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s);
 

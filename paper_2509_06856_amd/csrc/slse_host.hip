@@ -329,20 +329,32 @@ void enqueue_factor(const FactorBufs& f, int64_t rows, int d, const void* A, int
   if (method == SLSE_FACTOR_CHOL && !need_R) {
     launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.M, d, st, f.part,
                     f.part_n);
-    launch_fill_i32(f.info, 0, 2, st);
+    launch_fill_i32(f.info, 0, 3, st);
     launch_spd_inverse(d, f.M, f.colp, f.info, st);
     return;
   }
   launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st, f.part, f.part_n);
-  launch_cholesky(d, f.G, d, f.R, d, f.info, st);
   if (method == SLSE_FACTOR_QR) {
-    // CholeskyQR2: Q1 = Ad R1^{-1}, R2 = chol(Q1^T Q1), R = R2 R1
+    // shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa,
+    // SIAM J. Sci. Comput. 2020): a Cholesky of G + s I with
+    // s = 11 (rows d + d (d + 1)) u ||A||_F^2 always exists; Q0 = A R0^{-1} then
+    // has a modest condition number, and two CholeskyQR passes finish the job.
+    // R = R2 R1 R0 matches Householder's R to O(kappa u) for kappa up to ~u^{-1}.
+    const double u = std::ldexp(1.0, -53);
+    launch_shift_diag(d, f.G, 11.0 * ((double)rows * d + (double)d * (d + 1)) * u, st);
+    launch_cholesky(d, f.G, d, f.R, d, f.info, st);                        // R0
     launch_tri_inv(d, f.R, d, f.L, d, st);
     launch_gemm_f64(rows, d, d, 1.0, f.Ad, d, false, f.L, d, false, 0.0, f.Q, d, st, f.part, f.part_n);
     launch_gemm_f64(d, d, rows, 1.0, f.Q, d, true, f.Q, d, false, 0.0, f.G, d, st, f.part, f.part_n);
-    launch_cholesky(d, f.G, d, f.R2, d, f.info + 1, st);
+    launch_cholesky(d, f.G, d, f.R2, d, f.info + 1, st);                   // R1
+    launch_tri_inv(d, f.R2, d, f.L, d, st);
+    launch_gemm_f64(rows, d, d, 1.0, f.Q, d, false, f.L, d, false, 0.0, f.Ad, d, st, f.part, f.part_n);
+    launch_gemm_f64(d, d, rows, 1.0, f.Ad, d, true, f.Ad, d, false, 0.0, f.G, d, st, f.part, f.part_n);
+    launch_cholesky(d, f.G, d, f.L, d, f.info + 2, st);                    // R2
     launch_gemm_f64(d, d, d, 1.0, f.R2, d, false, f.R, d, false, 0.0, f.G, d, st, f.part, f.part_n);
-    launch_copy_f64(f.G, f.R, (int64_t)d * d, st);
+    launch_gemm_f64(d, d, d, 1.0, f.L, d, false, f.G, d, false, 0.0, f.R, d, st, f.part, f.part_n);
+  } else {
+    launch_cholesky(d, f.G, d, f.R, d, f.info, st);
   }
   // M = R^{-1} R^{-T}
   launch_tri_inv(d, f.R, d, f.L, d, st);
@@ -641,12 +653,12 @@ slse_status finish_report(slse_ctx* ctx, const SolvePlan& pl, const slse_params*
                           slse_report* rep, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   (void)ctx;
   int flags[4] = {0, 0, 0, 0};
-  int info[2] = {0, 0};
+  int info[3] = {0, 0, 0};
   SLSE_HIP(hipMemcpyAsync(flags, pl.it.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
   SLSE_HIP(hipMemcpyAsync(info, pl.f.info, sizeof(info), hipMemcpyDeviceToHost, st));
   SLSE_HIP(hipStreamSynchronize(st));
   slse_status status = SLSE_OK;
-  if (info[0] != 0 || info[1] != 0)
+  if (info[0] != 0 || info[1] != 0 || info[2] != 0)
     status = SLSE_ESINGULAR;
   else if (flags[1])
     status = SLSE_ENONFINITE;
@@ -845,11 +857,11 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
   slse_status status = SLSE_OK;
   if (rep) {
     int flags[4] = {0, 0, 0, 0};
-    int info[2] = {0, 0};
+    int info[3] = {0, 0, 0};
     SLSE_HIP(hipMemcpyAsync(flags, ib.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
     SLSE_HIP(hipMemcpyAsync(info, pl.f.info, sizeof(info), hipMemcpyDeviceToHost, st));
     SLSE_HIP(hipStreamSynchronize(st));
-    if (info[0] || info[1]) status = SLSE_ESINGULAR;
+    if (info[0] || info[1] || info[2]) status = SLSE_ESINGULAR;
     else if (flags[1]) status = SLSE_ENONFINITE;
     std::memset(rep, 0, sizeof(*rep));
     rep->status = status;
@@ -879,7 +891,7 @@ struct BatchPlan {
   double* Bpool = nullptr;  // 3 beta buffers per problem
   double* part = nullptr;
   int* flags = nullptr;     // per problem: non-finite
-  int* finfo = nullptr;     // per problem: 2 ints of factor info
+  int* finfo = nullptr;     // per problem: 3 ints of factor info
   BatchStep* d_steps = nullptr;
   int* d_prefix = nullptr;
   BatchProblem* d_probs = nullptr;
@@ -1007,7 +1019,7 @@ void enqueue_batch_factor(const BatchPlan& bp, int b, const slse_problem* ps,
   const SketchShape& sk = bp.sk[b];
   const int d = (int)ps[b].d;
   FactorBufs f = bp.f;
-  f.info = bp.finfo + 2 * b;
+  f.info = bp.finfo + 3 * b;
   enqueue_factor(f, sk.r, d, bp.Ahpool + bp.ah_off[b], bp.lda[b], bp.t, sk.hat_scale, qs[b].factor,
                  st);
   launch_copy_f64(f.M, bp.Mpool + bp.m_off[b], (int64_t)d * d, st);
@@ -1018,7 +1030,7 @@ void enqueue_batch_factor(const BatchPlan& bp, int b, const slse_problem* ps,
 void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_params* qs,
                    hipStream_t st) {
   launch_fill_i32(bp.flags, 0, bp.B, st);
-  launch_fill_i32(bp.finfo, 0, 2 * (int64_t)bp.B, st);
+  launch_fill_i32(bp.finfo, 0, 3 * (int64_t)bp.B, st);
   for (int b = 0; b < bp.B; ++b) enqueue_batch_sketch(bp, b, ps, qs, st);
   if (bp.batched_factor)
     launch_factor_batched(bp.d_jobs, bp.B, bp.dmax, bp.rmax, bp.t, st);
@@ -1099,7 +1111,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bp.Mpool = ctx->arena.get_t<double>("bM", (size_t)m_n);
   bp.Bpool = ctx->arena.get_t<double>("bBeta", (size_t)beta_n);
   bp.flags = ctx->arena.get_t<int>("bFlags", (size_t)B);
-  bp.finfo = ctx->arena.get_t<int>("bInfo", (size_t)2 * B);
+  bp.finfo = ctx->arena.get_t<int>("bInfo", (size_t)3 * B);
   bp.srht.pi_sgn = ctx->arena.get_t<int32_t>("srht_pi", (size_t)max_npad);
   bp.srht.slotA = ctx->arena.get_t<int32_t>("srht_slotA", (size_t)max_npad);
   bp.srht.slotH = ctx->arena.get_t<int32_t>("srht_slotH", (size_t)max_npad);
@@ -1146,7 +1158,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
       j.R = rp + so;
       j.L = lp + so;
       j.M = bp.Mpool + bp.m_off[b];
-      j.info = bp.finfo + 2 * b;
+      j.info = bp.finfo + 3 * b;
       ao += j.rows * d;
       so += d * d;
     }
@@ -1295,13 +1307,13 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   ctx->pre.valid = false;
   slse_status worst = SLSE_OK;
   if (reps) {
-    std::vector<int> flags(B), info(2 * B);
+    std::vector<int> flags(B), info(3 * B);
     SLSE_HIP(hipMemcpyAsync(flags.data(), bp.flags, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-    SLSE_HIP(hipMemcpyAsync(info.data(), bp.finfo, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, st));
+    SLSE_HIP(hipMemcpyAsync(info.data(), bp.finfo, sizeof(int) * 3 * B, hipMemcpyDeviceToHost, st));
     SLSE_HIP(hipStreamSynchronize(st));
     for (int b = 0; b < B; ++b) {
       slse_status sb = SLSE_OK;
-      if (info[2 * b] || info[2 * b + 1])
+      if (info[3 * b] || info[3 * b + 1] || info[3 * b + 2])
         sb = SLSE_ESINGULAR;
       else if (flags[b])
         sb = SLSE_ENONFINITE;
@@ -1433,19 +1445,19 @@ slse_status slse_factor(slse_ctx* ctx, int64_t rows, int64_t d, const void* A, i
     FactorBufs f = reserve_factor(ctx, rows, d, method);
     if (ctx->arena.grew) ctx->drop_graphs();
     ctx->pre.valid = false;
-    launch_fill_i32(f.info, 0, 2, st);
+    launch_fill_i32(f.info, 0, 3, st);
     enqueue_factor(f, rows, (int)d, A, lda, a_t, scale, method, st, true);
     SLSE_HIP(hipMemcpy2DAsync(R, ldr * sizeof(double), f.R, d * sizeof(double), d * sizeof(double),
                               d, hipMemcpyDeviceToDevice, st));
     if (M)
       SLSE_HIP(hipMemcpy2DAsync(M, ldm * sizeof(double), f.M, d * sizeof(double),
                                 d * sizeof(double), d, hipMemcpyDeviceToDevice, st));
-    int info[2] = {0, 0};
+    int info[3] = {0, 0, 0};
     SLSE_HIP(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, st));
     SLSE_HIP(hipStreamSynchronize(st));
-    if (info[0] || info[1]) {
+    if (info[0] || info[1] || info[2]) {
       set_last_error("factorization: non-positive or non-finite pivot at column " +
-                     std::to_string((info[0] ? info[0] : info[1]) - 1));
+                     std::to_string((info[0] ? info[0] : info[1] ? info[1] : info[2]) - 1));
       return SLSE_ESINGULAR;
     }
     return SLSE_OK;

@@ -74,6 +74,24 @@ def paper_params(d, r=None):
     return r, (1.0 - eta) ** 2, eta
 
 
+def auto_a(m, d, omega=0.5, a1=None):
+    """Stage-1 counts from the lower bound of Thm lowerBoundai (Sec. 4): for
+    i >= 2 the smallest integer a_i with 3^{a_i} >= ((1 + omega) r + 1) / omega,
+    r = ((m_i - d) / (m_{i-1} - d))^{1/2}.  a_1 (whose bound, Thm a1, needs the
+    first subproblem's unknown errors) is `a1`, else a_2."""
+    out = []
+    for i in range(1, len(m)):
+        if not m[i - 1] > d:
+            raise ValueError("the bound needs m_{i-1} > d")
+        target = ((1.0 + omega) * ((m[i] - d) / (m[i - 1] - d)) ** 0.5 + 1.0) / omega
+        k = 1
+        while 3.0 ** k < target:
+            k += 1
+        out.append(k)
+    first = a1 if a1 is not None else (out[0] if out else 2)
+    return [first] + out
+
+
 def paper_schedule(n, d, m1_factor=8):
     """m_1 = 8d (rounded up to a power of 2), doubling to the largest power of 2 <= N/2."""
     m1 = 1 << max(0, (m1_factor * d - 1).bit_length())

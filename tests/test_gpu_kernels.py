@@ -320,6 +320,38 @@ def test_factor_parity(G, method, rows, d, kappa):
     assert np.linalg.norm(Mg @ H - np.eye(d)) < kappa ** 2 * 1e3 * d * U64
 
 
+@pytest.mark.parametrize("rows,d,kappa", [(1536, 64, 1e8), (3072, 128, 1e12)])
+def test_factor_qr_ill_conditioned(G, rows, d, kappa):
+    # the Gram matrix has condition number kappa^2 (up to 1e24): only the
+    # shifted CholeskyQR3 route can factor it.  A = Z diag(s) has R = R_Z diag(s),
+    # so R is compared with Householder's after removing the column scale
+    g = np.random.default_rng(rows + d)
+    s = np.logspace(0, -np.log10(kappa), d)
+    A = g.standard_normal((rows, d)) * s[None, :]
+    R, _ = G.factor(dev(A), d, 1.0 / rows, "qr")
+    Rref = O.qr_r(np.sqrt(1.0 / rows) * A)
+    Rg = R.cpu().numpy()
+    assert np.all(np.diag(Rg) > 0)
+    err = np.linalg.norm((Rg - Rref) / s[None, :]) / np.linalg.norm(Rref / s[None, :])
+    assert err < 1e3 * d * U64
+
+
+def test_solve_qr_route_reaches_ls_error_at_kappa_1e8(G):
+    # the paper's recipe X = G D with kappa = 1e8 and sigma^2 = 1e-8: the
+    # prediction error reaches the LS error sigma^2 d (Sec. 5)
+    from slse_inputs import paper_problem
+
+    prob = paper_problem(1 << 15, 32, 1e8, 1e-8)
+    m = G.paper_schedule(prob.n, prob.d)
+    params = G.Params(kind="srht", seed=21, m=m, a=[2] * len(m), r=6 * 32, s_max=60, factor="qr")
+    beta, info = G.solve(dev(prob.X), dev(prob.Y), params)
+    assert info["status"] == "SLSE_OK"
+    bhat, _, _ = O.ols_refined(prob.X, prob.Y)
+    d_gpu = np.sum((prob.X @ (beta.cpu().numpy() - prob.beta_true)) ** 2)
+    d_ls = np.sum((prob.X @ (bhat - prob.beta_true)) ** 2)
+    assert abs(d_gpu / d_ls - 1) < 1e-3
+
+
 def test_factor_singular_reports_esingular(G):
     from paper_2509_06856_amd import _lib
 

@@ -176,3 +176,31 @@ def test_adjoint_matches_finite_differences():
     fX, fY = ADJ.fd_gradient(X, Y, w)
     np.testing.assert_allclose(dX, fX, rtol=1e-6, atol=1e-8)
     np.testing.assert_allclose(dY, fY, rtol=1e-6, atol=1e-8)
+
+
+def test_iteration_lower_bounds_and_binding_schedule():
+    # Thm lowerBoundai: a_i >= log_3[((1 + w) r + 1) / w], r = sqrt((m_i - d)/(m_{i-1} - d))
+    import math
+
+    from oracle import slse as OS
+    from paper_2509_06856_amd.slse import auto_a
+
+    d = 64
+    m = [512 * 2 ** k for k in range(8)]
+    for w in (1 / 16, 1 / 8, 1 / 4, 1 / 2, 1.0):
+        lb = OS.iteration_lower_bounds(m, d, w)
+        assert lb[0] is None
+        # the integer schedule is the ceiling of the real bound
+        a = auto_a(m, d, w, a1=7)
+        assert a[0] == 7 and a[1:] == [math.ceil(x - 1e-12) for x in lb[1:]]
+    # closed form: a doubling schedule has r -> sqrt(2) as m grows, so at w = 1/2
+    # the bound tends to log_3(6.24...) < 2 (the paper's a_i = 2 recommendation)
+    big = [2 ** 20, 2 ** 21]
+    lb = OS.iteration_lower_bounds(big, d, 0.5)[1]
+    assert abs(lb - math.log((1.5 * math.sqrt((2 ** 21 - d) / (2 ** 20 - d)) + 1) / 0.5, 3)) < 1e-12
+    assert 1.6 < lb < 1.7
+    # the bound falls as the tolerance w grows (Fig. on the determination of a_i)
+    vals = [OS.iteration_lower_bounds(m, d, w)[2] for w in (1 / 16, 1 / 8, 1 / 4, 1 / 2, 1.0)]
+    assert all(x > y for x, y in zip(vals, vals[1:]))
+    # equal consecutive sizes (r = 1) give log_3((2 + w)/w): w = 1 -> exactly 1
+    assert abs(OS.iteration_lower_bounds([1000, 1000], 10, 1.0)[1] - 1.0) < 1e-12
