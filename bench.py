@@ -171,6 +171,108 @@ def cpu_baseline(name, d, params_gpu, s_star, tol, n_sample):
     return t, rel_err(beta, bstar), threads
 
 
+def bench_paper(args, G, torch, dev):
+    """The paper's own problems (Sec. 5 recipe: X = G D, d = 64, sigma^2 = 1e-8) and
+    the schedule variants and baselines that run on the same kernels: prediction
+    error Delta_t = ||X (beta_t - beta)||^2 against the LS error sigma^2 d, and the
+    GPU seconds to come within 1% of the LS error."""
+    from slse_inputs import paper_problem
+
+    d, sigma2 = 64, 1e-8
+    rows = []
+
+    def deltas(X, XB, traj):
+        out = []
+        for t in range(traj.shape[0]):
+            _, rn = G.fused_resid_grad(X, XB, traj[t])
+            out.append(rn.item())
+        return out
+
+    def first_within(ds, target):
+        return next((t for t, v in enumerate(ds) if v <= target), None)
+
+    for N, kappa in ((1 << 17, 1e4), (1 << 19, 1e4), (1 << 20, 1e4), (1 << 22, 1e8)):
+        t0 = time.perf_counter()
+        prob = paper_problem(N, d, kappa, sigma2)
+        XBh = prob.X @ prob.beta_true
+        X = torch.from_numpy(prob.X).to(dev)
+        Y = torch.from_numpy(prob.Y).to(dev)
+        XB = torch.from_numpy(XBh).to(dev)
+        del prob, XBh
+        log(f"paper N={N} kappa={kappa:g}: generated in {time.perf_counter() - t0:.1f}s")
+        factor = "qr" if kappa > 1e6 else "chol"
+        m = G.paper_schedule(N, d)
+        methods = [("slse_frs_srht", dict(kind="srht", m=m, a=[2] * len(m))),
+                   ("slse_frs_countsketch", dict(kind="countsketch", m=m, a=[2] * len(m)))]
+        if N == 1 << 20:
+            methods.append(("slse_frs_auto_a", dict(kind="srht", m=m, a=G.auto_a(m, d, 0.5, a1=2))))
+            methods.append(("mihs_only", dict(kind="srht", m=[m[0]], a=[0])))
+        if N == 1 << 22:
+            mt = [1 << k for k in range(10, 17)] + [1 << 19]
+            methods.append(("slse_frs_tuning", dict(kind="srht", m=mt, a=[3] * len(mt))))
+        recs = {}
+        for name, kw in methods:
+            prm = G.Params(seed=7000 + len(rows), r=6 * d, s_max=60, factor=factor, **kw)
+            _, _, traj, _ = G.solve(X, Y, prm, record=True)
+            recs[name] = (prm, deltas(X, XB, traj))
+        d_ls = min(ds[-1] for _, ds in recs.values())
+        for name, (prm, ds) in recs.items():
+            s1 = sum(prm.a)
+            hit = first_within(ds, 1.01 * d_ls)
+            rec = {"N": N, "d": d, "kappa": kappa, "method": name, "factor": factor,
+                   "ls_error_over_sigma2d": d_ls / (sigma2 * d),
+                   "delta_T_over_ls": ds[-1] / d_ls, "iterations_to_1pct": hit}
+            if hit is not None:
+                prm.s_max = max(0, hit - s1)
+                t_s, _ = time_solves(G, torch, X, Y, prm, 5, 1)
+                rec["seconds_to_1pct"] = t_s
+            rows.append(rec)
+            log(f"  {name}: Delta_T/LS {rec['delta_T_over_ls']:.4f}, iterations {hit}, "
+                f"{rec.get('seconds_to_1pct', float('nan')) * 1e3:.2f} ms")
+        if N == 1 << 20:
+            # IHS with a fresh Hessian sketch every step (one full-data step per
+            # solve call, new seed, mu = 1, eta = 0)
+            def ihs(steps):
+                beta = torch.zeros(d, dtype=torch.float64, device=dev)
+                ds = []
+                for t in range(steps):
+                    prm = G.Params(kind="srht", seed=9000 + t, m=[m[0]], a=[0], r=6 * d, s_max=1,
+                                   mu=1.0, eta=0.0, factor=factor)
+                    beta, _ = G.solve(X, Y, prm, beta0=beta)
+                    ds.append(beta)
+                return ds
+            betas = ihs(40)
+            ds = [G.fused_resid_grad(X, XB, b)[1].item() for b in betas]
+            hit = first_within(ds, 1.01 * d_ls)
+            rec = {"N": N, "d": d, "kappa": kappa, "method": "ihs_refreshed_hessian",
+                   "factor": factor, "ls_error_over_sigma2d": d_ls / (sigma2 * d),
+                   "delta_T_over_ls": ds[-1] / d_ls,
+                   "iterations_to_1pct": None if hit is None else hit + 1}
+            if hit is not None:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ihs(hit + 1)
+                torch.cuda.synchronize()
+                rec["seconds_to_1pct"] = time.perf_counter() - t0
+            rows.append(rec)
+            log(f"  ihs_refreshed_hessian: Delta/LS {rec['delta_T_over_ls']:.4f}, iterations "
+                f"{rec['iterations_to_1pct']}, {rec.get('seconds_to_1pct', float('nan')) * 1e3:.2f} ms")
+        del X, Y, XB
+        torch.cuda.empty_cache()
+    main = [r for r in rows if r["N"] == 1 << 22 and r["method"] == "slse_frs_srht"][0]
+    out = {
+        "metric": METRIC, "value": main.get("seconds_to_1pct"), "unit": "s", "n_gpus": 1,
+        "steps": 5, "warmup": 1, "ms_per_step": (main.get("seconds_to_1pct") or 0) * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "paper: X = G D, d = 64, sigma^2 = 1e-8, N in {2^17, 2^19, 2^20, 2^22}, "
+                               "kappa 1e4 (1e8 at 2^22); time to within 1% of the LS error",
+                   "results": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_backward(args, G, torch, dev):
     """Adjoint of beta_hat for L = w^T beta_hat on the backward workload (2^20 x 256,
     float32): lambda by the sketch-preconditioned iteration, then the fused
@@ -348,7 +450,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "illcond", "batched", "backward"])
+    ap.add_argument("--workload", default="mixed",
+                    choices=["mixed", "illcond", "batched", "backward", "paper"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--s-cap", type=int, default=60)
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
@@ -380,6 +483,8 @@ def main():
         return bench_batched(args, G, torch, dev)
     if name == "backward":
         return bench_backward(args, G, torch, dev)
+    if name == "paper":
+        return bench_paper(args, G, torch, dev)
     ref = load_reference(name)
     beta_star = np.asarray(ref["beta_star"])
 

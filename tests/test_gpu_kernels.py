@@ -352,6 +352,35 @@ def test_solve_qr_route_reaches_ls_error_at_kappa_1e8(G):
     assert abs(d_gpu / d_ls - 1) < 1e-3
 
 
+@pytest.mark.parametrize("variant", ["countsketch", "auto_a", "stage2_only", "tuning"])
+def test_schedule_variants_reach_ls_error(G, variant):
+    # the paper's recipe (kappa = 1e4, sigma^2 = 1e-8): CountSketch levels, a_i
+    # from the lower bound of Thm lowerBoundai, stage 2 alone (M-IHS) and a
+    # tuning-style schedule all reach the LS error of the OLS estimator
+    from slse_inputs import paper_problem
+
+    prob = paper_problem(1 << 15, 32, 1e4, 1e-8)
+    d = prob.d
+    m = G.paper_schedule(prob.n, d)
+    kw = dict(kind="srht", m=m, a=[2] * len(m))
+    if variant == "countsketch":
+        kw = dict(kind="countsketch", m=m, a=[2] * len(m))
+    elif variant == "auto_a":
+        kw = dict(kind="srht", m=m, a=G.auto_a(m, d, 0.5, a1=2))
+    elif variant == "stage2_only":
+        kw = dict(kind="srht", m=[m[0]], a=[0])
+    elif variant == "tuning":
+        kw = dict(kind="srht", m=[512, 1024, 2048, 8192], a=[3] * 4)
+    params = G.Params(seed=31, r=6 * d, s_max=60, **kw)
+    beta, info = G.solve(dev(prob.X), dev(prob.Y), params)
+    assert info["status"] == "SLSE_OK"
+    bhat, _, _ = O.ols_refined(prob.X, prob.Y)
+    d_gpu = np.sum((prob.X @ (beta.cpu().numpy() - prob.beta_true)) ** 2)
+    d_ls = np.sum((prob.X @ (bhat - prob.beta_true)) ** 2)
+    assert abs(d_gpu / d_ls - 1) < 1e-6
+    assert 0.2 < d_ls / (1e-8 * d) < 3.0  # chi-square with d degrees of freedom
+
+
 def test_factor_singular_reports_esingular(G):
     from paper_2509_06856_amd import _lib
 
