@@ -1,8 +1,9 @@
 // Batched M-IHS steps for many independent regressions of uneven size (one
 // launch per step for the whole batch instead of one per problem).
 //
-// Residual gradient: the rows of every active problem are cut into tiles of
-// `tile_rows`; one flat list of (problem, tile) work items is walked by a
+// Residual gradient: the rows of every active problem are cut into tiles (the
+// tile height is chosen per step, smaller when few rows are active, so the
+// grid stays busy); one flat list of (problem, tile) work items is walked by a
 // persistent grid.  A block takes a tile, streams its rows with the problem's
 // own lane-group width (as in the single-problem pass: a row split over
 // `lpr` lanes, many rows in flight), reduces the tile's partial gradient in
@@ -40,6 +41,22 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
   }
 }
 
+// FP32 -> FP64 as an instruction the compiler cannot merge with an earlier
+// conversion of the same value, so widened rows are not kept alive from a
+// row's dot to its gradient update (that would double the registers held)
+template <typename T>
+__device__ __forceinline__ double widen_f64(T x) {
+  if constexpr (sizeof(T) == 4) {
+    double r;
+    asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+  } else {
+    return (double)x;
+  }
+}
+
+constexpr int kPrefixLds = 512;  // problems whose tile prefix is searched in LDS
+
 __device__ __forceinline__ int find_problem(const int* __restrict__ prefix, int B, int tile) {
   int lo = 0, hi = B;  // prefix[lo] <= tile < prefix[hi]
   while (hi - lo > 1) {
@@ -55,17 +72,24 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ prefix, int 
 template <typename T, int VEC, int NCH>
 __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
     const BatchStep* __restrict__ steps, const BatchProblem* __restrict__ probs,
-    const int* __restrict__ prefix, int B, int total_tiles, int tile_rows,
-    double* __restrict__ pool) {
+    const int* __restrict__ prefix, int B, int total_tiles, double* __restrict__ pool) {
   constexpr int UNROLL = 4;
   __shared__ double s_red[kWaves][kMaxD + 1];
+  __shared__ int s_prefix[kPrefixLds + 1];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  // the tile prefix of this step, searched in LDS (global if the batch is large)
+  const bool lds_prefix = B <= kPrefixLds;
+  if (lds_prefix) {
+    for (int i = threadIdx.x; i <= B; i += kThreads) s_prefix[i] = prefix[i];
+    __syncthreads();
+  }
+  const int* pfx = lds_prefix ? s_prefix : prefix;
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    const int b = find_problem(prefix, B, tile);
+    const int b = find_problem(pfx, B, tile);
     const BatchStep st = steps[b];
     const BatchProblem pr = probs[b];
-    const int lt = tile - prefix[b];
+    const int lt = tile - pfx[b];
     const int d = pr.d;
     const int lpr = pr.lpr;
     const int gpw = 64 / lpr;
@@ -89,8 +113,8 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[c][v] = 0.0;
     double rr = 0.0;
-    const int64_t r0 = (int64_t)lt * tile_rows;
-    const int64_t r1 = min(st.n, r0 + tile_rows);
+    const int64_t r0 = (int64_t)lt * st.tile_rows;
+    const int64_t r1 = min(st.n, r0 + st.tile_rows);
     const int rs = kWaves * gpw;
     for (int64_t base = r0 + wave * gpw + grp; base < r1; base += (int64_t)rs * UNROLL) {
       T x[UNROLL][NCH][VEC];
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, (double)x[u][c][v], acc[c][v]);
+          for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, widen_f64(x[u][c][v]), acc[c][v]);
         rr = fma(r, r, rr);
       }
     }
@@ -245,19 +269,19 @@ __global__ void batched_init_kernel(const BatchProblem* __restrict__ probs) {
 
 template <typename T, int VEC>
 void launch_rg(const BatchStep* steps, const BatchProblem* probs, const int* prefix, int B,
-               int total, int tile_rows, int grid, double* pool, int nch, hipStream_t s) {
+               int total, int grid, double* pool, int nch, hipStream_t s) {
   switch (nch) {
     case 1:
       batched_resid_grad_kernel<T, VEC, 1><<<grid, kThreads, 0, s>>>(steps, probs, prefix, B, total,
-                                                                      tile_rows, pool);
+                                                                      pool);
       break;
     case 2:
       batched_resid_grad_kernel<T, VEC, 2><<<grid, kThreads, 0, s>>>(steps, probs, prefix, B, total,
-                                                                      tile_rows, pool);
+                                                                      pool);
       break;
     default:
       batched_resid_grad_kernel<T, VEC, 4><<<grid, kThreads, 0, s>>>(steps, probs, prefix, B, total,
-                                                                      tile_rows, pool);
+                                                                      pool);
       break;
   }
 }
@@ -265,20 +289,20 @@ void launch_rg(const BatchStep* steps, const BatchProblem* probs, const int* pre
 }  // namespace
 
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
-                               int B, int total_tiles, int tile_rows, int grid, double* pool,
+                               int B, int total_tiles, int grid, double* pool,
                                slse_dtype t, bool vec, int nch, hipStream_t s) {
   if (total_tiles <= 0) return;
   grid = std::max(1, std::min(grid, total_tiles));
   if (t == SLSE_F32) {
     if (vec)
-      launch_rg<float, 4>(steps, probs, prefix, B, total_tiles, tile_rows, grid, pool, nch, s);
+      launch_rg<float, 4>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
     else
-      launch_rg<float, 1>(steps, probs, prefix, B, total_tiles, tile_rows, grid, pool, nch, s);
+      launch_rg<float, 1>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
   } else {
     if (vec)
-      launch_rg<double, 2>(steps, probs, prefix, B, total_tiles, tile_rows, grid, pool, nch, s);
+      launch_rg<double, 2>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
     else
-      launch_rg<double, 1>(steps, probs, prefix, B, total_tiles, tile_rows, grid, pool, nch, s);
+      launch_rg<double, 1>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
   }
   SLSE_LAUNCH_CHECK();
 }

@@ -370,7 +370,79 @@ size_t srht_z_bytes(const SrhtArgs& a) {
   return (size_t)(int64_t(1) << a.p) * (size_t)a.ldz * dtype_size(a.t);
 }
 
+namespace {
+
+__device__ __forceinline__ int find_job(const SrhtIndexJob* __restrict__ jobs, int B, int64_t g,
+                                        bool hat) {
+  int lo = 0, hi = B;  // base(lo) <= g < base(hi)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((hat ? jobs[mid].hbase : jobs[mid].base) <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// every row index of every job: pi_sgn, slotA (as srht_index_kernel) and slotH = -1
+__global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs, int B,
+                                          int64_t total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const SrhtIndexJob jb = jobs[find_job(jobs, B, g, false)];
+    const int64_t j = g - jb.base;
+    const uint64_t src = rng::prp((uint64_t)j, jb.seed, rng::kStreamP, jb.p);
+    const int D = rng::rademacher(jb.seed, (uint64_t)j);
+    jb.pi_sgn[j] = D > 0 ? (int32_t)src : ~(int32_t)src;
+    const uint64_t t = rng::prp_inv((uint64_t)j, jb.seed, rng::kStreamS, jb.p);
+    jb.slotA[last_pass_index(j, jb.s0_last, jb.b_last)] = t < (uint64_t)jb.mK ? (int32_t)t : -1;
+    jb.slotH[j] = -1;
+  }
+}
+
+// every Hessian sample of every job (after the kernel above)
+__global__ void srht_hat_batched_kernel(const SrhtIndexJob* __restrict__ jobs, int B,
+                                        int64_t total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const SrhtIndexJob jb = jobs[find_job(jobs, B, g, true)];
+    const int64_t t = g - jb.hbase;
+    const int64_t j = (int64_t)rng::prp((uint64_t)t, jb.seed, rng::kStreamShat, jb.p);
+    jb.slotH[last_pass_index(j, jb.s0_last, jb.b_last)] = (int32_t)t;
+  }
+}
+
+}  // namespace
+
+void srht_last_pass(const SrhtArgs& a, int* s0_last, int* b_last) {
+  const std::vector<int> bs = pass_sizes(a.p, a.bmax);
+  *b_last = bs.back();
+  *s0_last = a.p - bs.back();
+}
+
+void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t total_rows,
+                               int64_t total_hat, hipStream_t s) {
+  if (B <= 0) return;
+  const int threads = 256;
+  const int b1 = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total_rows, threads), 16384));
+  srht_index_batched_kernel<<<b1, threads, 0, s>>>(jobs, B, total_rows);
+  SLSE_LAUNCH_CHECK();
+  const int b2 = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total_hat, threads), 16384));
+  srht_hat_batched_kernel<<<b2, threads, 0, s>>>(jobs, B, total_hat);
+  SLSE_LAUNCH_CHECK();
+}
+
 void launch_srht(const SrhtArgs& a, hipStream_t s) {
+  if (a.indices_ready) {
+    if (a.t == SLSE_F64)
+      run_passes<double>(a, s);
+    else if (a.t == SLSE_F32)
+      run_passes<float>(a, s);
+    else
+      fail(SLSE_EUNSUPPORTED, "srht: dtype");
+    return;
+  }
   const int64_t npad = int64_t(1) << a.p;
   const int threads = 256;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(npad, threads), 16384));

@@ -122,9 +122,32 @@ struct SrhtArgs {
   int bmax = 0;               // stages per pass cap
   bool narrow = false;        // half-width column tiles (two blocks per CU)
   bool xcd_swizzle = true;    // contiguous work runs per XCD
+  bool indices_ready = false; // pi_sgn / slotA / slotH already built (batched)
 };
 
 void srht_plan(SrhtArgs& a, int prefer_ct);
+
+// Index maps of many SRHTs in two launches (rows of every job, then the r
+// Hessian samples of every job).  base/hbase: first global index of the job.
+struct SrhtIndexJob {
+  int64_t npad;
+  int64_t r;
+  int64_t mK;
+  uint64_t seed;
+  int p;
+  int s0_last;
+  int b_last;
+  int pad_;
+  int64_t base;
+  int64_t hbase;
+  int32_t* pi_sgn;
+  int32_t* slotA;
+  int32_t* slotH;
+};
+// b_last / s0_last of the pass split srht_plan chooses for `a` (a.p, a.bmax set)
+void srht_last_pass(const SrhtArgs& a, int* s0_last, int* b_last);
+void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t total_rows,
+                               int64_t total_hat, hipStream_t s);
 size_t srht_z_bytes(const SrhtArgs& a);
 void launch_srht(const SrhtArgs& a, hipStream_t s);
 
@@ -254,7 +277,7 @@ struct BatchStep {  // one problem at one global step
   const double* beta_prev;
   double* beta_next;
   int ntiles;
-  int pad_;
+  int tile_rows;  // rows per tile in this step (the last tile may be short)
 };
 struct BatchProblem {
   int d;
@@ -267,8 +290,8 @@ struct BatchProblem {
   double* beta_init;    // the iterate buffer the first step reads
 };
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
-                               int B, int total_tiles, int tile_rows, int grid, double* pool,
-                               slse_dtype t, bool vec, int nch, hipStream_t s);
+                               int B, int total_tiles, int grid, double* pool, slse_dtype t, bool vec,
+                               int nch, hipStream_t s);
 void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
                            const double* pool, int* flags, hipStream_t s);
 // beta_init = beta_out = beta0 (or 0) for every problem

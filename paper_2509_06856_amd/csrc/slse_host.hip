@@ -883,6 +883,7 @@ struct BatchPlan {
   int T = 0;                  // global steps (max over problems)
   int tile_rows = 2048;
   int grid = 512;
+  int cus = 256;  // compute units of the device
   bool vec = true;
   int nch = 4;
   char* Apool = nullptr;
@@ -903,6 +904,12 @@ struct BatchPlan {
   GaussianArgs ga, gh;
   void* cs = nullptr;  // CountSketch bucket lists (sized for the largest problem)
   FactorBufs f;
+  // SRHT index maps of every SRHT problem, built in two launches
+  std::vector<SrhtIndexJob> h_sjobs;
+  SrhtIndexJob* d_sjobs = nullptr;
+  std::vector<int64_t> s_off;  // offset of problem b in the index pools (-1: not SRHT)
+  int64_t s_rows = 0, s_hat = 0;
+  int32_t *s_pi = nullptr, *s_sa = nullptr, *s_sh = nullptr;
   // Cholesky route for every problem: one batched factorization
   bool batched_factor = false;
   int dmax = 0;
@@ -911,11 +918,31 @@ struct BatchPlan {
   std::vector<FactorJob> h_jobs;
 };
 
+constexpr int kBatchTileFloor = 256;  // no batched tile is shorter (partial pool size)
+constexpr int kBatchMinTile = 1024;   // shortest tile chosen by default
+constexpr int kBatchChunks = 4;     // most row vectors a lane holds in a batched step
+
+// shortest tile height a batched step may use (SLSE_BATCH_MIN_TILE overrides)
+int batch_min_tile() {
+  static const int v = [] {
+    int t = kBatchMinTile;
+    if (const char* e = std::getenv("SLSE_BATCH_MIN_TILE")) t = std::max(kBatchTileFloor, std::atoi(e));
+    return t;
+  }();
+  return v;
+}
+
 int batch_lpr(int d, bool vec, slse_dtype t) {
   const int v = vec ? 16 / (int)dtype_size(t) : 1;
   const int nvec = (int)ceil_div(d, v);
+  // at most kBatchChunks vectors per lane (SLSE_BATCH_CHUNKS overrides)
+  static const int chunks = [] {
+    int c = kBatchChunks;
+    if (const char* e = std::getenv("SLSE_BATCH_CHUNKS")) c = std::atoi(e);
+    return (c == 1 || c == 2 || c == 4) ? c : kBatchChunks;
+  }();
   int lpr = 1;
-  while (lpr < 64 && lpr * 4 < nvec) lpr *= 2;
+  while (lpr < 64 && lpr * chunks < nvec) lpr *= 2;
   return lpr;
 }
 
@@ -947,8 +974,6 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
       st.beta = ring[cur];
       st.beta_prev = ring[prev];
       st.beta_next = ring[next];
-      st.ntiles = (int)ceil_div(n, bp.tile_rows);
-      bp.max_tiles[b] = std::max<int64_t>(bp.max_tiles[b], st.ntiles);
       prev = cur;
       cur = next;
       ++t;
@@ -962,6 +987,21 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
     if (qs[b].momentum_reset) prev = cur;
     for (int j = 0; j < qs[b].s_max; ++j) add(ps[b].X, ps[b].ldx, ps[b].Y, 1, ps[b].N, 1.0);
     (void)betas;
+  }
+  // Tile height per step: the tuned height while the step has plenty of rows;
+  // when only a few (small) problems are still running, shorter tiles (down
+  // to batch_min_tile()) keep at least two tiles per CU.
+  for (int t = 0; t < bp.T; ++t) {
+    int64_t rows = 0;
+    for (int b = 0; b < B; ++b) rows += bp.h_steps[(size_t)t * B + b].n;
+    int tile = bp.tile_rows;
+    while (tile > batch_min_tile() && ceil_div(rows, (int64_t)tile) < 2 * (int64_t)bp.cus) tile /= 2;
+    for (int b = 0; b < B; ++b) {
+      BatchStep& st = bp.h_steps[(size_t)t * B + b];
+      st.tile_rows = tile;
+      st.ntiles = (int)ceil_div(st.n, (int64_t)tile);
+      bp.max_tiles[b] = std::max<int64_t>(bp.max_tiles[b], st.ntiles);
+    }
   }
   for (int t = 0; t < bp.T; ++t) {
     int acc = 0;
@@ -977,8 +1017,8 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
 void enqueue_batch_steps(const BatchPlan& bp, hipStream_t st) {
   for (int t = 0; t < bp.T; ++t) {
     launch_batched_resid_grad(bp.d_steps + (size_t)t * bp.B, bp.d_probs,
-                              bp.d_prefix + (size_t)t * (bp.B + 1), bp.B, bp.h_total[t],
-                              bp.tile_rows, bp.grid, bp.part, bp.t, bp.vec, bp.nch, st);
+                              bp.d_prefix + (size_t)t * (bp.B + 1), bp.B, bp.h_total[t], bp.grid,
+                              bp.part, bp.t, bp.vec, bp.nch, st);
     launch_batched_update(bp.d_steps + (size_t)t * bp.B, bp.d_probs, bp.B, bp.part, bp.flags, st);
   }
 }
@@ -996,6 +1036,12 @@ void enqueue_batch_sketch(const BatchPlan& bp, int b, const slse_problem* ps,
     sa.mK = sk.m[sk.K - 1];
     sa.r = sk.r;
     srht_plan(sa, 0);
+    if (bp.s_off[b] >= 0) {
+      sa.pi_sgn = bp.s_pi + bp.s_off[b];
+      sa.slotA = bp.s_sa + bp.s_off[b];
+      sa.slotH = bp.s_sh + bp.s_off[b];
+      sa.indices_ready = true;
+    }
   }
   GaussianArgs ga = bp.ga, gh = bp.gh;
   ga.N = gh.N = sk.N;
@@ -1031,6 +1077,8 @@ void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_param
                    hipStream_t st) {
   launch_fill_i32(bp.flags, 0, bp.B, st);
   launch_fill_i32(bp.finfo, 0, 3 * (int64_t)bp.B, st);
+  if (!bp.h_sjobs.empty())
+    launch_srht_index_batched(bp.d_sjobs, (int)bp.h_sjobs.size(), bp.s_rows, bp.s_hat, st);
   for (int b = 0; b < bp.B; ++b) enqueue_batch_sketch(bp, b, ps, qs, st);
   if (bp.batched_factor)
     launch_factor_batched(bp.d_jobs, bp.B, bp.dmax, bp.rmax, bp.t, st);
@@ -1044,6 +1092,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
                          double* const* betas, slse_report* reps, hipStream_t st) {
   BatchPlan bp;
   bp.B = B;
+  bp.cus = ctx->num_cus;
   bp.t = ps[0].dtype;
   for (int b = 0; b < B; ++b) {
     check_params(&ps[b], &qs[b]);
@@ -1117,6 +1166,41 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bp.srht.slotH = ctx->arena.get_t<int32_t>("srht_slotH", (size_t)max_npad);
   bp.srht.Z = z_bytes ? ctx->arena.get("srht_Z", z_bytes) : nullptr;
   bp.cs = cs_bytes ? ctx->arena.get("cs_lists", cs_bytes) : nullptr;
+  // per-problem SRHT index maps
+  bp.s_off.assign(B, -1);
+  for (int b = 0; b < B; ++b) {
+    const SketchShape& sk = bp.sk[b];
+    if (sk.kind != SLSE_SRHT) continue;
+    SrhtArgs sa;
+    sa.t = bp.t;
+    sa.d = (int)ps[b].d;
+    sa.p = sk.p;
+    srht_plan(sa, 0);
+    SrhtIndexJob j{};
+    j.npad = sk.n_pad;
+    j.r = sk.r;
+    j.mK = sk.m[sk.K - 1];
+    j.seed = qs[b].seed;
+    j.p = sk.p;
+    srht_last_pass(sa, &j.s0_last, &j.b_last);
+    j.base = bp.s_rows;
+    j.hbase = bp.s_hat;
+    bp.s_off[b] = bp.s_rows;
+    bp.s_rows += sk.n_pad;
+    bp.s_hat += sk.r;
+    bp.h_sjobs.push_back(j);
+  }
+  if (!bp.h_sjobs.empty()) {
+    bp.s_pi = ctx->arena.get_t<int32_t>("bSrhtPi", (size_t)bp.s_rows);
+    bp.s_sa = ctx->arena.get_t<int32_t>("bSrhtSlotA", (size_t)bp.s_rows);
+    bp.s_sh = ctx->arena.get_t<int32_t>("bSrhtSlotH", (size_t)bp.s_rows);
+    for (SrhtIndexJob& j : bp.h_sjobs) {
+      j.pi_sgn = bp.s_pi + j.base;
+      j.slotA = bp.s_sa + j.base;
+      j.slotH = bp.s_sh + j.base;
+    }
+    bp.d_sjobs = ctx->arena.get_t<SrhtIndexJob>("bSrhtJobs", bp.h_sjobs.size());
+  }
   bp.srht.t = bp.t;
   bp.ga.t = bp.gh.t = bp.t;
   bp.ga.stream_id = 7;
@@ -1212,11 +1296,12 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     bp.grid = 2 * ctx->num_cus;
     bp.tile_rows = 2048;
   }
-  // partial pool sized for the smallest tile any tuning candidate may use
+  // partial pool sized for the shortest tile a step may use
   int64_t part_n = 0;
   for (int b = 0; b < B; ++b) {
     bp.part_off.push_back(part_n);
-    part_n += ceil_div(std::max<int64_t>(bp.sk[b].rows_A, ps[b].N), 1024) * (ps[b].d + 1);
+    part_n += ceil_div(std::max<int64_t>(bp.sk[b].rows_A, ps[b].N), (int64_t)kBatchTileFloor) *
+              (ps[b].d + 1);
   }
   bp.part = ctx->arena.get_t<double>("bPart", (size_t)part_n + 1);
   bp.d_steps = ctx->arena.get_t<BatchStep>("bSteps", (size_t)bp.T * B);
@@ -1227,6 +1312,9 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   SLSE_HIP(hipMemcpy(bp.d_probs, bp.h_probs.data(), sizeof(BatchProblem) * B, hipMemcpyHostToDevice));
   if (bp.batched_factor)
     SLSE_HIP(hipMemcpy(bp.d_jobs, bp.h_jobs.data(), sizeof(FactorJob) * B, hipMemcpyHostToDevice));
+  if (!bp.h_sjobs.empty())
+    SLSE_HIP(hipMemcpy(bp.d_sjobs, bp.h_sjobs.data(), sizeof(SrhtIndexJob) * bp.h_sjobs.size(),
+                       hipMemcpyHostToDevice));
 
   auto upload = [&]() {
     build_batch_tables(bp, ps, qs, betas);
@@ -1254,7 +1342,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
           auto run = [&]() {
             launch_batched_resid_grad(bp.d_steps + (size_t)tmax * B, bp.d_probs,
                                       bp.d_prefix + (size_t)tmax * (B + 1), B, bp.h_total[tmax],
-                                      tr, g, bp.part, bp.t, bp.vec, bp.nch, st);
+                                      g, bp.part, bp.t, bp.vec, bp.nch, st);
           };
           run();
           SLSE_HIP(hipEventRecord(e0, st));
