@@ -39,6 +39,10 @@ def load_reference(name):
         return json.load(f)
 
 
+# the residual-gradient kernel and the device helpers it uses
+KERNEL_SOURCES = ("k_resid_grad.hip", "common.hpp")
+
+
 def counted_traffic(name):
     """HBM bytes per residual-gradient launch from the committed counter runs,
     or None when they were not taken on this workload or the kernel source has
@@ -46,14 +50,17 @@ def counted_traffic(name):
     if name != "mixed":
         return None
     path = os.path.join(ROOT, "profiles", "resid_grad_f32_4194304x512_counters.md")
-    src = os.path.join(ROOT, "paper_2509_06856_amd", "csrc", "k_resid_grad.hip")
+    csrc = os.path.join(ROOT, "paper_2509_06856_amd", "csrc")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
                       if ": " in line and not line.startswith(("-", "|", "#")))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        digest = h.hexdigest()
     except OSError:
         return None
-    if fields.get("k_resid_grad.hip sha256", "").strip() != digest:
+    if fields.get("kernel sources sha256", "").strip() != digest:
         return None
     return int(fields["traffic_bytes_per_launch"])
 

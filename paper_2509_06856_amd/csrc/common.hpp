@@ -75,4 +75,21 @@ __device__ __forceinline__ T lane_group_sum(T v, int group) {
   return v;
 }
 
+// Block partials handed to the last block of a grid (or of a block group).
+// Each XCD has its own L2, so a plain store may sit in the writer's L2 where
+// a block on another XCD does not see it, and a device-scope fence would
+// write back and invalidate the whole L2 of every block that issues it.
+// Instead the partials are stored and loaded with device-scope (sc1) accesses,
+// which go past the non-coherent L2 level; the writer waits until its stores
+// have completed before it takes its ticket, and the last block issues its
+// loads after it has drawn the final ticket.
+__device__ __forceinline__ void store_device(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_device(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait for this thread's outstanding memory operations (stores included)
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 }  // namespace slse

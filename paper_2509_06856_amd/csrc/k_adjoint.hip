@@ -16,77 +16,176 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-template <typename T, typename G, int NCH>
+template <typename T, int VEC>
+using vec_of = T __attribute__((ext_vector_type(VEC)));
+
+// VEC elements at p (16-byte vector loads/stores when VEC > 1), streamed past
+// the caches
+template <typename T, int VEC>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    v[0] = __builtin_nontemporal_load(p);
+  } else {
+    const vec_of<T, VEC> t = __builtin_nontemporal_load(reinterpret_cast<const vec_of<T, VEC>*>(p));
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) v[k] = t[k];
+  }
+}
+template <typename G, int VEC>
+__device__ __forceinline__ void store_chunk(G* __restrict__ p, const G (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    __builtin_nontemporal_store(v[0], p);
+  } else {
+    vec_of<G, VEC> t;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) t[k] = v[k];
+    __builtin_nontemporal_store(t, reinterpret_cast<vec_of<G, VEC>*>(p));
+  }
+}
+
+// rows of [X|Y] a lane keeps in flight: about 128 bytes of X per lane
+template <typename T, int VEC, int NCH>
+constexpr int adjoint_unroll() {
+  constexpr int u = 128 / (NCH * VEC * (int)sizeof(T));
+  return u < 1 ? 1 : (u > 8 ? 8 : u);
+}
+
+// A row is split over `lpr` lanes, each holding NCH chunks of VEC columns
+// (column (c lpr + l) VEC + k); a block handles tiles of UNROLL x (rows per
+// block step) rows, every lane group keeping UNROLL rows in flight.  With
+// VEC > 1, d is a multiple of VEC and X, dX rows are VEC-aligned.
+template <typename T, typename G, int VEC, int NCH>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(int64_t n, int d, const T* __restrict__ X,
                                                            int64_t ldx, const T* __restrict__ Y,
                                                            const double* __restrict__ beta,
                                                            const double* __restrict__ lambda,
                                                            int lpr, G* __restrict__ dX, int64_t lddx,
                                                            G* __restrict__ dY) {
+  constexpr int UNROLL = adjoint_unroll<T, VEC, NCH>();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int gpw = 64 / lpr;
   const int grp = lane / lpr;
   const int l = lane - grp * lpr;
-  double b[NCH], lam[NCH];
+  double b[NCH][VEC], lam[NCH][VEC];
+  bool inside[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const int col = c * lpr + l;
-    b[c] = col < d ? beta[col] : 0.0;
-    lam[c] = col < d ? lambda[col] : 0.0;
-  }
-  const int64_t stride = (int64_t)gridDim.x * kWaves * gpw;
-  for (int64_t row = ((int64_t)blockIdx.x * kWaves + wave) * gpw + grp; row < n; row += stride) {
-    const T* xr = X + row * ldx;
-    double x[NCH];
-    double d1 = 0.0, d2 = 0.0;
+    const int col0 = (c * lpr + l) * VEC;
+    inside[c] = col0 < d;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int col = c * lpr + l;
-      x[c] = col < d ? (double)__builtin_nontemporal_load(xr + col) : 0.0;
-      d1 = fma(x[c], b[c], d1);
-      d2 = fma(x[c], lam[c], d2);
+    for (int k = 0; k < VEC; ++k) {
+      b[c][k] = inside[c] ? beta[col0 + k] : 0.0;
+      lam[c][k] = inside[c] ? lambda[col0 + k] : 0.0;
     }
-    d1 = lane_group_sum(d1, lpr);
-    d2 = lane_group_sum(d2, lpr);
-    const double r = (Y ? (double)Y[row] : 0.0) - d1;
-    if (dX) {
-      G* out = dX + row * lddx;
+  }
+  const int step = kWaves * gpw;  // rows per block step
+  const int64_t tile = (int64_t)step * UNROLL;
+  const int my = wave * gpw + grp;
+  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+    T x[UNROLL][NCH][VEC];
+    double y[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t row = base + (int64_t)u * step + my;
+      const bool ok = row < n;
+      const T* xr = X + (ok ? row : 0) * ldx;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        const int col = c * lpr + l;
-        if (col < d) __builtin_nontemporal_store((G)(r * lam[c] - d2 * b[c]), out + col);
+        if (ok && inside[c]) {
+          load_chunk<T, VEC>(xr + (c * lpr + l) * VEC, x[u][c]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) x[u][c][k] = (T)0;
+        }
+      }
+      y[u] = (Y && ok) ? (double)Y[row] : 0.0;
+    }
+    double d1[UNROLL], d2[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          s1 = fma((double)x[u][c][k], b[c][k], s1);
+          s2 = fma((double)x[u][c][k], lam[c][k], s2);
+        }
+      d1[u] = s1;
+      d2[u] = s2;
+    }
+    for (int m = lpr >> 1; m > 0; m >>= 1) {
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        d1[u] += wave_xor(d1[u], m);
+        d2[u] += wave_xor(d2[u], m);
       }
     }
-    if (dY && l == 0) dY[row] = (G)d2;
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t row = base + (int64_t)u * step + my;
+      if (row >= n) continue;
+      const double r = y[u] - d1[u];
+      if (dX) {
+        G* out = dX + row * lddx;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          if (!inside[c]) continue;
+          G o[VEC];
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) o[k] = (G)(r * lam[c][k] - d2[u] * b[c][k]);
+          store_chunk<G, VEC>(out + (c * lpr + l) * VEC, o);
+        }
+      }
+      if (dY && l == 0) dY[row] = (G)d2[u];
+    }
   }
 }
 
-template <typename T, typename G, int NCH>
-void launch3(const AdjointArgs& a, int lpr, hipStream_t s) {
-  const int rows_per_block = kWaves * (64 / lpr);
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.n, rows_per_block), 4096));
-  adjoint_kernel<T, G, NCH><<<blocks, kThreads, 0, s>>>(
+template <typename T, typename G, int VEC, int NCH>
+void launch4(const AdjointArgs& a, int lpr, hipStream_t s) {
+  const int64_t tile = (int64_t)kWaves * (64 / lpr) * adjoint_unroll<T, VEC, NCH>();
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.n, tile), 2048));
+  adjoint_kernel<T, G, VEC, NCH><<<blocks, kThreads, 0, s>>>(
       a.n, a.d, static_cast<const T*>(a.X), a.ldx, static_cast<const T*>(a.Y), a.beta, a.lambda,
       lpr, static_cast<G*>(a.dX), a.lddx, static_cast<G*>(a.dY));
   SLSE_LAUNCH_CHECK();
 }
 
-template <typename T, typename G>
-void launch2(const AdjointArgs& a, hipStream_t s) {
+template <typename T, typename G, int VEC>
+void launch3(const AdjointArgs& a, hipStream_t s) {
+  // lane groups of at most a wave, about four chunks per lane
+  const int nvec = (int)ceil_div(a.d, VEC);
   int lpr = 1;
-  while (lpr < 64 && lpr * 4 <= a.d) lpr *= 2;
-  const int nch = (int)ceil_div(a.d, lpr);
-  if (nch <= 4)
-    launch3<T, G, 4>(a, lpr, s);
+  while (lpr < 64 && lpr * 4 < nvec) lpr *= 2;
+  const int nch = (int)ceil_div(nvec, lpr);
+  if (nch <= 1)
+    launch4<T, G, VEC, 1>(a, lpr, s);
+  else if (nch <= 2)
+    launch4<T, G, VEC, 2>(a, lpr, s);
+  else if (nch <= 4)
+    launch4<T, G, VEC, 4>(a, lpr, s);
   else if (nch <= 8)
-    launch3<T, G, 8>(a, lpr, s);
+    launch4<T, G, VEC, 8>(a, lpr, s);
   else if (nch <= 16)
-    launch3<T, G, 16>(a, lpr, s);
-  else if (nch <= 32)
-    launch3<T, G, 32>(a, lpr, s);
+    launch4<T, G, VEC, 16>(a, lpr, s);
   else
     fail(SLSE_EUNSUPPORTED, "adjoint: d too large for this build");
+}
+
+template <typename T, typename G>
+void launch2(const AdjointArgs& a, hipStream_t s) {
+  // 16-byte chunks when every row of X and dX starts on such a boundary
+  constexpr int V = 16 / (int)sizeof(T);
+  auto aligned = [](const void* p, int64_t ld, size_t es) {
+    return p == nullptr ||
+           (reinterpret_cast<uintptr_t>(p) % (V * es) == 0 && (ld * (int64_t)es) % (V * (int64_t)es) == 0);
+  };
+  if (a.d % V == 0 && aligned(a.X, a.ldx, sizeof(T)) && aligned(a.dX, a.lddx, sizeof(G)))
+    launch3<T, G, V>(a, s);
+  else
+    launch3<T, G, 1>(a, s);
 }
 
 // ---------------------------------------------------------------------------

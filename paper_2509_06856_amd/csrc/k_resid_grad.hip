@@ -305,13 +305,13 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) t += s_red[w][col - c0];
-      prow[col] = t;
+      store_device(prow + col, t);
     }
     __syncthreads();
   }
 
   // last block of the group sums the group's partial rows in block order
-  __threadfence();
+  wait_memory();
   __syncthreads();
   const int group = blockIdx.x / kGroupSize;
   const int g0 = group * kGroupSize;
@@ -319,12 +319,11 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
   if (threadIdx.x == 0) s_ticket = atomicAdd(&counters[group], 1);
   __syncthreads();
   if (s_ticket == gsz - 1) {
-    __threadfence();
     for (int col = threadIdx.x; col < d + 1; col += kThreads) {
       double v[kGroupSize];
 #pragma unroll
       for (int bk = 0; bk < kGroupSize; ++bk)
-        v[bk] = bk < gsz ? partial[(int64_t)(g0 + bk) * ldp + col] : 0.0;
+        v[bk] = bk < gsz ? load_device(partial + (int64_t)(g0 + bk) * ldp + col) : 0.0;
       double t = 0.0;
 #pragma unroll
       for (int bk = 0; bk < kGroupSize; ++bk) t += v[bk];

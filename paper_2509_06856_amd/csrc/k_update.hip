@@ -74,22 +74,21 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
   if (threadIdx.x < 3) {
     double t = 0.0;
     for (int w = 0; w < kWaves; ++w) t += s_red[threadIdx.x][w];
-    a.sur_partial[3 * blockIdx.x + threadIdx.x] = t;
+    store_device(a.sur_partial + 3 * blockIdx.x + threadIdx.x, t);
   }
-  __threadfence();
+  wait_memory();
   __syncthreads();
   if (threadIdx.x == 0) s_ticket = atomicAdd(a.sur_counter, 1);
   __syncthreads();
   if (s_ticket != (int)gridDim.x - 1) return;
-  __threadfence();
   // the last block: every thread sums a fixed subset of the block partials,
   // then a fixed tree over the threads (deterministic)
   __shared__ double s_tail[3][kThreads];
   double tgp = 0.0, tpp = 0.0, tbb = 0.0;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads) {
-    tgp += a.sur_partial[3 * b + 0];
-    tpp += a.sur_partial[3 * b + 1];
-    tbb += a.sur_partial[3 * b + 2];
+    tgp += load_device(a.sur_partial + 3 * b + 0);
+    tpp += load_device(a.sur_partial + 3 * b + 1);
+    tbb += load_device(a.sur_partial + 3 * b + 2);
   }
   s_tail[0][threadIdx.x] = tgp;
   s_tail[1][threadIdx.x] = tpp;

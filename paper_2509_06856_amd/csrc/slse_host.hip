@@ -419,7 +419,7 @@ ResidGradPlan rg_plan(const slse_ctx* ctx, const IterBufs& b, int64_t n, int d,
 void tune_resid_grad(slse_ctx* ctx, const IterBufs& b, int64_t n, int d, slse_dtype storage,
                      slse_dtype accum, const void* X, int64_t ldx, const void* Y, int64_t incy,
                      hipStream_t st) {
-  if (n < (int64_t(1) << 16)) return;
+  if (n < (int64_t(1) << 12)) return;
   if (const char* e = std::getenv("SLSE_AUTOTUNE"))
     if (std::atoi(e) == 0) return;
   const std::string key = rg_key(n, d, storage, accum, X, ldx);
