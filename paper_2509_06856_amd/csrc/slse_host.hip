@@ -881,7 +881,7 @@ struct BatchPlan {
   std::vector<int64_t> lda, a_off, ah_off, m_off, beta_off, part_off, max_tiles;
   std::vector<int> steps_of;  // total steps of each problem
   int T = 0;                  // global steps (max over problems)
-  int tile_rows = 2048;
+  int64_t tile_bytes = int64_t(1) << 20;  // X bytes per tile of a full step
   int grid = 512;
   int cus = 256;  // compute units of the device
   bool vec = true;
@@ -918,18 +918,29 @@ struct BatchPlan {
   std::vector<FactorJob> h_jobs;
 };
 
-constexpr int kBatchTileFloor = 256;  // no batched tile is shorter (partial pool size)
-constexpr int kBatchMinTile = 1024;   // shortest tile chosen by default
-constexpr int kBatchChunks = 4;     // most row vectors a lane holds in a batched step
+constexpr int kBatchTileFloor = 256;      // no batched tile is shorter (partial pool size)
+constexpr int kBatchTileCeil = 1 << 20;   // nor longer
+constexpr int64_t kBatchMinTileBytes = int64_t(256) << 10;  // smallest tile size chosen by default
+constexpr int kBatchChunks = 4;  // most row vectors a lane holds in a batched step
 
-// shortest tile height a batched step may use (SLSE_BATCH_MIN_TILE overrides)
-int batch_min_tile() {
-  static const int v = [] {
-    int t = kBatchMinTile;
-    if (const char* e = std::getenv("SLSE_BATCH_MIN_TILE")) t = std::max(kBatchTileFloor, std::atoi(e));
+// smallest tile size (bytes of [X|Y]) a batched step may use
+// (SLSE_BATCH_MIN_TILE_KB overrides)
+int64_t batch_min_tile_bytes() {
+  static const int64_t v = [] {
+    int64_t t = kBatchMinTileBytes;
+    if (const char* e = std::getenv("SLSE_BATCH_MIN_TILE_KB"))
+      t = std::max<int64_t>(16 << 10, (int64_t)std::atoi(e) << 10);
     return t;
   }();
   return v;
+}
+
+// rows of a tile holding about `bytes` of [X|Y] rows of `row_bytes` each
+// (a power of 2 between the floor and the ceiling)
+int batch_tile_rows(int64_t bytes, int64_t row_bytes) {
+  int64_t rows = kBatchTileFloor;
+  while (rows * 2 <= kBatchTileCeil && rows * 2 * row_bytes <= bytes) rows *= 2;
+  return (int)rows;
 }
 
 int batch_lpr(int d, bool vec, slse_dtype t) {
@@ -988,18 +999,27 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
     for (int j = 0; j < qs[b].s_max; ++j) add(ps[b].X, ps[b].ldx, ps[b].Y, 1, ps[b].N, 1.0);
     (void)betas;
   }
-  // Tile height per step: the tuned height while the step has plenty of rows;
-  // when only a few (small) problems are still running, shorter tiles (down
-  // to batch_min_tile()) keep at least two tiles per CU.
+  // Tile heights per (step, problem): about the same bytes of [X|Y] per tile
+  // whatever the problem's width, so the grid's strided walk over the tiles
+  // gives every block about the same work.  The tuned size holds while a step
+  // has plenty of rows; when only a few (small) problems are still running,
+  // smaller tiles (down to batch_min_tile_bytes()) keep two tiles per CU.
+  const int64_t es = (int64_t)dtype_size(bp.t);
   for (int t = 0; t < bp.T; ++t) {
-    int64_t rows = 0;
-    for (int b = 0; b < B; ++b) rows += bp.h_steps[(size_t)t * B + b].n;
-    int tile = bp.tile_rows;
-    while (tile > batch_min_tile() && ceil_div(rows, (int64_t)tile) < 2 * (int64_t)bp.cus) tile /= 2;
+    auto tiles_at = [&](int64_t bytes) {
+      int64_t n = 0;
+      for (int b = 0; b < B; ++b) {
+        const BatchStep& st = bp.h_steps[(size_t)t * B + b];
+        n += ceil_div(st.n, (int64_t)batch_tile_rows(bytes, (ps[b].d + 1) * es));
+      }
+      return n;
+    };
+    int64_t bytes = bp.tile_bytes;
+    while (bytes > batch_min_tile_bytes() && tiles_at(bytes) < 2 * (int64_t)bp.cus) bytes /= 2;
     for (int b = 0; b < B; ++b) {
       BatchStep& st = bp.h_steps[(size_t)t * B + b];
-      st.tile_rows = tile;
-      st.ntiles = (int)ceil_div(st.n, (int64_t)tile);
+      st.tile_rows = batch_tile_rows(bytes, (ps[b].d + 1) * es);
+      st.ntiles = (int)ceil_div(st.n, (int64_t)st.tile_rows);
       bp.max_tiles[b] = std::max<int64_t>(bp.max_tiles[b], st.ntiles);
     }
   }
@@ -1290,11 +1310,11 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bool tuned = false;
   if (auto it = ctx->rg_tune.find(key); it != ctx->rg_tune.end()) {
     bp.grid = it->second.first;
-    bp.tile_rows = it->second.second;
+    bp.tile_bytes = (int64_t)it->second.second << 10;
     tuned = true;
   } else {
     bp.grid = 2 * ctx->num_cus;
-    bp.tile_rows = 2048;
+    bp.tile_bytes = int64_t(1) << 20;
   }
   // partial pool sized for the shortest tile a step may use
   int64_t part_n = 0;
@@ -1327,14 +1347,14 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     // time the step with the most tiles for a few (tile, grid) shapes
     const char* env = std::getenv("SLSE_AUTOTUNE");
     const bool do_tune = !(env && std::atoi(env) == 0);
-    std::pair<int, int> best{bp.grid, bp.tile_rows};
+    std::pair<int, int> best{bp.grid, (int)(bp.tile_bytes >> 10)};
     if (do_tune) {
       hipEvent_t e0, e1;
       SLSE_HIP(hipEventCreate(&e0));
       SLSE_HIP(hipEventCreate(&e1));
       float best_ms = 1e30f;
-      for (int tr : {1024, 2048, 4096, 8192}) {
-        bp.tile_rows = tr;
+      for (int kb : {256, 512, 1024, 2048, 4096}) {
+        bp.tile_bytes = (int64_t)kb << 10;
         upload();
         const int tmax = (int)(std::max_element(bp.h_total.begin(), bp.h_total.end()) -
                                bp.h_total.begin());
@@ -1353,7 +1373,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
           SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
           if (ms < best_ms) {
             best_ms = ms;
-            best = {g, tr};
+            best = {g, kb};
           }
         }
       }
@@ -1362,7 +1382,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     }
     ctx->rg_tune[key] = best;
     bp.grid = best.first;
-    bp.tile_rows = best.second;
+    bp.tile_bytes = (int64_t)best.second << 10;
   }
   upload();
   // one graph for the whole batch (sketches, factors, every step)
