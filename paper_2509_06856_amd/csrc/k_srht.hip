@@ -17,6 +17,7 @@
 // signs D on load; the last pass scatters only the sampled rows.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 #include <vector>
 
@@ -47,6 +48,7 @@ struct PassParams {
   int s0;
   int n_ct;
   int64_t xcd_q;  // > 0: blocks [0, 8 xcd_q) are remapped so that each XCD walks a contiguous range
+  int64_t blocks;  // work items (row groups x column tiles) of this pass
 };
 
 // Threads per block: one phase-A item (a column of 2^BA rows) per thread when
@@ -59,8 +61,9 @@ constexpr int pass_threads() {
 // ROUNDS > 1 exchanges the tile through LDS in ROUNDS slices of the high
 // (phase-A) index, so a group of 2^B rows x CT columns needs only 1/ROUNDS of
 // it in LDS; every thread keeps all its phase-A values in registers meanwhile.
+// One work item (row group x column tile) `bid` of a pass.
 template <typename T, int CT, int BA, int BB, int MODE, int ROUNDS>
-__global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_kernel(PassParams<T> P) {
+__device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
   constexpr int NT = pass_threads<CT, BB, ROUNDS>();
   constexpr int RA = 1 << BA;
   constexpr int RB = 1 << BB;
@@ -79,13 +82,6 @@ __global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_ke
   __shared__ int32_t s_pi[(MODE & kFirst) ? (1 << B) : 1];
   __shared__ int32_t s_slot[(MODE & kLast) ? 2 * (1 << B) : 1];
 
-  // Workgroups are dealt to the 8 XCDs round-robin.  Remapping block b to
-  // (b % 8) q + b / 8 hands each XCD a contiguous run of work items, so the
-  // column tiles of one row group run back to back on the same XCD: the
-  // partial cache lines they write meet in that XCD's L2 and the DRAM pages
-  // of the rows they touch are reused while open.
-  int64_t bid = blockIdx.x;
-  if (P.xcd_q > 0 && bid < 8 * P.xcd_q) bid = (bid & 7) * P.xcd_q + (bid >> 3);
   const int ct = (int)(bid % P.n_ct);
   const int64_t g = bid / P.n_ct;
   const int64_t lo = g & ((int64_t(1) << P.s0) - 1);
@@ -227,6 +223,29 @@ __global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_ke
   }
 }
 
+template <typename T, int CT, int BA, int BB, int MODE, int ROUNDS>
+__global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_kernel(PassParams<T> P) {
+  // Workgroups are dealt to the 8 XCDs round-robin.  Remapping block b to
+  // (b % 8) q + b / 8 hands each XCD a contiguous run of work items, so the
+  // column tiles of one row group run back to back on the same XCD: the
+  // partial cache lines they write meet in that XCD's L2 and the DRAM pages
+  // of the rows they touch are reused while open.
+  int64_t bid = blockIdx.x;
+  if (P.xcd_q > 0 && bid < 8 * P.xcd_q) bid = (bid & 7) * P.xcd_q + (bid >> 3);
+  fwht_pass<T, CT, BA, BB, MODE, ROUNDS>(P, bid);
+}
+
+// The same pass for several transforms at once: blockIdx.y picks the
+// transform's parameters, blockIdx.x its work item (blocks past the
+// transform's own count return at once).
+template <typename T, int CT, int BA, int BB, int MODE, int ROUNDS>
+__global__ __launch_bounds__((pass_threads<CT, BB, ROUNDS>())) void fwht_pass_batched_kernel(
+    const PassParams<T>* __restrict__ Ps) {
+  const PassParams<T> P = Ps[blockIdx.y];
+  if ((int64_t)blockIdx.x >= P.blocks) return;
+  fwht_pass<T, CT, BA, BB, MODE, ROUNDS>(P, blockIdx.x);
+}
+
 // Position of row j in the last pass's order: group g = (hi, lo), slot pos.
 __device__ __forceinline__ int64_t last_pass_index(int64_t j, int s0, int B) {
   const int64_t hi = j >> (s0 + B);
@@ -277,6 +296,7 @@ void launch_pass(PassParams<T> P, int64_t npad, hipStream_t s) {
   P.n_ct = (int)(P.ldz / CT);
   const int64_t blocks = groups * P.n_ct;
   if (blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "srht: grid too large");
+  P.blocks = blocks;
   P.xcd_q = P.xcd_q != 0 ? blocks / 8 : 0;
   fwht_pass_kernel<T, CT, BA, BB, MODE, ROUNDS>
       <<<(unsigned)blocks, pass_threads<CT, BB, ROUNDS>(), 0, s>>>(P);
@@ -311,6 +331,49 @@ void dispatch_mode(int mode, int b, PassParams<T> P, int64_t npad, hipStream_t s
     case kFirst: dispatch_b<T, kFirst>(b, P, npad, s); break;
     case kLast: dispatch_b<T, kLast>(b, P, npad, s); break;
     default: dispatch_b<T, kFirst | kLast>(b, P, npad, s); break;
+  }
+}
+
+template <typename T, int B, int MODE>
+void launch_pass_batched(const PassParams<T>* d_params, int count, int64_t max_blocks, hipStream_t s) {
+  constexpr int BA = (B + 1) / 2;
+  constexpr int BB = B / 2;
+  constexpr int CT = ct_of<T>();
+  constexpr int ROUNDS = B > 10 ? 2 : 1;
+  fwht_pass_batched_kernel<T, CT, BA, BB, MODE, ROUNDS>
+      <<<dim3((unsigned)max_blocks, (unsigned)count), pass_threads<CT, BB, ROUNDS>(), 0, s>>>(d_params);
+  SLSE_LAUNCH_CHECK();
+}
+
+template <typename T, int MODE>
+void dispatch_b_batched(int b, const PassParams<T>* d, int count, int64_t max_blocks, hipStream_t s) {
+  switch (b) {
+#define SLSE_CASE(BV) \
+  case BV: launch_pass_batched<T, BV, MODE>(d, count, max_blocks, s); break;
+    SLSE_CASE(1)
+    SLSE_CASE(2)
+    SLSE_CASE(3)
+    SLSE_CASE(4)
+    SLSE_CASE(5)
+    SLSE_CASE(6)
+    SLSE_CASE(7)
+    SLSE_CASE(8)
+    SLSE_CASE(9)
+    SLSE_CASE(10)
+    SLSE_CASE(11)
+#undef SLSE_CASE
+    default: fail(SLSE_EUNSUPPORTED, "srht: bad pass size");
+  }
+}
+
+template <typename T>
+void dispatch_mode_batched(int mode, int b, const PassParams<T>* d, int count, int64_t max_blocks,
+                           hipStream_t s) {
+  switch (mode) {
+    case 0: dispatch_b_batched<T, 0>(b, d, count, max_blocks, s); break;
+    case kFirst: dispatch_b_batched<T, kFirst>(b, d, count, max_blocks, s); break;
+    case kLast: dispatch_b_batched<T, kLast>(b, d, count, max_blocks, s); break;
+    default: dispatch_b_batched<T, kFirst | kLast>(b, d, count, max_blocks, s); break;
   }
 }
 
@@ -350,7 +413,96 @@ void run_passes(const SrhtArgs& a, hipStream_t s) {
   }
 }
 
+// Parameter records of every pass of every transform, ordered by pass round
+// (a transform's passes run in order), then by pass shape; one launch per
+// (round, shape) covers every transform with that pass.
+template <typename T>
+std::vector<SrhtBatchLaunch> batch_plan_t(const std::vector<SrhtArgs>& as, std::vector<char>& rec) {
+  struct Item {
+    int round, mode, b;
+    PassParams<T> P;
+  };
+  std::vector<Item> items;
+  constexpr int CT = ct_of<T>();
+  for (const SrhtArgs& a : as) {
+    if (a.ldz % CT != 0) fail(SLSE_EINVAL, "srht batch: workspace rows must be whole column tiles");
+    PassParams<T> P{};
+    P.X = static_cast<const T*>(a.X);
+    P.ldx = a.ldx;
+    P.Y = static_cast<const T*>(a.Y);
+    P.N = a.N;
+    P.d = a.d;
+    P.pi_sgn = a.pi_sgn;
+    P.Z = static_cast<T*>(a.Z);
+    P.ldz = a.ldz;
+    P.slotA = a.slotA;
+    P.slotH = a.slotH;
+    P.A = static_cast<T*>(a.A);
+    P.lda = a.lda;
+    P.Ahat = static_cast<T*>(a.Ahat);
+    P.ldah = a.ldah;
+    P.xcd_q = 0;
+    P.n_ct = (int)(a.ldz / CT);
+    const std::vector<int> bs = pass_sizes(a.p, a.bmax);
+    if (bs.size() > 1 && a.Z == nullptr) fail(SLSE_EINVAL, "srht batch: missing workspace");
+    int s0 = 0;
+    for (size_t i = 0; i < bs.size(); ++i) {
+      const int mode = (i == 0 ? kFirst : 0) | (i + 1 == bs.size() ? kLast : 0);
+      P.s0 = s0;
+      P.blocks = ((int64_t(1) << a.p) >> bs[i]) * P.n_ct;
+      if (P.blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "srht: grid too large");
+      items.push_back({(int)i, mode, bs[i], P});
+      s0 += bs[i];
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+    if (x.round != y.round) return x.round < y.round;
+    if (x.mode != y.mode) return x.mode < y.mode;
+    return x.b < y.b;
+  });
+  std::vector<SrhtBatchLaunch> L;
+  rec.assign(items.size() * sizeof(PassParams<T>), 0);
+  for (size_t k = 0; k < items.size(); ++k) {
+    std::memcpy(rec.data() + k * sizeof(PassParams<T>), &items[k].P, sizeof(PassParams<T>));
+    const bool same = !L.empty() && k > 0 && items[k - 1].round == items[k].round &&
+                      items[k - 1].mode == items[k].mode && items[k - 1].b == items[k].b &&
+                      L.back().count < 65535;
+    if (!same) {
+      SrhtBatchLaunch l;
+      l.b = items[k].b;
+      l.mode = items[k].mode;
+      l.first = (int)k;
+      L.push_back(l);
+    }
+    L.back().count += 1;
+    L.back().max_blocks = std::max(L.back().max_blocks, items[k].P.blocks);
+  }
+  return L;
+}
+
 }  // namespace
+
+std::vector<SrhtBatchLaunch> srht_batch_plan(const std::vector<SrhtArgs>& as, slse_dtype t,
+                                             std::vector<char>& records) {
+  if (t == SLSE_F64) return batch_plan_t<double>(as, records);
+  if (t == SLSE_F32) return batch_plan_t<float>(as, records);
+  fail(SLSE_EUNSUPPORTED, "srht: dtype");
+}
+
+void launch_srht_batched(const std::vector<SrhtBatchLaunch>& L, const void* d_records, slse_dtype t,
+                         hipStream_t s) {
+  for (const SrhtBatchLaunch& l : L) {
+    if (t == SLSE_F64) {
+      const auto* d = static_cast<const PassParams<double>*>(d_records) + l.first;
+      dispatch_mode_batched<double>(l.mode, l.b, d, l.count, l.max_blocks, s);
+    } else if (t == SLSE_F32) {
+      const auto* d = static_cast<const PassParams<float>*>(d_records) + l.first;
+      dispatch_mode_batched<float>(l.mode, l.b, d, l.count, l.max_blocks, s);
+    } else {
+      fail(SLSE_EUNSUPPORTED, "srht: dtype");
+    }
+  }
+}
 
 void srht_plan(SrhtArgs& a, int prefer_bmax) {
   const int es = (int)dtype_size(a.t);
@@ -372,26 +524,13 @@ size_t srht_z_bytes(const SrhtArgs& a) {
 
 namespace {
 
-__device__ __forceinline__ int find_job(const SrhtIndexJob* __restrict__ jobs, int B, int64_t g,
-                                        bool hat) {
-  int lo = 0, hi = B;  // base(lo) <= g < base(hi)
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((hat ? jobs[mid].hbase : jobs[mid].base) <= g)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// every row index of every job: pi_sgn, slotA (as srht_index_kernel) and slotH = -1
-__global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs, int B,
-                                          int64_t total) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const SrhtIndexJob jb = jobs[find_job(jobs, B, g, false)];
-    const int64_t j = g - jb.base;
+// Index maps of many transforms: blockIdx.y picks the job (its fields are
+// uniform over the block), blockIdx.x and the threads stride over its rows.
+// Every row index: pi_sgn, slotA (as srht_index_kernel) and slotH = -1.
+__global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs) {
+  const SrhtIndexJob jb = jobs[blockIdx.y];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < jb.npad;
+       j += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t src = rng::prp((uint64_t)j, jb.seed, rng::kStreamP, jb.p);
     const int D = rng::rademacher(jb.seed, (uint64_t)j);
     jb.pi_sgn[j] = D > 0 ? (int32_t)src : ~(int32_t)src;
@@ -402,12 +541,10 @@ __global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs,
 }
 
 // every Hessian sample of every job (after the kernel above)
-__global__ void srht_hat_batched_kernel(const SrhtIndexJob* __restrict__ jobs, int B,
-                                        int64_t total) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const SrhtIndexJob jb = jobs[find_job(jobs, B, g, true)];
-    const int64_t t = g - jb.hbase;
+__global__ void srht_hat_batched_kernel(const SrhtIndexJob* __restrict__ jobs) {
+  const SrhtIndexJob jb = jobs[blockIdx.y];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < jb.r;
+       t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = (int64_t)rng::prp((uint64_t)t, jb.seed, rng::kStreamShat, jb.p);
     jb.slotH[last_pass_index(j, jb.s0_last, jb.b_last)] = (int32_t)t;
   }
@@ -421,16 +558,21 @@ void srht_last_pass(const SrhtArgs& a, int* s0_last, int* b_last) {
   *s0_last = a.p - bs.back();
 }
 
-void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t total_rows,
-                               int64_t total_hat, hipStream_t s) {
+void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t max_npad, int64_t max_r,
+                               hipStream_t s) {
   if (B <= 0) return;
   const int threads = 256;
-  const int b1 = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total_rows, threads), 16384));
-  srht_index_batched_kernel<<<b1, threads, 0, s>>>(jobs, B, total_rows);
-  SLSE_LAUNCH_CHECK();
-  const int b2 = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total_hat, threads), 16384));
-  srht_hat_batched_kernel<<<b2, threads, 0, s>>>(jobs, B, total_hat);
-  SLSE_LAUNCH_CHECK();
+  // about four rows per thread in the largest job; blocks past a smaller
+  // job's rows return at once
+  for (int j0 = 0; j0 < B; j0 += 65535) {
+    const int nb = std::min(65535, B - j0);
+    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(max_npad, 4 * threads), 4096));
+    srht_index_batched_kernel<<<dim3(bx, nb), threads, 0, s>>>(jobs + j0);
+    SLSE_LAUNCH_CHECK();
+    const int hx = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(max_r, 4 * threads), 4096));
+    srht_hat_batched_kernel<<<dim3(hx, nb), threads, 0, s>>>(jobs + j0);
+    SLSE_LAUNCH_CHECK();
+  }
 }
 
 void launch_srht(const SrhtArgs& a, hipStream_t s) {

@@ -2,6 +2,8 @@
 // `stream` and checks the launch; shapes are validated by the caller.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace slse {
@@ -146,11 +148,27 @@ struct SrhtIndexJob {
 };
 // b_last / s0_last of the pass split srht_plan chooses for `a` (a.p, a.bmax set)
 void srht_last_pass(const SrhtArgs& a, int* s0_last, int* b_last);
-void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t total_rows,
-                               int64_t total_hat, hipStream_t s);
+// index maps of B jobs (max_npad / max_r: the largest npad and r among them)
+void launch_srht_index_batched(const SrhtIndexJob* jobs, int B, int64_t max_npad, int64_t max_r,
+                               hipStream_t s);
 size_t srht_z_bytes(const SrhtArgs& a);
 void launch_srht(const SrhtArgs& a, hipStream_t s);
 
+// SRHT passes of many transforms in shared launches (index maps already
+// built, one workspace Z per multi-pass transform).  srht_batch_plan writes
+// the device parameter records into `records` (host bytes, to be uploaded by
+// the caller) and returns the launches; launch_srht_batched enqueues them.
+struct SrhtBatchLaunch {
+  int b = 0;     // butterfly stages of the pass
+  int mode = 0;  // first / last pass flags
+  int first = 0;  // first record of the launch
+  int count = 0;  // transforms in the launch
+  int64_t max_blocks = 0;
+};
+std::vector<SrhtBatchLaunch> srht_batch_plan(const std::vector<SrhtArgs>& as, slse_dtype t,
+                                             std::vector<char>& records);
+void launch_srht_batched(const std::vector<SrhtBatchLaunch>& L, const void* d_records, slse_dtype t,
+                         hipStream_t s);
 // --------------------------------------------------------------------------
 // CountSketch and Gaussian sketches.
 // --------------------------------------------------------------------------

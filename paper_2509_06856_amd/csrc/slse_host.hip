@@ -908,7 +908,13 @@ struct BatchPlan {
   std::vector<SrhtIndexJob> h_sjobs;
   SrhtIndexJob* d_sjobs = nullptr;
   std::vector<int64_t> s_off;  // offset of problem b in the index pools (-1: not SRHT)
-  int64_t s_rows = 0, s_hat = 0;
+  // SRHT passes of every SRHT problem in shared launches (each with its own Z)
+  std::vector<SrhtBatchLaunch> srht_launches;
+  std::vector<char> h_srec;
+  void* d_srec = nullptr;
+  std::vector<char> srht_batched;  // problem b's sketch runs in the shared launches
+  int64_t s_rows = 0, s_hat = 0;          // index-map rows and Hessian samples of all jobs
+  int64_t s_max_npad = 0, s_max_r = 0;   // the largest of one job
   int32_t *s_pi = nullptr, *s_sa = nullptr, *s_sh = nullptr;
   // Cholesky route for every problem: one batched factorization
   bool batched_factor = false;
@@ -922,6 +928,7 @@ constexpr int kBatchTileFloor = 256;      // no batched tile is shorter (partial
 constexpr int kBatchTileCeil = 1 << 20;   // nor longer
 constexpr int64_t kBatchMinTileBytes = int64_t(256) << 10;  // smallest tile size chosen by default
 constexpr int kBatchChunks = 4;  // most row vectors a lane holds in a batched step
+constexpr size_t kBatchSrhtZMax = size_t(16) << 30;  // workspace cap for shared SRHT launches
 
 // smallest tile size (bytes of [X|Y]) a batched step may use
 // (SLSE_BATCH_MIN_TILE_KB overrides)
@@ -1098,8 +1105,10 @@ void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_param
   launch_fill_i32(bp.flags, 0, bp.B, st);
   launch_fill_i32(bp.finfo, 0, 3 * (int64_t)bp.B, st);
   if (!bp.h_sjobs.empty())
-    launch_srht_index_batched(bp.d_sjobs, (int)bp.h_sjobs.size(), bp.s_rows, bp.s_hat, st);
-  for (int b = 0; b < bp.B; ++b) enqueue_batch_sketch(bp, b, ps, qs, st);
+    launch_srht_index_batched(bp.d_sjobs, (int)bp.h_sjobs.size(), bp.s_max_npad, bp.s_max_r, st);
+  if (!bp.srht_launches.empty()) launch_srht_batched(bp.srht_launches, bp.d_srec, bp.t, st);
+  for (int b = 0; b < bp.B; ++b)
+    if (bp.srht_batched.empty() || !bp.srht_batched[b]) enqueue_batch_sketch(bp, b, ps, qs, st);
   if (bp.batched_factor)
     launch_factor_batched(bp.d_jobs, bp.B, bp.dmax, bp.rmax, bp.t, st);
   else
@@ -1208,6 +1217,8 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     bp.s_off[b] = bp.s_rows;
     bp.s_rows += sk.n_pad;
     bp.s_hat += sk.r;
+    bp.s_max_npad = std::max<int64_t>(bp.s_max_npad, sk.n_pad);
+    bp.s_max_r = std::max<int64_t>(bp.s_max_r, sk.r);
     bp.h_sjobs.push_back(j);
   }
   if (!bp.h_sjobs.empty()) {
@@ -1220,6 +1231,44 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
       j.slotH = bp.s_sh + j.base;
     }
     bp.d_sjobs = ctx->arena.get_t<SrhtIndexJob>("bSrhtJobs", bp.h_sjobs.size());
+    // the passes of every SRHT in shared launches, each transform with its
+    // own workspace (skipped when those would exceed kBatchSrhtZMax bytes)
+    std::vector<SrhtArgs> sas;
+    std::vector<int> who;
+    size_t zsum = 0;
+    for (int b = 0; b < B; ++b) {
+      if (bp.s_off[b] < 0) continue;
+      const SketchShape& sk = bp.sk[b];
+      SrhtArgs sa;
+      sa.t = bp.t;
+      sa.N = sk.N;
+      sa.d = (int)ps[b].d;
+      sa.p = sk.p;
+      srht_plan(sa, 0);
+      sa.X = ps[b].X;
+      sa.ldx = ps[b].ldx;
+      sa.Y = ps[b].Y;
+      sa.A = bp.Apool + bp.a_off[b];
+      sa.lda = bp.lda[b];
+      sa.Ahat = bp.Ahpool + bp.ah_off[b];
+      sa.ldah = bp.lda[b];
+      sa.pi_sgn = bp.s_pi + bp.s_off[b];
+      sa.slotA = bp.s_sa + bp.s_off[b];
+      sa.slotH = bp.s_sh + bp.s_off[b];
+      sa.Z = reinterpret_cast<void*>(zsum);  // offset until the pool exists
+      zsum += round_up((int64_t)srht_z_bytes(sa), 256);
+      sas.push_back(sa);
+      who.push_back(b);
+    }
+    bp.srht_batched.assign(B, 0);
+    if (!sas.empty() && zsum <= kBatchSrhtZMax) {
+      char* zpool = zsum ? static_cast<char*>(ctx->arena.get("bSrhtZ", zsum)) : nullptr;
+      for (SrhtArgs& sa : sas)
+        sa.Z = srht_z_bytes(sa) ? zpool + reinterpret_cast<uintptr_t>(sa.Z) : nullptr;
+      bp.srht_launches = srht_batch_plan(sas, bp.t, bp.h_srec);
+      bp.d_srec = ctx->arena.get("bSrhtRec", bp.h_srec.size());
+      for (int b : who) bp.srht_batched[b] = 1;
+    }
   }
   bp.srht.t = bp.t;
   bp.ga.t = bp.gh.t = bp.t;
@@ -1332,6 +1381,8 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   SLSE_HIP(hipMemcpy(bp.d_probs, bp.h_probs.data(), sizeof(BatchProblem) * B, hipMemcpyHostToDevice));
   if (bp.batched_factor)
     SLSE_HIP(hipMemcpy(bp.d_jobs, bp.h_jobs.data(), sizeof(FactorJob) * B, hipMemcpyHostToDevice));
+  if (!bp.h_srec.empty())
+    SLSE_HIP(hipMemcpy(bp.d_srec, bp.h_srec.data(), bp.h_srec.size(), hipMemcpyHostToDevice));
   if (!bp.h_sjobs.empty())
     SLSE_HIP(hipMemcpy(bp.d_sjobs, bp.h_sjobs.data(), sizeof(SrhtIndexJob) * bp.h_sjobs.size(),
                        hipMemcpyHostToDevice));
