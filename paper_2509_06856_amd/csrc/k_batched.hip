@@ -73,7 +73,9 @@ template <typename T, int VEC, int NCH>
 __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
     const BatchStep* __restrict__ steps, const BatchProblem* __restrict__ probs,
     const int* __restrict__ prefix, int B, int total_tiles, double* __restrict__ pool) {
-  constexpr int UNROLL = 4;
+  // rows in flight per lane group: two with four chunks per lane (fewer
+  // registers, measured faster than four), else four
+  constexpr int UNROLL = NCH >= 4 ? 2 : 4;
   __shared__ double s_red[kWaves][kMaxD + 1];
   __shared__ int s_prefix[kPrefixLds + 1];
   const int lane = threadIdx.x & 63;
