@@ -300,6 +300,20 @@ def bench_backward(args, G, torch, dev):
     m = G.paper_schedule(N, d)
     params = G.Params(kind="srht", seed=sketch_seed("backward"), m=m, a=[2] * len(m), r=6 * d,
                       precision="mixed")
+    if args.kernel_only:
+        # the rank-2 pass (lambda_0 = M w, then one read of [X|Y] and one write
+        # of [dX|dY] in float32), ten times, then a copy of X
+        p0 = G.Params(**{**params.__dict__, "s_max": 0})
+        b0 = torch.from_numpy(bstar).to(dev)
+        for _ in range(10):
+            G.backward(X, Y, p0, b0, w)
+        torch.cuda.synchronize()
+        log(f"rank-2 pass: 10 calls, N={N}, d={d}")
+        for _ in range(3):
+            Z = X.clone()
+        torch.cuda.synchronize()
+        log(f"copy reference: {X.numel() * X.element_size()} bytes read and written per launch")
+        return
     s_star, _ = calibrate(G, torch, X, Y, params, bstar, args.tol, args.s_cap)
     if s_star is None:
         print("forward solve did not reach the tolerance", file=sys.stderr)
@@ -467,7 +481,11 @@ def main():
                     help="skip the sketch-kernel and device-copy measurements")
     ap.add_argument("--cpu-rows", type=int, default=1 << 17)
     ap.add_argument("--kernel-only", action="store_true",
-                    help="only loop the fused residual-gradient kernel (for counter runs)")
+                    help="only loop the fused residual-gradient kernel (backward: the rank-2 "
+                         "adjoint pass), then a copy of X (for counter runs)")
+    ap.add_argument("--sketch-only", action="store_true",
+                    help="only loop the SRHT and CountSketch sketches, then a copy of X "
+                         "(for counter runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -513,6 +531,18 @@ def main():
                       precision="mixed" if mixed else "f64")
     bytes_per_sweep = N * (d + 1) * X.element_size()
 
+    if args.sketch_only:
+        # three SRHT sketches (m_K + r rows), three CountSketches (every level)
+        for kind, mm in (("srht", [m[-1]]), ("countsketch", m)):
+            for _ in range(3):
+                G.sketch_apply(X, Y, kind, params.seed, mm, 6 * d)
+            torch.cuda.synchronize()
+            log(f"{kind}: 3 sketches of N={N}, m_K={mm[-1]}, r={6 * d}")
+        for _ in range(3):
+            Z = X.clone()
+        torch.cuda.synchronize()
+        log(f"copy reference: {X.numel() * X.element_size()} bytes read and written per launch")
+        return
     if args.kernel_only:
         beta0 = torch.from_numpy(beta_star).to(dev)
         t_k = time_resid_grad(G, torch, X, Y, beta0, reps=50)
