@@ -262,6 +262,111 @@ __global__ void cs_fold_kernel(const T* __restrict__ src, T* __restrict__ dst, i
   }
 }
 
+// Several levels at once by repeated halving, fold(A)[k] = A[k] + A[k + m/2]:
+// work item (group g < mT, column tile) holds rows g + q mT, q < R, of the
+// source level (R = m_S / mT rows, a power of 2 up to kFoldMax) in LDS and
+// halves them down to one row; after the halving to s rows, the level of
+// s mT rows (when the schedule has it) gets rows g + q mT, q < s.  Work
+// items are dealt to the XCDs in contiguous runs, so the column tiles of one
+// group (the same rows) run back to back on one XCD.
+constexpr int kFoldMax = 512;  // source rows per group
+template <typename T, int VEC>
+struct FoldVec {
+  using type = T __attribute__((ext_vector_type(VEC)));
+};
+template <typename T>
+struct FoldVec<T, 1> {
+  using type = T;
+};
+struct FoldTargets {
+  int64_t off[10];  // off[lg]: first row (in A) of the level of 2^lg mT rows, or -1
+};
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(256) void cs_fold_tree_kernel(const T* __restrict__ src,
+                                                           T* __restrict__ A, int64_t lda,
+                                                           int64_t mT, int lgR, int cols, int n_ct,
+                                                           int64_t xcd_q, FoldTargets tg) {
+  constexpr int CT = 128 / (int)sizeof(T);  // columns per tile (128 bytes)
+  constexpr int NV = CT / VEC;              // vectors per row segment
+  __shared__ __attribute__((aligned(16))) T tile[kFoldMax * CT];
+  int64_t bid = blockIdx.x;
+  if (xcd_q > 0 && bid < 8 * xcd_q) bid = (bid & 7) * xcd_q + (bid >> 3);
+  const int ct = (int)(bid % n_ct);
+  const int64_t g = bid / n_ct;
+  const int c0 = ct * CT;
+  const int R = 1 << lgR;
+  using V = typename FoldVec<T, VEC>::type;
+  // load the group's R rows of this column tile (whole vectors inside the
+  // row), eight vectors per thread in flight
+  constexpr int U = 8;
+  for (int base = threadIdx.x; base < R * NV; base += 256 * U) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * 256;
+      const int q = e / NV, cv = (e % NV) * VEC;
+      const int col = c0 + cv;
+      const T* p = src + (g + (int64_t)(e < R * NV ? q : 0) * mT) * lda + col;
+      if (e < R * NV && col + VEC <= cols) {
+        if constexpr (VEC == 1) {
+          v[u] = __builtin_nontemporal_load(p);
+        } else {
+          v[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          const T x = (e < R * NV && col + k < cols) ? p[k] : (T)0;
+          if constexpr (VEC == 1) {
+            v[u] = x;
+          } else {
+            v[u][k] = x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * 256;
+      if (e < R * NV) *reinterpret_cast<V*>(&tile[(e / NV) * CT + (e % NV) * VEC]) = v[u];
+    }
+  }
+  __syncthreads();
+  for (int lg = lgR - 1; lg >= 0; --lg) {
+    const int sz = 1 << lg;
+    const int64_t off = tg.off[lg];
+    for (int e = threadIdx.x; e < sz * NV; e += 256) {
+      const int q = e / NV, cv = (e % NV) * VEC;
+      V a = *reinterpret_cast<const V*>(&tile[q * CT + cv]);
+      const V b = *reinterpret_cast<const V*>(&tile[(q + sz) * CT + cv]);
+      a = a + b;
+      *reinterpret_cast<V*>(&tile[q * CT + cv]) = a;
+      if (off >= 0) {
+        const int col = c0 + cv;
+        T* p = A + (off + g + (int64_t)q * mT) * lda + col;
+        if (col + VEC <= cols) {
+          if constexpr (VEC == 1) {
+            __builtin_nontemporal_store(a, p);
+          } else {
+            __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) {
+            if constexpr (VEC == 1) {
+              if (col + k < cols) p[k] = a;
+            } else {
+              if (col + k < cols) p[k] = a[k];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gaussian entries: u = (w32 + 1/2) 2^-32, z = sqrt(-2 ln u1) (cos | sin)(2 pi u2)
 // ---------------------------------------------------------------------------
@@ -570,6 +675,50 @@ void gather(int64_t nb, int parts, const CountSketchArgs& a, const int* off, con
   SLSE_LAUNCH_CHECK();
 }
 
+// Levels K-2 .. 0 from level K-1 (stored at row offK of A; level i sits just
+// before level i + 1).  Each pass folds a source level down as far as kFoldMax
+// rows per group allow and writes every level on the way; a step between two
+// levels wider than that falls back to the one-level fold.
+template <typename T>
+void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, hipStream_t s) {
+  std::vector<int64_t> off(a.K);
+  off[a.K - 1] = offK;
+  for (int i = a.K - 2; i >= 0; --i) off[i] = off[i + 1] - a.m[i];
+  const int cols = a.d + 1;
+  constexpr int CT = 128 / (int)sizeof(T);
+  const int n_ct = (int)ceil_div(cols, CT);
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((a.lda * (int64_t)sizeof(T)) % 16 == 0);
+  int S = a.K - 1;
+  while (S > 0) {
+    int Tl = S;
+    while (Tl > 0 && a.m[S] / a.m[Tl - 1] <= kFoldMax) --Tl;
+    if (Tl == S) {  // the next level is more than kFoldMax times smaller
+      const int i = S - 1;
+      cs_fold_kernel<T><<<(unsigned)std::min<int64_t>(a.m[i], 65536), 256, 0, s>>>(
+          A + off[S] * a.lda, A + off[i] * a.lda, a.m[i], (int)(a.m[S] / a.m[i]), cols, a.lda);
+      SLSE_LAUNCH_CHECK();
+      S = i;
+      continue;
+    }
+    const int64_t mT = a.m[Tl];
+    const int lgR = ilog2_exact(a.m[S] / mT);
+    FoldTargets tg;
+    for (int k = 0; k < 10; ++k) tg.off[k] = -1;
+    for (int i = Tl; i < S; ++i) tg.off[ilog2_exact(a.m[i] / mT)] = off[i];
+    const int64_t blocks = mT * n_ct;
+    if (blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "countsketch: too many fold work items");
+    const int64_t xq = blocks / 8;
+    if (vec)
+      cs_fold_tree_kernel<T, 16 / sizeof(T)><<<(unsigned)blocks, 256, 0, s>>>(
+          A + off[S] * a.lda, A, a.lda, mT, lgR, cols, n_ct, xq, tg);
+    else
+      cs_fold_tree_kernel<T, 1><<<(unsigned)blocks, 256, 0, s>>>(A + off[S] * a.lda, A, a.lda, mT,
+                                                                 lgR, cols, n_ct, xq, tg);
+    SLSE_LAUNCH_CHECK();
+    S = Tl;
+  }
+}
+
 template <typename T>
 void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   if (a.N >= (int64_t(1) << 31)) fail(SLSE_EUNSUPPORTED, "countsketch: N >= 2^31 rows");
@@ -611,16 +760,8 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
                                                              a.ldah);
     SLSE_LAUNCH_CHECK();
   }
-  // 5. smaller levels by folding
-  int64_t off_hi = offK;
-  for (int i = a.K - 2; i >= 0; --i) {
-    const int64_t off_lo = off_hi - a.m[i];
-    const int ratio = (int)(a.m[i + 1] / a.m[i]);
-    cs_fold_kernel<T><<<(unsigned)std::min<int64_t>(a.m[i], 65536), 256, 0, s>>>(
-        A + off_hi * a.lda, A + off_lo * a.lda, a.m[i], ratio, a.d + 1, a.lda);
-    SLSE_LAUNCH_CHECK();
-    off_hi = off_lo;
-  }
+  // 5. smaller levels by folding, several levels per pass
+  fold_levels<T>(a, A, offK, s);
 }
 
 template <typename T>

@@ -242,6 +242,9 @@ def test_srht_two_eleven_stage_passes(G):
     (60000, 3, [16384, 32768], 9000),     # S_hat counted with global atomics (r > 8192)
     (5000, 33, [2048, 4096], 40),         # many empty buckets in the largest level
     (7, 2, [2, 4], 3),                    # tiny
+    (40000, 40, [64, 512, 4096], 100),    # levels 8x apart, folded in one pass
+    (70000, 7, [16, 16384], 50),          # levels 1024x apart: the one-level fold
+    (150000, 36, [64 << k for k in range(11)], 200),  # 11 levels: two multi-level passes
 ])
 def test_countsketch_parity(G, dtype, N, d, m, r):
     g = np.random.default_rng(N + d)
