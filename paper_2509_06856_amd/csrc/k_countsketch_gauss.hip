@@ -497,10 +497,16 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 // ---------------------------------------------------------------------------
 // Gaussian sketch on the matrix cores: G and [X|Y] rounded to BF16 (nearest
 // even), products accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  Block
-// tile 128 sketch rows x 128 columns, one wave per 32 rows, four 32 x 32
-// accumulators per wave; 16 data rows per step, G generated into LDS by the
-// block (one Philox block per thread per step), [X|Y] staged transposed so
-// that every lane reads its 8 consecutive k as one 16-byte load.
+// tile kMT sketch rows x kNT columns, one wave per 32 rows, kNT / 32
+// accumulators of 32 x 32 per wave; 16 data rows per step, G generated into
+// LDS by the block (one Philox block per thread per step), [X|Y] staged
+// transposed so that every lane reads its 8 consecutive k as one 16-byte load.
+// Two costs set the tile: every block of sketch rows stages [X|Y] again
+// (BF16 conversion, transposed LDS stores; measured about 3 ms per 2^22 x 513
+// pass) and every block of columns generates G again (about 15 ms per
+// 3072 x 2^22 entries), while the waves need four per SIMD to hide their
+// latencies.  512 x 160 (the largest block, five accumulators per wave within
+// 128 registers) measured best: 256 x 288 at two waves per SIMD was slower.
 // Lane layout (checked by an in-bounds probe): lane l holds A[l%32][8(l/32)+j]
 // and B[8(l/32)+j][l%32], j < 8; accumulator r of lane l is
 // C[(r%4) + 8(r/4) + 4(l/32)][l%32].
@@ -508,8 +514,9 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-constexpr int kMT = 128;  // sketch rows per block
-constexpr int kNT = 128;  // columns per block
+constexpr int kMT = 512;  // sketch rows per block
+constexpr int kGThreads = kMT / 32 * 64;  // one wave per 32 sketch rows
+constexpr int kNT = 160;  // columns per block
 constexpr int kKT = 16;   // data rows per step
 constexpr int kKP = kKT + 8;  // padded LDS row (bf16 elements)
 
@@ -520,7 +527,7 @@ __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const T* __restrict__ X,
+__global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d, const T* __restrict__ X,
                                                          int64_t ldx, const T* __restrict__ Y,
                                                          uint64_t seed, uint64_t stream, int64_t m,
                                                          int splits, float* __restrict__ part,
@@ -535,14 +542,16 @@ __global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const
   const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
   const int64_t j_begin = (int64_t)split * per;
   const int64_t j_end = min(N, j_begin + per);
-  f32x16_t acc[4];
+  constexpr int NQ = kNT / 32;
+  f32x16_t acc[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kKT) {
     {  // G tile: thread -> (row block of 8, data row)
-      const int kb = threadIdx.x / kKT;  // 0..15
+      static_assert(kMT / 8 * kKT == kGThreads, "one Philox block per thread per step");
+      const int kb = threadIdx.x / kKT;  // group of 8 sketch rows
       const int jj = threadIdx.x % kKT;
       const int64_t j = j0 + jj;
       float z[8];
@@ -555,7 +564,7 @@ __global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const
 #pragma unroll
       for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
     }
-    for (int e = threadIdx.x; e < kKT * kNT; e += 256) {  // [X|Y] tile, stored transposed
+    for (int e = threadIdx.x; e < kKT * kNT; e += kGThreads) {  // [X|Y] tile, stored transposed
       const int jj = e / kNT, cc = e % kNT;
       const int64_t j = j0 + jj;
       const int col = c0 + cc;
@@ -571,14 +580,14 @@ __global__ __launch_bounds__(256) void gauss_mfma_kernel(int64_t N, int d, const
     __syncthreads();
     const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[wave * 32 + (lane & 31)][8 * (lane >> 5)]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Ws[q * 32 + (lane & 31)][8 * (lane >> 5)]);
       acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t k = k0 + wave * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
@@ -771,7 +780,7 @@ void gaussian_mfma_t(const GaussianArgs& a, hipStream_t s) {
   // blockIdx.x is the sketch-row block: the blocks that read the same data
   // rows and columns run side by side and share them through the caches
   dim3 grid((unsigned)ceil_div(a.m, kMT), (unsigned)ceil_div(cols, kNT), (unsigned)a.splits);
-  gauss_mfma_kernel<T><<<grid, 256, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
+  gauss_mfma_kernel<T><<<grid, kGThreads, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
                                             static_cast<const T*>(a.Y), a.seed, a.stream_id, a.m,
                                             a.splits, a.partial, ldp);
   SLSE_LAUNCH_CHECK();
