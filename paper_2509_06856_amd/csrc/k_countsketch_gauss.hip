@@ -514,11 +514,17 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-constexpr int kMT = 512;  // sketch rows per block
-constexpr int kGThreads = kMT / 32 * 64;  // one wave per 32 sketch rows
-constexpr int kNT = 160;  // columns per block
-constexpr int kKT = 16;   // data rows per step
-constexpr int kKP = kKT + 8;  // padded LDS row (bf16 elements)
+// 16 x 1 waves measured best (166 ms for two 3072-row sketches; 8 x 2 with
+// 32-row steps 182 ms, 4 x 4 with 64-row steps 265 ms)
+constexpr int kRG = 16;             // waves along the sketch rows (32 rows each)
+constexpr int kCG = 1;              // waves along the columns
+constexpr int kNQ = 5;              // 32-column tiles per wave
+constexpr int kMT = 32 * kRG;       // sketch rows per block
+constexpr int kNT = 32 * kNQ * kCG; // columns per block
+constexpr int kGThreads = 64 * kRG * kCG;
+constexpr int kKT = 8 * kGThreads / kMT;  // data rows per step: one Philox block per thread
+constexpr int kKP = kKT + 8;        // padded LDS row (bf16 elements)
+static_assert(kKT % 16 == 0, "steps are whole MFMA k-blocks");
 
 __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
   uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -542,7 +548,9 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
   const int64_t j_begin = (int64_t)split * per;
   const int64_t j_end = min(N, j_begin + per);
-  constexpr int NQ = kNT / 32;
+  constexpr int NQ = kNQ;
+  const int rg = wave % kRG;  // 32-row group
+  const int cg = wave / kRG;  // column group
   f32x16_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -578,11 +586,16 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
       Ws[cc][jj] = to_bf16_rne(v);
     }
     __syncthreads();
-    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[wave * 32 + (lane & 31)][8 * (lane >> 5)]);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Ws[q * 32 + (lane & 31)][8 * (lane >> 5)]);
-      acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+    for (int ks = 0; ks < kKT / 16; ++ks) {
+      const int kk = 16 * ks + 8 * (lane >> 5);
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[rg * 32 + (lane & 31)][kk]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const bf16x8_t b =
+            *reinterpret_cast<const bf16x8_t*>(&Ws[(cg * NQ + q) * 32 + (lane & 31)][kk]);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
@@ -590,8 +603,8 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t k = k0 + wave * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
-      const int col = c0 + q * 32 + (lane & 31);
+      const int64_t k = k0 + rg * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
+      const int col = c0 + (cg * NQ + q) * 32 + (lane & 31);
       if (k < m && col <= d) part[((int64_t)split * m + k) * ldp + col] = acc[q][r];
     }
 }
