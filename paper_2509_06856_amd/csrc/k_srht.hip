@@ -27,7 +27,10 @@
 namespace slse {
 namespace {
 
-enum { kFirst = 1, kLast = 2 };
+// kGroupOrder (two-pass transforms): the workspace Z holds its rows in the
+// last pass's group order, so the last pass reads each group as contiguous
+// rows and the first pass writes them at a stride instead
+enum { kFirst = 1, kLast = 2, kGroupOrder = 4 };
 
 template <typename T>
 struct PassParams {
@@ -49,6 +52,7 @@ struct PassParams {
   int n_ct;
   int64_t xcd_q;  // > 0: blocks [0, 8 xcd_q) are remapped so that each XCD walks a contiguous range
   int64_t blocks;  // work items (row groups x column tiles) of this pass
+  int zb;          // kGroupOrder: stages of the last pass
 };
 
 // Threads per block: one phase-A item (a column of 2^BA rows) per thread when
@@ -148,7 +152,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
 #pragma unroll
       for (int k = 0; k < RA; ++k) {
         const int64_t pos = q + (k << BB);
-        const int64_t j = hi_part | (pos << P.s0) | lo;
+        const int64_t j = (MODE & kGroupOrder) ? ((g << B) | pos) : (hi_part | (pos << P.s0) | lo);
         v[ia][k] = __builtin_nontemporal_load(P.Z + j * P.ldz + col);
       }
     }
@@ -215,7 +219,9 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
           const int64_t pos = ((int64_t)qq << BB) + k;
-          const int64_t j = hi_part | (pos << P.s0) | lo;
+          // group order: the first pass (s0 = 0) holds rows (g, pos), which
+          // the last pass's group pos reads at slot g
+          const int64_t j = (MODE & kGroupOrder) ? ((pos << P.zb) | g) : (hi_part | (pos << P.s0) | lo);
           __builtin_nontemporal_store(w[k], P.Z + j * P.ldz + col);
         }
       }
@@ -330,6 +336,8 @@ void dispatch_mode(int mode, int b, PassParams<T> P, int64_t npad, hipStream_t s
     case 0: dispatch_b<T, 0>(b, P, npad, s); break;
     case kFirst: dispatch_b<T, kFirst>(b, P, npad, s); break;
     case kLast: dispatch_b<T, kLast>(b, P, npad, s); break;
+    case kFirst | kGroupOrder: dispatch_b<T, kFirst | kGroupOrder>(b, P, npad, s); break;
+    case kLast | kGroupOrder: dispatch_b<T, kLast | kGroupOrder>(b, P, npad, s); break;
     default: dispatch_b<T, kFirst | kLast>(b, P, npad, s); break;
   }
 }
@@ -373,6 +381,12 @@ void dispatch_mode_batched(int mode, int b, const PassParams<T>* d, int count, i
     case 0: dispatch_b_batched<T, 0>(b, d, count, max_blocks, s); break;
     case kFirst: dispatch_b_batched<T, kFirst>(b, d, count, max_blocks, s); break;
     case kLast: dispatch_b_batched<T, kLast>(b, d, count, max_blocks, s); break;
+    case kFirst | kGroupOrder:
+      dispatch_b_batched<T, kFirst | kGroupOrder>(b, d, count, max_blocks, s);
+      break;
+    case kLast | kGroupOrder:
+      dispatch_b_batched<T, kLast | kGroupOrder>(b, d, count, max_blocks, s);
+      break;
     default: dispatch_b_batched<T, kFirst | kLast>(b, d, count, max_blocks, s); break;
   }
 }
@@ -382,6 +396,16 @@ std::vector<int> pass_sizes(int p, int bmax) {
   std::vector<int> b(npass, p / npass);
   for (int i = 0; i < p % npass; ++i) b[i] += 1;
   return b;
+}
+
+// whether two-pass transforms keep Z in the last pass's group order
+// (SLSE_SRHT_GROUP_ORDER overrides)
+bool srht_group_order() {
+  static const bool v = [] {
+    const char* e = std::getenv("SLSE_SRHT_GROUP_ORDER");
+    return e ? std::atoi(e) != 0 : true;
+  }();
+  return v;
 }
 
 template <typename T>
@@ -407,6 +431,8 @@ void run_passes(const SrhtArgs& a, hipStream_t s) {
   int s0 = 0;
   for (size_t i = 0; i < bs.size(); ++i) {
     int mode = (i == 0 ? kFirst : 0) | (i + 1 == bs.size() ? kLast : 0);
+    if (bs.size() == 2 && srht_group_order()) mode |= kGroupOrder;
+    P.zb = bs.back();
     P.s0 = s0;
     dispatch_mode<T>(mode, bs[i], P, npad, s);
     s0 += bs[i];
@@ -447,7 +473,9 @@ std::vector<SrhtBatchLaunch> batch_plan_t(const std::vector<SrhtArgs>& as, std::
     if (bs.size() > 1 && a.Z == nullptr) fail(SLSE_EINVAL, "srht batch: missing workspace");
     int s0 = 0;
     for (size_t i = 0; i < bs.size(); ++i) {
-      const int mode = (i == 0 ? kFirst : 0) | (i + 1 == bs.size() ? kLast : 0);
+      int mode = (i == 0 ? kFirst : 0) | (i + 1 == bs.size() ? kLast : 0);
+      if (bs.size() == 2 && srht_group_order()) mode |= kGroupOrder;
+      P.zb = bs.back();
       P.s0 = s0;
       P.blocks = ((int64_t(1) << a.p) >> bs[i]) * P.n_ct;
       if (P.blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "srht: grid too large");
