@@ -479,7 +479,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sketches", action="store_true",
                     help="skip the sketch-kernel and device-copy measurements")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 17)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 19)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only loop the fused residual-gradient kernel (backward: the rank-2 "
                          "adjoint pass), then a copy of X (for counter runs)")

@@ -117,3 +117,23 @@ def test_batched_f32_mixed_reaches_ols(G):
         for b in range(len(probs)):
             assert infos[b]["status"] == "SLSE_OK"
             assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-10, (call, b)
+
+
+def test_batched_f32_odd_widths_reach_ols(G):
+    # float32 rows of 13, 37 and 29 values are not 16-byte multiples: the
+    # batched pass takes its one-value-per-lane path; every problem still
+    # reaches its OLS solution (the oracle's, on the same rounded data)
+    shapes = [(3000, 13), (7000, 37), (12000, 29)]
+    Xs, Ys, ps, refs = [], [], [], []
+    for k, (n, d) in enumerate(shapes):
+        p = make_problem("plain_small", n=n, d=d, seed=900 + k)
+        X32 = p.X.astype(np.float32)
+        Y32 = p.Y.astype(np.float32)
+        Xs.append(dev(X32))
+        Ys.append(dev(Y32))
+        ps.append(_params(G, n, d, 950 + k, s_max=40, precision="mixed"))
+        refs.append(O.ols_refined(X32.astype(np.float64), Y32.astype(np.float64))[0])
+    betas, infos = G.solve_batched(Xs, Ys, ps)
+    for b, shape in enumerate(shapes):
+        assert infos[b]["status"] == "SLSE_OK", shape
+        assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-10, shape
