@@ -112,16 +112,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 
 // Batched products of the factor jobs (blockIdx.z = job):
 //   which = 0: G = Ad^T Ad    which = 1: M = L L^T
-__global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJob* __restrict__ jobs,
-                                                                  int which) {
+// G = Ad^T Ad of every job (blockIdx.z = job)
+__global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJob* __restrict__ jobs) {
   const FactorJob jb = jobs[blockIdx.z];
   const int64_t d = jb.d;
   const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
   if (i0 >= d || j0 >= d) return;
-  if (which == 0)
-    gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, nullptr, 0, i0, j0, 0, jb.rows);
-  else
-    gemm_tile(d, d, 1.0, jb.L, d, 0, jb.L, d, 1, 0.0, jb.M, d, nullptr, 0, i0, j0, 0, d);
+  gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, nullptr, 0, i0, j0, 0, jb.rows);
 }
 
 // C = alpha * sum_s part[s] + beta * C (splits summed in order)
@@ -264,13 +261,6 @@ __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int d, const dou
   cholesky_block(d, G, ldg, R, ldr, info);
 }
 
-// one job per block
-__global__ __launch_bounds__(kCholThreads) void cholesky_batched_kernel(
-    const FactorJob* __restrict__ jobs) {
-  const FactorJob jb = jobs[blockIdx.x];
-  cholesky_block(jb.d, jb.G, jb.d, jb.R, jb.d, jb.info);
-}
-
 // Rinv = R^{-1} row by row: row i solves x^T R = e_i^T by forward
 // substitution over j with running sums s_l = -sum_{k<j} x_k R_kl, so each
 // step reads one row of R (contiguous).  Lane l keeps s for the columns
@@ -336,14 +326,6 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(int d, const double* __res
   tri_inv_rows(d, R, ldr, Rinv, ldi, blockIdx.x * 4);
 }
 
-// blockIdx.y = job; blocks past a job's rows exit
-__global__ __launch_bounds__(256) void tri_inv_batched_kernel(const FactorJob* __restrict__ jobs) {
-  const FactorJob jb = jobs[blockIdx.y];
-  const int i0 = blockIdx.x * 4;
-  if (i0 >= jb.d) return;
-  tri_inv_rows(jb.d, jb.R, jb.d, jb.L, jb.d, i0);
-}
-
 // Ad = scale * A[:, :d] of every job (blockIdx.y = job)
 __global__ void convert_scale_batched_kernel(const FactorJob* __restrict__ jobs, int is_f32) {
   const FactorJob jb = jobs[blockIdx.y];
@@ -394,9 +376,9 @@ __device__ __forceinline__ void gj_invert32(double (&col)[kGJ], int lane, bool* 
   }
 }
 
-__global__ __launch_bounds__(256) void gj_panel_kernel(int d, int k0, double* __restrict__ G,
-                                                       double* __restrict__ colp,
-                                                       int* __restrict__ info) {
+__device__ __forceinline__ void gj_panel(int d, int k0, double* __restrict__ G,
+                                         double* __restrict__ colp, int* __restrict__ info,
+                                         int bx) {
   __shared__ double Pinv[kGJ][kGJ + 1];
   __shared__ double Rp[kGJ][kGJChunk + 1];
   const int t = threadIdx.x;
@@ -415,19 +397,19 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(int d, int k0, double* __
 #pragma unroll
       for (int a = 0; a < kGJ; ++a) {
         Pinv[a][c] = col[a];
-        if (blockIdx.x == 0 && a < kw && c < kw) colp[(int64_t)(k0 + a) * kGJ + c] = col[a];
+        if (bx == 0 && a < kw && c < kw) colp[(int64_t)(k0 + a) * kGJ + c] = col[a];
       }
     }
     if (bad && t == 0) atomicCAS(info, 0, k0 + 1);
   }
   // 2. save the old column panel for rows [64 b, 64 b + 64) outside K
-  const int r0 = blockIdx.x * kGJChunk;
+  const int r0 = bx * kGJChunk;
   for (int e = t; e < kGJChunk * kGJ; e += 256) {
     const int i = r0 + e / kGJ, a = e % kGJ;
     if (i < d && (i < k0 || i >= k0 + kw) && a < kw) colp[(int64_t)i * kGJ + a] = G[(int64_t)i * d + k0 + a];
   }
   // 3. row panel of this block's columns [64 b, 64 b + 64)
-  const int c0 = blockIdx.x * kGJChunk;
+  const int c0 = bx * kGJChunk;
   for (int e = t; e < kGJ * kGJChunk; e += 256) {
     const int a = e / kGJChunk, j = c0 + e % kGJChunk;
     Rp[a][e % kGJChunk] = (a < kw && j < d) ? G[(int64_t)(k0 + a) * d + j] : 0.0;
@@ -443,13 +425,27 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(int d, int k0, double* __
   }
 }
 
-// one 32 x 32 output tile per block (blockIdx.y = row tile, blockIdx.x = column tile)
-__global__ __launch_bounds__(256) void gj_update_kernel(int d, int k0, double* __restrict__ G,
-                                                        const double* __restrict__ colp) {
+__global__ __launch_bounds__(256) void gj_panel_kernel(int d, int k0, double* __restrict__ G,
+                                                       double* __restrict__ colp,
+                                                       int* __restrict__ info) {
+  gj_panel(d, k0, G, colp, info, blockIdx.x);
+}
+
+// the panel step of every job (blockIdx.y), past the end of a smaller job: nothing
+__global__ __launch_bounds__(256) void gj_panel_batched_kernel(const FactorJob* __restrict__ jobs,
+                                                               int k0) {
+  const FactorJob jb = jobs[blockIdx.y];
+  if (k0 >= jb.d || (int)blockIdx.x * kGJChunk >= jb.d) return;
+  gj_panel(jb.d, k0, jb.M, jb.colp, jb.info, blockIdx.x);
+}
+
+// one 32 x 32 output tile per block (by = row tile, bx = column tile)
+__device__ __forceinline__ void gj_update(int d, int k0, double* __restrict__ G,
+                                          const double* __restrict__ colp, int bx, int by) {
   __shared__ double Cp[kGJ][kGJ + 1];  // colp rows of this tile
   __shared__ double Rw[kGJ][kGJ + 1];  // new row panel columns of this tile
   const int kw = min(kGJ, d - k0);
-  const int i0 = blockIdx.y * kGJ, j0 = blockIdx.x * kGJ;
+  const int i0 = by * kGJ, j0 = bx * kGJ;
   const int t = threadIdx.x;
   const bool pivcols = j0 == k0;
   if (i0 == k0) {  // the pivot rows were finished by the panel step, but for G[K, K]
@@ -482,6 +478,20 @@ __global__ __launch_bounds__(256) void gj_update_kernel(int d, int k0, double* _
     else
       G[(int64_t)i * d + j] -= v;
   }
+}
+
+__global__ __launch_bounds__(256) void gj_update_kernel(int d, int k0, double* __restrict__ G,
+                                                        const double* __restrict__ colp) {
+  gj_update(d, k0, G, colp, blockIdx.x, blockIdx.y);
+}
+
+// the update step of every job (blockIdx.z)
+__global__ __launch_bounds__(256) void gj_update_batched_kernel(const FactorJob* __restrict__ jobs,
+                                                                int k0) {
+  const FactorJob jb = jobs[blockIdx.z];
+  const int nt = (int)ceil_div(jb.d, kGJ);
+  if (k0 >= jb.d || (int)blockIdx.x >= nt || (int)blockIdx.y >= nt) return;
+  gj_update(jb.d, k0, jb.M, jb.colp, blockIdx.x, blockIdx.y);
 }
 
 // G += coef trace(G) I (one block): the diagonal shift of shifted CholeskyQR
@@ -573,14 +583,19 @@ void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_
   convert_scale_batched_kernel<<<dim3(cb, (unsigned)B), 256, 0, s>>>(jobs, at == SLSE_F32 ? 1 : 0);
   SLSE_LAUNCH_CHECK();
   const unsigned tiles = (unsigned)ceil_div(dmax, kTile);
-  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs, 0);
+  // the scaled Gram into M (G points at M), then M = G^{-1} in place by the
+  // blocked Gauss-Jordan steps of every job at once
+  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs);
   SLSE_LAUNCH_CHECK();
-  cholesky_batched_kernel<<<(unsigned)B, kCholThreads, 0, s>>>(jobs);
-  SLSE_LAUNCH_CHECK();
-  tri_inv_batched_kernel<<<dim3((unsigned)ceil_div(dmax, 4), (unsigned)B), 256, 0, s>>>(jobs);
-  SLSE_LAUNCH_CHECK();
-  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs, 1);
-  SLSE_LAUNCH_CHECK();
+  if (B > 65535) fail(SLSE_EUNSUPPORTED, "factor: too many batched jobs");
+  const unsigned nt = (unsigned)ceil_div(dmax, kGJ);
+  for (int k0 = 0; k0 < dmax; k0 += kGJ) {
+    gj_panel_batched_kernel<<<dim3((unsigned)ceil_div(dmax, kGJChunk), (unsigned)B), 256, 0, s>>>(jobs,
+                                                                                                k0);
+    SLSE_LAUNCH_CHECK();
+    gj_update_batched_kernel<<<dim3(nt, nt, (unsigned)B), 256, 0, s>>>(jobs, k0);
+    SLSE_LAUNCH_CHECK();
+  }
 }
 
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s) {

@@ -243,8 +243,10 @@ void launch_shift_diag(int d, double* G, double coef, hipStream_t s);
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s);
 
 // One Cholesky-route factorization of a batch: Ad = scale * A[:, :d] (FP64),
-// G = Ad^T Ad, R^T R = G, L = R^{-1}, M = L L^T.  Every buffer is the job's
-// own, row-major with leading dimension d (A: lda).
+// G = Ad^T Ad, then M = G^{-1} by the blocked Gauss-Jordan steps of the
+// single-problem route (info[0]: first non-positive pivot block + 1).  Every
+// buffer is the job's own, row-major with leading dimension d (A: lda); G may
+// be M (the Gram is then inverted in place).
 struct FactorJob {
   const void* A = nullptr;
   int64_t lda = 0;
@@ -253,9 +255,8 @@ struct FactorJob {
   double scale = 1.0;
   double* Ad = nullptr;
   double* G = nullptr;
-  double* R = nullptr;
-  double* L = nullptr;
   double* M = nullptr;
+  double* colp = nullptr;  // d x 32 Gauss-Jordan column panel
   int* info = nullptr;
 };
 // All jobs at once (jobs in device memory; dmax, rows_max bound every job).

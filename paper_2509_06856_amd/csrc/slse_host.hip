@@ -1286,18 +1286,17 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bp.rmax = max_r;
   bp.batched_factor = fm == SLSE_FACTOR_CHOL;
   if (bp.batched_factor) {
-    // each problem owns its Ad, G, R and L; M goes straight into the M pool
-    int64_t ad_n = 0, sq_n = 0;
+    // each problem owns its scaled sketch Ad and a Gauss-Jordan column panel;
+    // the Gram is formed in its M-pool slot and inverted there
+    int64_t ad_n = 0, cp_n = 0;
     for (int b = 0; b < B; ++b) {
       ad_n += bp.sk[b].r * ps[b].d;
-      sq_n += ps[b].d * ps[b].d;
+      cp_n += ps[b].d * 32;
     }
     double* adp = ctx->arena.get_t<double>("bfAd", (size_t)ad_n);
-    double* gp = ctx->arena.get_t<double>("bfG", (size_t)sq_n);
-    double* rp = ctx->arena.get_t<double>("bfR", (size_t)sq_n);
-    double* lp = ctx->arena.get_t<double>("bfL", (size_t)sq_n);
+    double* cpp = ctx->arena.get_t<double>("bfColp", (size_t)cp_n);
     bp.h_jobs.resize(B);
-    int64_t ao = 0, so = 0;
+    int64_t ao = 0, co = 0;
     for (int b = 0; b < B; ++b) {
       FactorJob& j = bp.h_jobs[b];
       const int64_t d = ps[b].d;
@@ -1307,13 +1306,12 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
       j.d = (int)d;
       j.scale = std::sqrt(bp.sk[b].hat_scale);
       j.Ad = adp + ao;
-      j.G = gp + so;
-      j.R = rp + so;
-      j.L = lp + so;
       j.M = bp.Mpool + bp.m_off[b];
+      j.G = j.M;
+      j.colp = cpp + co;
       j.info = bp.finfo + 3 * b;
       ao += j.rows * d;
-      so += d * d;
+      co += d * 32;
     }
     bp.d_jobs = ctx->arena.get_t<FactorJob>("bJobs", (size_t)B);
   } else {

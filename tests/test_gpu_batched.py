@@ -137,3 +137,18 @@ def test_batched_f32_odd_widths_reach_ols(G):
     for b, shape in enumerate(shapes):
         assert infos[b]["status"] == "SLSE_OK", shape
         assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-10, shape
+
+
+def test_batched_rank_deficient_problem_is_singular(G):
+    # a zero column makes one problem's Hessian sketch singular: its
+    # Gauss-Jordan pivot block is not positive, and the batch reports it
+    from paper_2509_06856_amd import _lib as L
+
+    p0 = make_problem("plain_small", n=4000, d=12, seed=31)
+    p1 = make_problem("plain_small", n=5000, d=40, seed=32)
+    X1 = p1.X.copy()
+    X1[:, 7] = 0.0
+    ps = [_params(G, 4000, 12, 61, s_max=5), _params(G, 5000, 40, 62, s_max=5)]
+    with pytest.raises(L.SlseError) as e:
+        G.solve_batched([dev(p0.X), dev(X1)], [dev(p0.Y), dev(p1.Y)], ps)
+    assert e.value.status == L.SLSE_ESINGULAR
