@@ -112,13 +112,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 
 // Batched products of the factor jobs (blockIdx.z = job):
 //   which = 0: G = Ad^T Ad    which = 1: M = L L^T
-// G = Ad^T Ad of every job (blockIdx.z = job)
-__global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJob* __restrict__ jobs) {
-  const FactorJob jb = jobs[blockIdx.z];
+// G = Ad^T Ad of every job (blockIdx.z = job x splits + split): with splits > 1
+// each split sums its share of the rows into the job's partial slot
+__global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJob* __restrict__ jobs,
+                                                                  int splits) {
+  const int z = blockIdx.z / splits, sp = blockIdx.z % splits;
+  const FactorJob jb = jobs[z];
   const int64_t d = jb.d;
   const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
   if (i0 >= d || j0 >= d) return;
-  gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, nullptr, 0, i0, j0, 0, jb.rows);
+  const int64_t kper = round_up(ceil_div(jb.rows, (int64_t)splits), kKStep);
+  const int64_t kb0 = sp * kper;
+  gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, splits > 1 ? jb.part : nullptr, sp,
+            i0, j0, kb0, min(jb.rows, kb0 + kper));
+}
+
+// G = sum of the job's split slots, in split order (blockIdx.y = job)
+__global__ void factor_reduce_batched_kernel(const FactorJob* __restrict__ jobs, int splits) {
+  const FactorJob jb = jobs[blockIdx.y];
+  const int64_t n = (int64_t)jb.d * jb.d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < splits; ++q) t += jb.part[(int64_t)q * n + e];
+    jb.G[e] = t;
+  }
 }
 
 // C = alpha * sum_s part[s] + beta * C (splits summed in order)
@@ -575,6 +593,10 @@ void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr
   SLSE_LAUNCH_CHECK();
 }
 
+int factor_batched_splits(int64_t rows_max) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, rows_max / 256));
+}
+
 void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_max,
                            slse_dtype at, hipStream_t s) {
   if (B <= 0) return;
@@ -585,9 +607,16 @@ void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_
   const unsigned tiles = (unsigned)ceil_div(dmax, kTile);
   // the scaled Gram into M (G points at M), then M = G^{-1} in place by the
   // blocked Gauss-Jordan steps of every job at once
-  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)B), 256, 0, s>>>(jobs);
-  SLSE_LAUNCH_CHECK();
   if (B > 65535) fail(SLSE_EUNSUPPORTED, "factor: too many batched jobs");
+  const int splits = factor_batched_splits(rows_max);
+  if ((int64_t)B * splits > 65535) fail(SLSE_EUNSUPPORTED, "factor: too many batched jobs");
+  factor_gemm_batched_kernel<<<dim3(tiles, tiles, (unsigned)(B * splits)), 256, 0, s>>>(jobs, splits);
+  SLSE_LAUNCH_CHECK();
+  if (splits > 1) {
+    const unsigned rb = (unsigned)std::min<int64_t>(ceil_div((int64_t)dmax * dmax, 256), 256);
+    factor_reduce_batched_kernel<<<dim3(rb, (unsigned)B), 256, 0, s>>>(jobs, splits);
+    SLSE_LAUNCH_CHECK();
+  }
   const unsigned nt = (unsigned)ceil_div(dmax, kGJ);
   for (int k0 = 0; k0 < dmax; k0 += kGJ) {
     gj_panel_batched_kernel<<<dim3((unsigned)ceil_div(dmax, kGJChunk), (unsigned)B), 256, 0, s>>>(jobs,

@@ -257,8 +257,11 @@ struct FactorJob {
   double* G = nullptr;
   double* M = nullptr;
   double* colp = nullptr;  // d x 32 Gauss-Jordan column panel
+  double* part = nullptr;  // splits x d x d partial Grams (factor_batched_splits > 1)
   int* info = nullptr;
 };
+// row splits of the batched Gram for sketches of at most rows_max rows
+int factor_batched_splits(int64_t rows_max);
 // All jobs at once (jobs in device memory; dmax, rows_max bound every job).
 void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_max,
                            slse_dtype at, hipStream_t s);

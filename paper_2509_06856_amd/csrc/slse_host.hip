@@ -1288,15 +1288,18 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   if (bp.batched_factor) {
     // each problem owns its scaled sketch Ad and a Gauss-Jordan column panel;
     // the Gram is formed in its M-pool slot and inverted there
-    int64_t ad_n = 0, cp_n = 0;
+    const int splits = factor_batched_splits(max_r);
+    int64_t ad_n = 0, cp_n = 0, sq_n = 0;
     for (int b = 0; b < B; ++b) {
       ad_n += bp.sk[b].r * ps[b].d;
       cp_n += ps[b].d * 32;
+      sq_n += ps[b].d * ps[b].d;
     }
     double* adp = ctx->arena.get_t<double>("bfAd", (size_t)ad_n);
     double* cpp = ctx->arena.get_t<double>("bfColp", (size_t)cp_n);
+    double* pp = splits > 1 ? ctx->arena.get_t<double>("bfPart", (size_t)(splits * sq_n)) : nullptr;
     bp.h_jobs.resize(B);
-    int64_t ao = 0, co = 0;
+    int64_t ao = 0, co = 0, so = 0;
     for (int b = 0; b < B; ++b) {
       FactorJob& j = bp.h_jobs[b];
       const int64_t d = ps[b].d;
@@ -1309,9 +1312,11 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
       j.M = bp.Mpool + bp.m_off[b];
       j.G = j.M;
       j.colp = cpp + co;
+      j.part = pp ? pp + splits * so : nullptr;
       j.info = bp.finfo + 3 * b;
       ao += j.rows * d;
       co += d * 32;
+      so += d * d;
     }
     bp.d_jobs = ctx->arena.get_t<FactorJob>("bJobs", (size_t)B);
   } else {
