@@ -186,13 +186,15 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
   }
 }
 
-// One block per problem: g = scale * sum_tiles partial, p = M g,
-// beta' = beta + mu p + eta (beta - beta_prev).  The tile sum is split over
-// (column, tile residue class) pairs and the classes are combined in a fixed
-// order, so the result does not depend on timing; the GEMV runs four rows per
-// wave at once so that their loads overlap.
+// Blocks (problem, 64-row block): g = scale * sum_tiles partial (every block of
+// a problem forms all of g), p = M g for the block's rows,
+// beta' = beta + mu p + eta (beta - beta_prev) on those rows.  The tile sum is
+// split over (column, tile residue class) pairs and the classes are combined
+// in a fixed order, so the result does not depend on timing; the GEMV runs
+// four rows per wave at once so that their loads overlap.
 constexpr int kUpdThreads = 1024;
 constexpr int kUpdWaves = kUpdThreads / 64;
+constexpr int kUpdRows = 4 * kUpdWaves;  // rows of p = M g per block (blockIdx.y)
 
 __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
     const BatchStep* __restrict__ steps, const BatchProblem* __restrict__ probs,
@@ -204,6 +206,9 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
   if (st.n <= 0) return;  // this problem has finished its schedule
   const BatchProblem pr = probs[b];
   const int d = pr.d;
+  const int row_lo = blockIdx.y * kUpdRows;  // this block's rows of p and beta
+  if (row_lo >= d) return;
+  const int row_hi = min(d, row_lo + kUpdRows);
   const int ntiles = st.ntiles;
   const double* part = pool + pr.part_off;
   // classes of tiles per column: nq = 1024 / d rounded down to a power of 2
@@ -236,18 +241,18 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   bool bad = false;
-  for (int i0 = 4 * wave; i0 < d; i0 += 4 * kUpdWaves) {
+  for (int i0 = row_lo + 4 * wave; i0 < row_hi; i0 += 4 * kUpdWaves) {
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = lane; k < d; k += 64) {
       const double gk = s_g[k];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (i0 + u < d) p[u] = fma(pr.M[(int64_t)(i0 + u) * d + k], gk, p[u]);
+        if (i0 + u < row_hi) p[u] = fma(pr.M[(int64_t)(i0 + u) * d + k], gk, p[u]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       for (int m = 32; m > 0; m >>= 1) p[u] += wave_xor(p[u], m);
-    if (lane < 4 && i0 + lane < d) {
+    if (lane < 4 && i0 + lane < row_hi) {
       const int i = i0 + lane;
       const double pi = lane == 0 ? p[0] : lane == 1 ? p[1] : lane == 2 ? p[2] : p[3];
       const double bi = st.beta[i];
@@ -315,10 +320,11 @@ void launch_batched_init(const BatchProblem* probs, int B, int dmax, hipStream_t
   SLSE_LAUNCH_CHECK();
 }
 
-void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
+void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B, int dmax,
                            const double* pool, int* flags, hipStream_t s) {
-  if (B <= 0) return;
-  batched_update_kernel<<<B, kUpdThreads, 0, s>>>(steps, probs, pool, flags);
+  if (B <= 0 || dmax <= 0) return;
+  const dim3 grid((unsigned)B, (unsigned)ceil_div(dmax, kUpdRows));
+  batched_update_kernel<<<grid, kUpdThreads, 0, s>>>(steps, probs, pool, flags);
   SLSE_LAUNCH_CHECK();
 }
 

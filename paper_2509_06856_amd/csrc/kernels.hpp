@@ -314,7 +314,7 @@ struct BatchProblem {
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
                                int B, int total_tiles, int grid, double* pool, slse_dtype t, bool vec,
                                int nch, hipStream_t s);
-void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B,
+void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B, int dmax,
                            const double* pool, int* flags, hipStream_t s);
 // beta_init = beta_out = beta0 (or 0) for every problem
 void launch_batched_init(const BatchProblem* probs, int B, int dmax, hipStream_t s);

@@ -1046,7 +1046,8 @@ void enqueue_batch_steps(const BatchPlan& bp, hipStream_t st) {
     launch_batched_resid_grad(bp.d_steps + (size_t)t * bp.B, bp.d_probs,
                               bp.d_prefix + (size_t)t * (bp.B + 1), bp.B, bp.h_total[t], bp.grid,
                               bp.part, bp.t, bp.vec, bp.nch, st);
-    launch_batched_update(bp.d_steps + (size_t)t * bp.B, bp.d_probs, bp.B, bp.part, bp.flags, st);
+    launch_batched_update(bp.d_steps + (size_t)t * bp.B, bp.d_probs, bp.B, bp.dmax, bp.part,
+                          bp.flags, st);
   }
 }
 
