@@ -262,17 +262,54 @@ __device__ __forceinline__ int64_t last_pass_index(int64_t j, int s0, int B) {
 
 // pi_sgn[j] = pi(j) (or ~pi(j) when D_j = -1), in row order (the first pass reads it
 // contiguously); slotA = sigma^{-1}(j) if < m_K else -1, in the last pass's order
+// The permutation of [0, 2^p) (INV: its inverse) of every index j = j0,
+// j0 + stride, .. < n, handed to emit(j, value).  Cycle walking (an odd p
+// walks twice on average) would hold a wave for its longest walk; here every
+// iteration evaluates the Feistel network once per lane, on the lane's next
+// index as soon as its current one has left the walking range.  The values
+// are those of rng::prp / rng::prp_inv.
+template <bool INV, typename Emit>
+__device__ __forceinline__ void prp_each(int64_t j0, int64_t n, int64_t stride, uint64_t seed,
+                                         uint64_t stream, int p, Emit&& emit) {
+  if (j0 >= n) return;
+  const int h = (p + 1) >> 1;
+  const uint64_t lim = uint64_t(1) << p;
+  int64_t j = j0;
+  uint64_t x = (uint64_t)j;
+  while (true) {
+    const uint64_t y =
+        INV ? rng::feistel_dec(x, seed, stream, h) : rng::feistel_enc(x, seed, stream, h);
+    if (y < lim) {
+      emit(j, y);
+      j += stride;
+      if (j >= n) break;
+      x = (uint64_t)j;
+    } else {
+      x = y;
+    }
+  }
+}
+
+// pi_sgn and slotA of the indices j0, j0 + stride, .. < npad
+__device__ __forceinline__ void srht_index_range(int64_t j0, int64_t stride, int64_t npad, int p,
+                                                 uint64_t seed, int64_t mK, int s0_last, int b_last,
+                                                 int32_t* __restrict__ pi_sgn,
+                                                 int32_t* __restrict__ slotA) {
+  prp_each<false>(j0, npad, stride, seed, rng::kStreamP, p,
+                  [&](int64_t j, uint64_t src) { pi_sgn[j] = (int32_t)src; });
+  // the signs D over the same indices (each thread rereads its own writes)
+  for (int64_t j = j0; j < npad; j += stride)
+    if (rng::rademacher(seed, (uint64_t)j) < 0) pi_sgn[j] = ~pi_sgn[j];
+  prp_each<true>(j0, npad, stride, seed, rng::kStreamS, p, [&](int64_t j, uint64_t t) {
+    slotA[last_pass_index(j, s0_last, b_last)] = t < (uint64_t)mK ? (int32_t)t : -1;
+  });
+}
+
 __global__ void srht_index_kernel(int64_t npad, int p, uint64_t seed, int64_t mK, int s0_last,
                                   int b_last, int32_t* __restrict__ pi_sgn,
                                   int32_t* __restrict__ slotA) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npad;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t src = rng::prp((uint64_t)j, seed, rng::kStreamP, p);
-    const int D = rng::rademacher(seed, (uint64_t)j);
-    pi_sgn[j] = D > 0 ? (int32_t)src : ~(int32_t)src;
-    const uint64_t t = rng::prp_inv((uint64_t)j, seed, rng::kStreamS, p);
-    slotA[last_pass_index(j, s0_last, b_last)] = t < (uint64_t)mK ? (int32_t)t : -1;
-  }
+  srht_index_range(blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x,
+                   npad, p, seed, mK, s0_last, b_last, pi_sgn, slotA);
 }
 
 // slotH (pre-filled with -1): the row sigma_hat(t) carries slot t, for t < r
@@ -557,15 +594,11 @@ namespace {
 // Every row index: pi_sgn, slotA (as srht_index_kernel) and slotH = -1.
 __global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs) {
   const SrhtIndexJob jb = jobs[blockIdx.y];
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < jb.npad;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t src = rng::prp((uint64_t)j, jb.seed, rng::kStreamP, jb.p);
-    const int D = rng::rademacher(jb.seed, (uint64_t)j);
-    jb.pi_sgn[j] = D > 0 ? (int32_t)src : ~(int32_t)src;
-    const uint64_t t = rng::prp_inv((uint64_t)j, jb.seed, rng::kStreamS, jb.p);
-    jb.slotA[last_pass_index(j, jb.s0_last, jb.b_last)] = t < (uint64_t)jb.mK ? (int32_t)t : -1;
-    jb.slotH[j] = -1;
-  }
+  const int64_t j0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  srht_index_range(j0, stride, jb.npad, jb.p, jb.seed, jb.mK, jb.s0_last, jb.b_last, jb.pi_sgn,
+                   jb.slotA);
+  for (int64_t j = j0; j < jb.npad; j += stride) jb.slotH[j] = -1;
 }
 
 // every Hessian sample of every job (after the kernel above)
