@@ -1,17 +1,18 @@
 // Batched M-IHS steps for many independent regressions of uneven size (one
 // launch per step for the whole batch instead of one per problem).
 //
-// Residual gradient: the rows of every active problem are cut into tiles (the
-// tile height is chosen per step, smaller when few rows are active, so the
-// grid stays busy); one flat list of (problem, tile) work items is walked by a
-// persistent grid.  A block takes a tile, streams its rows with the problem's
-// own lane-group width (as in the single-problem pass: a row split over
-// `lpr` lanes, many rows in flight), reduces the tile's partial gradient in
-// LDS and writes it to the problem's partial rows.  Tiles never share a
+// Residual gradient: the bytes of [X|Y] a step reads are cut into tiles of
+// about equal size (grid x items tiles, shared out over the active problems;
+// a problem's rows split evenly over its tiles); one flat list of (problem,
+// tile) work items is walked by a persistent grid.  A block takes a tile and
+// streams its rows with the problem's own lane groups (a row split over `lpr`
+// lanes, one to four 16-byte vectors per lane, several rows in flight),
+// reduces the tile's partial gradient in LDS and writes it to the tile's own
 // partial row, so the result does not depend on which block ran which tile.
 //
-// Update: one block per problem sums its tile partials in tile order, applies
-// M = H_hat^{-1} (GEMV) and takes the heavy-ball step of eqs. (98)/(99).
+// Update: blocks per (problem, 64 rows) sum the problem's tile partials in a
+// fixed order, apply M = H_hat^{-1} (GEMV) and take the heavy-ball step of
+// eqs. (98)/(99).
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -19,12 +20,32 @@
 namespace slse {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kBatchThreads;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxD = 1024;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// [X|Y] rows live in global memory: loads through global (address space 1)
+// pointers, not flat ones (the descriptors holding the pointers come from
+// memory, so the compiler cannot infer it)
+#define SLSE_GLOBAL __attribute__((address_space(1)))
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec_g(const T* p, T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    v[0] = __builtin_nontemporal_load((const SLSE_GLOBAL T*)p);
+  } else if constexpr (sizeof(T) == 4) {
+    f32x4 x = __builtin_nontemporal_load((const SLSE_GLOBAL f32x4*)p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = x[i];
+  } else {
+    f64x2 x = __builtin_nontemporal_load((const SLSE_GLOBAL f64x2*)p);
+    v[0] = x[0];
+    v[1] = x[1];
+  }
+}
 
 template <typename T, int VEC>
 __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
@@ -56,6 +77,7 @@ __device__ __forceinline__ double widen_f64(T x) {
 }
 
 constexpr int kPrefixLds = 512;  // problems whose tile prefix is searched in LDS
+constexpr int kSlots = kBatchSlots;
 
 __device__ __forceinline__ int find_problem(const int* __restrict__ prefix, int B, int tile) {
   int lo = 0, hi = B;  // prefix[lo] <= tile < prefix[hi]
@@ -69,17 +91,168 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ prefix, int 
   return lo;
 }
 
-template <typename T, int VEC, int NCH>
+// Rows of one tile: lane group `grp` of `lpr` lanes covers a row with CH
+// vectors per lane (vector k*lpr + l), so every load instruction of a wave
+// reads gpw consecutive rows as one contiguous range; a lane keeps kSlots
+// vectors in flight, i.e. kSlots / CH rows.  The tile's partial gradient is
+// reduced over the lane groups, then over the waves in LDS, and written to
+// the tile's own partial row.
+
+// RU rows per lane group: the dots (row by row, so that the widened values
+// of a row die with its dot), the lane-group sums of all RU dots interleaved,
+// then the residuals and the gradient update
+template <typename T, int VEC, int CH, int RU>
+__device__ __forceinline__ void rows_update(const T (&x)[RU][CH][VEC], const T (&y)[RU],
+                                            const double (&bv)[CH][VEC], int lpr,
+                                            double (&acc)[CH][VEC], double& rr) {
+  double dot[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    __builtin_amdgcn_sched_barrier(0);
+    double p = 0.0;
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) p = fma((double)x[u][k][v], bv[k][v], p);
+    dot[u] = p;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  for (int m = lpr >> 1; m > 0; m >>= 1) {
+    double o[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) o[u] = wave_xor(dot[u], m);
+#pragma unroll
+    for (int u = 0; u < RU; ++u) dot[u] += o[u];
+  }
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const double r = (double)y[u] - dot[u];
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[k][v] = fma(r, widen_f64(x[u][k][v]), acc[k][v]);
+    rr = fma(r, r, rr);
+  }
+}
+
+template <typename T, int VEC, int CH>
+__device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr, int lt,
+                                             double* __restrict__ prow,
+                                             double (*s_red)[kMaxD + 1]) {
+  constexpr int RU = kSlots / CH;         // rows per lane group in flight
+  constexpr int RG = RU < 2 ? RU : 2;     // the same in the guarded loop
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gpw = 64 / lpr;
+  const int grp = lane / lpr;
+  const int l = lane - grp * lpr;
+  const T* X = static_cast<const T*>(st.X);
+  const T* Y = static_cast<const T*>(st.Y);
+  const double* beta = st.beta;
+  double bv[CH][VEC];
+  bool full[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int col0 = (k * lpr + l) * VEC;
+    full[k] = col0 + VEC <= d;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) bv[k][v] = (col0 + v < d) ? beta[col0 + v] : 0.0;
+  }
+  double acc[CH][VEC];
+#pragma unroll
+  for (int k = 0; k < CH; ++k)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+  double rr = 0.0;
+  const int64_t r0 = (int64_t)lt * st.tile_rows;
+  const int64_t r1 = min(st.n, r0 + st.tile_rows);
+  const int rs = kWaves * gpw;
+  int64_t base = r0 + wave * gpw + grp;
+  if (lpr * CH * VEC == d) {
+    // every lane's vectors lie inside the row: while all RU rows of every
+    // lane group of the wave are in range (a wave-uniform test), no guards
+    // (row pointers advance by uniform strides: no per-row 64-bit products)
+    const int64_t last = (int64_t)(gpw - 1) + (int64_t)(RU - 1) * rs;
+    const int64_t xs = (int64_t)rs * st.ldx;   // between a group's rows in flight
+    const int64_t ys = (int64_t)rs * st.incy;
+    int64_t wb = r0 + wave * gpw;
+    const T* xp = X + (wb + grp) * st.ldx + l * VEC;
+    const T* yp = Y + (wb + grp) * st.incy;
+    for (; wb + last < r1; wb += (int64_t)rs * RU, xp += RU * xs, yp += RU * ys) {
+      T x[RU][CH][VEC];
+      T y[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) load_vec_g<T, VEC>(xp + u * xs + k * lpr * VEC, x[u][k]);
+        y[u] = __builtin_nontemporal_load((const SLSE_GLOBAL T*)(yp + u * ys));
+      }
+      rows_update<T, VEC, CH, RU>(x, y, bv, lpr, acc, rr);
+    }
+    base = wb + grp;
+  }
+  // guarded rows: the rest of the tile, or all of it when a lane's vectors
+  // may pass the end of the row
+  for (; base < r1; base += (int64_t)rs * RG) {
+    T x[RG][CH][VEC];
+    T y[RG];
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+      const int64_t row = base + (int64_t)u * rs;
+      const bool ok = row < r1;
+      const T* xr = X + (ok ? row : r0) * st.ldx;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int col0 = (k * lpr + l) * VEC;
+        if (ok && full[k]) {
+          load_vec<T, VEC>(xr + col0, x[u][k]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) x[u][k][v] = (ok && col0 + v < d) ? xr[col0 + v] : (T)0;
+        }
+      }
+      y[u] = ok ? Y[(ok ? row : r0) * st.incy] : (T)0;
+    }
+    rows_update<T, VEC, CH, RG>(x, y, bv, lpr, acc, rr);
+  }
+#pragma unroll
+  for (int k = 0; k < CH; ++k)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      double t = acc[k][v];
+      for (int m = lpr; m < 64; m <<= 1) t += wave_xor(t, m);
+      acc[k][v] = t;
+    }
+  rr = (l == 0) ? rr : 0.0;
+  for (int m = 1; m < 64; m <<= 1) rr += wave_xor(rr, m);
+  __syncthreads();  // s_red of the previous tile is consumed
+  if (grp == 0) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int col = (k * lpr + l) * VEC + v;
+        if (col < d) s_red[wave][col] = acc[k][v];
+      }
+    if (l == 0) s_red[wave][d] = rr;
+  }
+  __syncthreads();
+  for (int col = threadIdx.x; col <= d; col += kThreads) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += s_red[w][col];
+    prow[col] = t;
+  }
+}
+
+// Persistent grid over the step's (problem, tile) items; CHMAX is the most
+// vectors per lane of any problem's row in the batch.
+template <typename T, int VEC, int CHMAX>
 __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
     const BatchStep* __restrict__ steps, const BatchProblem* __restrict__ probs,
     const int* __restrict__ prefix, int B, int total_tiles, double* __restrict__ pool) {
-  // rows in flight per lane group: two with four chunks per lane (fewer
-  // registers, measured faster than four), else four
-  constexpr int UNROLL = NCH >= 4 ? 2 : 4;
   __shared__ double s_red[kWaves][kMaxD + 1];
   __shared__ int s_prefix[kPrefixLds + 1];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   // the tile prefix of this step, searched in LDS (global if the batch is large)
   const bool lds_prefix = B <= kPrefixLds;
   if (lds_prefix) {
@@ -88,101 +261,19 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
   }
   const int* pfx = lds_prefix ? s_prefix : prefix;
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    const int b = find_problem(pfx, B, tile);
+    // the problem and tile are block-uniform: in scalar registers, the step
+    // and problem descriptors come in through scalar loads
+    const int b = __builtin_amdgcn_readfirstlane(find_problem(pfx, B, tile));
     const BatchStep st = steps[b];
     const BatchProblem pr = probs[b];
-    const int lt = tile - pfx[b];
-    const int d = pr.d;
-    const int lpr = pr.lpr;
-    const int gpw = 64 / lpr;
-    const int grp = lane / lpr;
-    const int l = lane - grp * lpr;
-    const T* X = static_cast<const T*>(st.X);
-    const T* Y = static_cast<const T*>(st.Y);
-    const double* beta = st.beta;
-    double bv[NCH][VEC];
-    bool full[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int col0 = (c * lpr + l) * VEC;
-      full[c] = col0 + VEC <= d;
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) bv[c][v] = (col0 + v < d) ? beta[col0 + v] : 0.0;
-    }
-    double acc[NCH][VEC];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) acc[c][v] = 0.0;
-    double rr = 0.0;
-    const int64_t r0 = (int64_t)lt * st.tile_rows;
-    const int64_t r1 = min(st.n, r0 + st.tile_rows);
-    const int rs = kWaves * gpw;
-    for (int64_t base = r0 + wave * gpw + grp; base < r1; base += (int64_t)rs * UNROLL) {
-      T x[UNROLL][NCH][VEC];
-      T y[UNROLL];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const int64_t row = base + (int64_t)u * rs;
-        const bool ok = row < r1;
-        const T* xr = X + (ok ? row : r0) * st.ldx;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const int col0 = (c * lpr + l) * VEC;
-          if (ok && full[c]) {
-            load_vec<T, VEC>(xr + col0, x[u][c]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) x[u][c][v] = (ok && col0 + v < d) ? xr[col0 + v] : (T)0;
-          }
-        }
-        y[u] = ok ? Y[(ok ? row : r0) * st.incy] : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        double dot = 0.0;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) dot = fma((double)x[u][c][v], bv[c][v], dot);
-        dot = lane_group_sum(dot, lpr);
-        const double r = (double)y[u] - dot;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[c][v] = fma(r, widen_f64(x[u][c][v]), acc[c][v]);
-        rr = fma(r, r, rr);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        double t = acc[c][v];
-        for (int m = lpr; m < 64; m <<= 1) t += wave_xor(t, m);
-        acc[c][v] = t;
-      }
-    rr = (l == 0) ? rr : 0.0;
-    for (int m = 1; m < 64; m <<= 1) rr += wave_xor(rr, m);
-    __syncthreads();  // s_red of the previous tile is consumed
-    if (grp == 0) {
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int col = (c * lpr + l) * VEC + v;
-          if (col < d) s_red[wave][col] = acc[c][v];
-        }
-      if (l == 0) s_red[wave][d] = rr;
-    }
-    __syncthreads();
-    double* prow = pool + pr.part_off + (int64_t)lt * (d + 1);
-    for (int col = threadIdx.x; col <= d; col += kThreads) {
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) t += s_red[w][col];
-      prow[col] = t;
-    }
+    const int lt = __builtin_amdgcn_readfirstlane(tile - pfx[b]);
+    double* prow = pool + pr.part_off + (int64_t)lt * (pr.d + 1);
+    if (CHMAX >= 4 && pr.ch == 4)
+      batched_tile<T, VEC, (CHMAX >= 4 ? 4 : 1)>(st, pr.d, pr.lpr, lt, prow, s_red);
+    else if (CHMAX >= 2 && pr.ch == 2)
+      batched_tile<T, VEC, (CHMAX >= 2 ? 2 : 1)>(st, pr.d, pr.lpr, lt, prow, s_red);
+    else
+      batched_tile<T, VEC, 1>(st, pr.d, pr.lpr, lt, prow, s_red);
   }
 }
 
@@ -276,8 +367,8 @@ __global__ void batched_init_kernel(const BatchProblem* __restrict__ probs) {
 
 template <typename T, int VEC>
 void launch_rg(const BatchStep* steps, const BatchProblem* probs, const int* prefix, int B,
-               int total, int grid, double* pool, int nch, hipStream_t s) {
-  switch (nch) {
+               int total, int grid, double* pool, int chmax, hipStream_t s) {
+  switch (chmax) {
     case 1:
       batched_resid_grad_kernel<T, VEC, 1><<<grid, kThreads, 0, s>>>(steps, probs, prefix, B, total,
                                                                       pool);
@@ -297,19 +388,19 @@ void launch_rg(const BatchStep* steps, const BatchProblem* probs, const int* pre
 
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
                                int B, int total_tiles, int grid, double* pool,
-                               slse_dtype t, bool vec, int nch, hipStream_t s) {
+                               slse_dtype t, bool vec, int chmax, hipStream_t s) {
   if (total_tiles <= 0) return;
   grid = std::max(1, std::min(grid, total_tiles));
   if (t == SLSE_F32) {
     if (vec)
-      launch_rg<float, 4>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
+      launch_rg<float, 4>(steps, probs, prefix, B, total_tiles, grid, pool, chmax, s);
     else
-      launch_rg<float, 1>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
+      launch_rg<float, 1>(steps, probs, prefix, B, total_tiles, grid, pool, chmax, s);
   } else {
     if (vec)
-      launch_rg<double, 2>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
+      launch_rg<double, 2>(steps, probs, prefix, B, total_tiles, grid, pool, chmax, s);
     else
-      launch_rg<double, 1>(steps, probs, prefix, B, total_tiles, grid, pool, nch, s);
+      launch_rg<double, 1>(steps, probs, prefix, B, total_tiles, grid, pool, chmax, s);
   }
   SLSE_LAUNCH_CHECK();
 }

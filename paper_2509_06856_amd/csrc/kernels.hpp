@@ -288,6 +288,11 @@ void launch_adjoint(const AdjointArgs& a, hipStream_t s);
 // --------------------------------------------------------------------------
 // Batched M-IHS steps (many problems per launch).
 // --------------------------------------------------------------------------
+// batched residual-gradient pass: threads per block, and 16-byte vectors of
+// [X|Y] a lane has in flight (a lane group's rows per step of its main loop
+// are kBatchSlots / ch)
+constexpr int kBatchThreads = 256;
+constexpr int kBatchSlots = 8;
 struct BatchStep {  // one problem at one global step
   const void* X;
   int64_t ldx;
@@ -303,7 +308,8 @@ struct BatchStep {  // one problem at one global step
 };
 struct BatchProblem {
   int d;
-  int lpr;
+  int lpr;  // lanes per row (a power of 2 <= 64)
+  int ch;   // 16-byte vectors per lane per row (1, 2 or 4)
   int64_t part_off;  // first partial row of this problem in the pool
   const double* M;
   double* beta_out;
@@ -313,7 +319,7 @@ struct BatchProblem {
 };
 void launch_batched_resid_grad(const BatchStep* steps, const BatchProblem* probs, const int* prefix,
                                int B, int total_tiles, int grid, double* pool, slse_dtype t, bool vec,
-                               int nch, hipStream_t s);
+                               int chmax, hipStream_t s);
 void launch_batched_update(const BatchStep* steps, const BatchProblem* probs, int B, int dmax,
                            const double* pool, int* flags, hipStream_t s);
 // beta_init = beta_out = beta0 (or 0) for every problem

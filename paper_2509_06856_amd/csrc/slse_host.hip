@@ -878,10 +878,10 @@ struct BatchPlan {
   int B = 0;
   slse_dtype t = SLSE_F32;
   std::vector<SketchShape> sk;
-  std::vector<int64_t> lda, a_off, ah_off, m_off, beta_off, part_off, max_tiles;
+  std::vector<int64_t> lda, a_off, ah_off, m_off, beta_off, part_off;
   std::vector<int> steps_of;  // total steps of each problem
   int T = 0;                  // global steps (max over problems)
-  int64_t tile_bytes = int64_t(1) << 20;  // X bytes per tile of a full step
+  int items = 1;  // work items per block of a full step (tiles = grid x items)
   int grid = 512;
   int cus = 256;  // compute units of the device
   bool vec = true;
@@ -899,6 +899,7 @@ struct BatchPlan {
   std::vector<BatchStep> h_steps;
   std::vector<int> h_prefix;
   std::vector<int> h_total;
+  std::vector<double> h_bytes;  // bytes of [X|Y] each step reads
   std::vector<BatchProblem> h_probs;
   SrhtArgs srht;
   GaussianArgs ga, gh;
@@ -924,13 +925,12 @@ struct BatchPlan {
   std::vector<FactorJob> h_jobs;
 };
 
-constexpr int kBatchTileFloor = 256;      // no batched tile is shorter (partial pool size)
-constexpr int kBatchTileCeil = 1 << 20;   // nor longer
-constexpr int64_t kBatchMinTileBytes = int64_t(256) << 10;  // smallest tile size chosen by default
-constexpr int kBatchChunks = 4;  // most row vectors a lane holds in a batched step
+constexpr int kBatchTileFloor = 256;  // tiles per problem <= ceil(rows / 256) (partial pool size)
+constexpr int kBatchTileCeil = 1 << 20;  // and >= ceil(rows / 2^20)
+constexpr int64_t kBatchMinTileBytes = int64_t(128) << 10;  // smallest tile a step is cut into
 constexpr size_t kBatchSrhtZMax = size_t(16) << 30;  // workspace cap for shared SRHT launches
 
-// smallest tile size (bytes of [X|Y]) a batched step may use
+// smallest tile (bytes of [X|Y]) a batched step is cut into
 // (SLSE_BATCH_MIN_TILE_KB overrides)
 int64_t batch_min_tile_bytes() {
   static const int64_t v = [] {
@@ -942,25 +942,23 @@ int64_t batch_min_tile_bytes() {
   return v;
 }
 
-// rows of a tile holding about `bytes` of [X|Y] rows of `row_bytes` each
-// (a power of 2 between the floor and the ceiling)
-int batch_tile_rows(int64_t bytes, int64_t row_bytes) {
-  int64_t rows = kBatchTileFloor;
-  while (rows * 2 <= kBatchTileCeil && rows * 2 * row_bytes <= bytes) rows *= 2;
-  return (int)rows;
-}
-
+// lanes per row of the batched pass: one 16-byte vector of the row (an
+// element when rows are not 16-byte aligned) per lane up to 16 lanes, more
+// vectors per lane beyond that (at most 4, so up to 64 lanes); 16 lanes, i.e.
+// 256 contiguous bytes of a row per load instruction and four xor steps per
+// row dot, measured fastest (SLSE_BATCH_LPR_MAX overrides the 16)
 int batch_lpr(int d, bool vec, slse_dtype t) {
+  static const int cap = [] {
+    int c = 16;
+    if (const char* e = std::getenv("SLSE_BATCH_LPR_MAX")) c = std::atoi(e);
+    return (c == 4 || c == 8 || c == 16 || c == 32 || c == 64) ? c : 16;
+  }();
   const int v = vec ? 16 / (int)dtype_size(t) : 1;
   const int nvec = (int)ceil_div(d, v);
-  // at most kBatchChunks vectors per lane (SLSE_BATCH_CHUNKS overrides)
-  static const int chunks = [] {
-    int c = kBatchChunks;
-    if (const char* e = std::getenv("SLSE_BATCH_CHUNKS")) c = std::atoi(e);
-    return (c == 1 || c == 2 || c == 4) ? c : kBatchChunks;
-  }();
-  int lpr = 1;
-  while (lpr < 64 && lpr * chunks < nvec) lpr *= 2;
+  int p2 = 1;
+  while (p2 < nvec) p2 *= 2;
+  int lpr = std::min(p2, cap);
+  while (lpr < 64 && lpr * 4 < p2) lpr *= 2;
   return lpr;
 }
 
@@ -971,7 +969,7 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
   bp.h_steps.assign((size_t)bp.T * B, BatchStep{});
   bp.h_prefix.assign((size_t)bp.T * (B + 1), 0);
   bp.h_total.assign(bp.T, 0);
-  bp.max_tiles.assign(B, 0);
+  bp.h_bytes.assign(bp.T, 0.0);
   for (int b = 0; b < B; ++b) {
     const SketchShape& sk = bp.sk[b];
     const int d = (int)ps[b].d;
@@ -1006,28 +1004,65 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
     for (int j = 0; j < qs[b].s_max; ++j) add(ps[b].X, ps[b].ldx, ps[b].Y, 1, ps[b].N, 1.0);
     (void)betas;
   }
-  // Tile heights per (step, problem): about the same bytes of [X|Y] per tile
-  // whatever the problem's width, so the grid's strided walk over the tiles
-  // gives every block about the same work.  The tuned size holds while a step
-  // has plenty of rows; when only a few (small) problems are still running,
-  // smaller tiles (down to batch_min_tile_bytes()) keep two tiles per CU.
+  // Tiles per (step, problem): a step's bytes of [X|Y] are cut into about
+  // grid x items tiles of equal size (no smaller than batch_min_tile_bytes()),
+  // shared out over the problems by largest remainder, so the grid's strided
+  // walk gives every block about the same bytes; a problem's rows are split
+  // evenly over its tiles.
   const int64_t es = (int64_t)dtype_size(bp.t);
+  const int64_t slots = (int64_t)bp.grid * bp.items;
+  std::vector<double> frac(B);
+  std::vector<int> order(B);
   for (int t = 0; t < bp.T; ++t) {
-    auto tiles_at = [&](int64_t bytes) {
-      int64_t n = 0;
-      for (int b = 0; b < B; ++b) {
-        const BatchStep& st = bp.h_steps[(size_t)t * B + b];
-        n += ceil_div(st.n, (int64_t)batch_tile_rows(bytes, (ps[b].d + 1) * es));
-      }
-      return n;
-    };
-    int64_t bytes = bp.tile_bytes;
-    while (bytes > batch_min_tile_bytes() && tiles_at(bytes) < 2 * (int64_t)bp.cus) bytes /= 2;
+    BatchStep* row = &bp.h_steps[(size_t)t * B];
+    double total = 0.0;
+    for (int b = 0; b < B; ++b) total += (double)std::max<int64_t>(row[b].n, 0) * (ps[b].d + 1) * es;
+    bp.h_bytes[t] = total;
+    int64_t want = 0;
+    if (total > 0.0)
+      want = std::clamp<int64_t>((int64_t)std::ceil(total / (double)batch_min_tile_bytes()), 1, slots);
+    int64_t given = 0;
+    std::vector<int64_t> lo(B, 0), cap(B, 0), tiles(B, 0);
     for (int b = 0; b < B; ++b) {
-      BatchStep& st = bp.h_steps[(size_t)t * B + b];
-      st.tile_rows = batch_tile_rows(bytes, (ps[b].d + 1) * es);
+      frac[b] = -1.0;
+      if (row[b].n <= 0) continue;
+      lo[b] = ceil_div(row[b].n, (int64_t)kBatchTileCeil);
+      cap[b] = ceil_div(row[b].n, (int64_t)kBatchTileFloor);
+      const double q = (double)row[b].n * (ps[b].d + 1) * es * (double)want / total;
+      tiles[b] = std::clamp<int64_t>((int64_t)q, lo[b], cap[b]);
+      frac[b] = q - std::floor(q);
+      given += tiles[b];
+    }
+    // one tile more for the largest remainders, or (when the one-tile minimum
+    // of small problems overshot) one fewer for the smallest
+    for (int b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return frac[x] > frac[y]; });
+    for (int i = 0; i < B && given < want; ++i) {
+      const int b = order[i];
+      if (frac[b] < 0.0 || tiles[b] >= cap[b]) continue;
+      ++tiles[b];
+      ++given;
+    }
+    for (int i = B - 1; i >= 0 && given > want; --i) {
+      const int b = order[i];
+      if (frac[b] < 0.0 || tiles[b] <= lo[b]) continue;
+      --tiles[b];
+      --given;
+    }
+    for (int b = 0; b < B; ++b) {
+      BatchStep& st = row[b];
+      if (st.n <= 0) {
+        st.tile_rows = 1;
+        st.ntiles = 0;
+        continue;
+      }
+      // whole steps of the pass's unguarded main loop per tile (only the
+      // problem's last tile has a remainder)
+      const BatchProblem& pr = bp.h_probs[b];
+      const int64_t step_rows =
+          (int64_t)(kBatchThreads / 64) * (64 / pr.lpr) * (kBatchSlots / pr.ch);
+      st.tile_rows = (int)std::min<int64_t>(round_up(ceil_div(st.n, tiles[b]), step_rows), st.n);
       st.ntiles = (int)ceil_div(st.n, (int64_t)st.tile_rows);
-      bp.max_tiles[b] = std::max<int64_t>(bp.max_tiles[b], st.ntiles);
     }
   }
   for (int t = 0; t < bp.T; ++t) {
@@ -1345,6 +1380,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     BatchProblem& pr = bp.h_probs[b];
     pr.d = d;
     pr.lpr = lpr;
+    pr.ch = p2;
     pr.M = bp.Mpool + bp.m_off[b];
     pr.beta_out = betas[b];
     const double eta = qs[b].eta, mu = qs[b].mu;
@@ -1363,11 +1399,17 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bool tuned = false;
   if (auto it = ctx->rg_tune.find(key); it != ctx->rg_tune.end()) {
     bp.grid = it->second.first;
-    bp.tile_bytes = (int64_t)it->second.second << 10;
+    bp.items = it->second.second;
+    tuned = true;
+  } else if (const char* e = std::getenv("SLSE_BATCH_GRID")) {
+    // fixed launch shape (SLSE_BATCH_GRID blocks, SLSE_BATCH_ITEMS tiles each)
+    bp.grid = std::max(1, std::atoi(e));
+    const char* k = std::getenv("SLSE_BATCH_ITEMS");
+    bp.items = std::max(1, k ? std::atoi(k) : 1);
     tuned = true;
   } else {
-    bp.grid = 2 * ctx->num_cus;
-    bp.tile_bytes = int64_t(1) << 20;
+    bp.grid = 4 * ctx->num_cus;
+    bp.items = 1;
   }
   // partial pool sized for the shortest tile a step may use
   int64_t part_n = 0;
@@ -1399,21 +1441,22 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
                        hipMemcpyHostToDevice));
   };
   if (!tuned && bp.T > 0) {
-    // time the step with the most tiles for a few (tile, grid) shapes
+    // time the step with the most bytes for a few (grid, tiles per block) shapes
     const char* env = std::getenv("SLSE_AUTOTUNE");
     const bool do_tune = !(env && std::atoi(env) == 0);
-    std::pair<int, int> best{bp.grid, (int)(bp.tile_bytes >> 10)};
+    std::pair<int, int> best{bp.grid, bp.items};
     if (do_tune) {
       hipEvent_t e0, e1;
       SLSE_HIP(hipEventCreate(&e0));
       SLSE_HIP(hipEventCreate(&e1));
       float best_ms = 1e30f;
-      for (int kb : {256, 512, 1024, 2048, 4096}) {
-        bp.tile_bytes = (int64_t)kb << 10;
-        upload();
-        const int tmax = (int)(std::max_element(bp.h_total.begin(), bp.h_total.end()) -
-                               bp.h_total.begin());
-        for (int g : {ctx->num_cus, 2 * ctx->num_cus, 4 * ctx->num_cus}) {
+      for (int g : {ctx->num_cus, 2 * ctx->num_cus, 3 * ctx->num_cus, 4 * ctx->num_cus})
+        for (int k : {1, 2, 4}) {
+          bp.grid = g;
+          bp.items = k;
+          upload();
+          const int tmax = (int)(std::max_element(bp.h_bytes.begin(), bp.h_bytes.end()) -
+                                 bp.h_bytes.begin());
           auto run = [&]() {
             launch_batched_resid_grad(bp.d_steps + (size_t)tmax * B, bp.d_probs,
                                       bp.d_prefix + (size_t)tmax * (B + 1), B, bp.h_total[tmax],
@@ -1428,16 +1471,15 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
           SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
           if (ms < best_ms) {
             best_ms = ms;
-            best = {g, kb};
+            best = {g, k};
           }
         }
-      }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
     ctx->rg_tune[key] = best;
     bp.grid = best.first;
-    bp.tile_bytes = (int64_t)best.second << 10;
+    bp.items = best.second;
   }
   upload();
   // one graph for the whole batch (sketches, factors, every step)
