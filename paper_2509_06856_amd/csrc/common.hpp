@@ -63,6 +63,22 @@ inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // ---------------------------------------------------------------------------
 // Device helpers.
 // ---------------------------------------------------------------------------
+// Global-memory (address space 1) pointers.  A pointer that a kernel reads
+// from a descriptor in memory (not a kernel argument) is generic to the
+// compiler, and its accesses become flat instructions, which also count
+// against the LDS counter: every wait for an LDS result then waits for the
+// memory accesses in flight too.  Casting such pointers at their accesses
+// keeps them global.
+#define SLSE_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SLSE_GLOBAL T* gptr(const T* p) {
+  return (const SLSE_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ SLSE_GLOBAL T* gptr(T* p) {
+  return (SLSE_GLOBAL T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_xor(T v, int mask) {
   return __shfl_xor(v, mask, 64);

@@ -30,8 +30,6 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // [X|Y] rows live in global memory: loads through global (address space 1)
 // pointers, not flat ones (the descriptors holding the pointers come from
 // memory, so the compiler cannot infer it)
-#define SLSE_GLOBAL __attribute__((address_space(1)))
-
 template <typename T, int VEC>
 __device__ __forceinline__ void load_vec_g(const T* p, T (&v)[VEC]) {
   if constexpr (VEC == 1) {
@@ -79,15 +77,22 @@ __device__ __forceinline__ double widen_f64(T x) {
 constexpr int kPrefixLds = 512;  // problems whose tile prefix is searched in LDS
 constexpr int kSlots = kBatchSlots;
 
-__device__ __forceinline__ int find_problem(const int* __restrict__ prefix, int B, int tile) {
-  int lo = 0, hi = B;  // prefix[lo] <= tile < prefix[hi]
+// the problem b with prefix[b] <= tile < prefix[b + 1]; *first = prefix[b]
+// (prefix[0] = 0)
+template <typename P>
+__device__ __forceinline__ int find_problem(P prefix, int B, int tile, int* first) {
+  int lo = 0, hi = B, vlo = 0;  // prefix[lo] = vlo <= tile < prefix[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= tile)
+    const int v = prefix[mid];
+    if (v <= tile) {
       lo = mid;
-    else
+      vlo = v;
+    } else {
       hi = mid;
+    }
   }
+  *first = vlo;
   return lo;
 }
 
@@ -156,7 +161,7 @@ __device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr
     const int col0 = (k * lpr + l) * VEC;
     full[k] = col0 + VEC <= d;
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) bv[k][v] = (col0 + v < d) ? beta[col0 + v] : 0.0;
+    for (int v = 0; v < VEC; ++v) bv[k][v] = (col0 + v < d) ? gptr(beta)[col0 + v] : 0.0;
   }
   double acc[CH][VEC];
 #pragma unroll
@@ -205,13 +210,13 @@ __device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr
       for (int k = 0; k < CH; ++k) {
         const int col0 = (k * lpr + l) * VEC;
         if (ok && full[k]) {
-          load_vec<T, VEC>(xr + col0, x[u][k]);
+          load_vec_g<T, VEC>(xr + col0, x[u][k]);
         } else {
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) x[u][k][v] = (ok && col0 + v < d) ? xr[col0 + v] : (T)0;
+          for (int v = 0; v < VEC; ++v) x[u][k][v] = (ok && col0 + v < d) ? gptr(xr)[col0 + v] : (T)0;
         }
       }
-      y[u] = ok ? Y[(ok ? row : r0) * st.incy] : (T)0;
+      y[u] = ok ? gptr(Y)[(ok ? row : r0) * st.incy] : (T)0;
     }
     rows_update<T, VEC, CH, RG>(x, y, bv, lpr, acc, rr);
   }
@@ -241,7 +246,7 @@ __device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) t += s_red[w][col];
-    prow[col] = t;
+    gptr(prow)[col] = t;
   }
 }
 
@@ -259,14 +264,16 @@ __global__ __launch_bounds__(kThreads) void batched_resid_grad_kernel(
     for (int i = threadIdx.x; i <= B; i += kThreads) s_prefix[i] = prefix[i];
     __syncthreads();
   }
-  const int* pfx = lds_prefix ? s_prefix : prefix;
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     // the problem and tile are block-uniform: in scalar registers, the step
-    // and problem descriptors come in through scalar loads
-    const int b = __builtin_amdgcn_readfirstlane(find_problem(pfx, B, tile));
+    // and problem descriptors come in through scalar loads (the LDS and the
+    // global search are kept apart so that neither becomes a flat access)
+    int first;
+    const int b = __builtin_amdgcn_readfirstlane(lds_prefix ? find_problem(s_prefix, B, tile, &first)
+                                                            : find_problem(prefix, B, tile, &first));
     const BatchStep st = steps[b];
     const BatchProblem pr = probs[b];
-    const int lt = __builtin_amdgcn_readfirstlane(tile - pfx[b]);
+    const int lt = __builtin_amdgcn_readfirstlane(tile - first);
     double* prow = pool + pr.part_off + (int64_t)lt * (pr.d + 1);
     if (CHMAX >= 4 && pr.ch == 4)
       batched_tile<T, VEC, (CHMAX >= 4 ? 4 : 1)>(st, pr.d, pr.lpr, lt, prow, s_red);
@@ -314,11 +321,11 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
       for (; j + 7 * nq < ntiles; j += 8 * nq) {
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(j + u * nq) * (d + 1) + k];
+        for (int u = 0; u < 8; ++u) v[u] = gptr(part)[(int64_t)(j + u * nq) * (d + 1) + k];
 #pragma unroll
         for (int u = 0; u < 8; ++u) t += v[u];
       }
-      for (; j < ntiles; j += nq) t += part[(int64_t)j * (d + 1) + k];
+      for (; j < ntiles; j += nq) t += gptr(part)[(int64_t)j * (d + 1) + k];
       s_part[q * d + k] = t;
     }
   }
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
       const double gk = s_g[k];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (i0 + u < row_hi) p[u] = fma(pr.M[(int64_t)(i0 + u) * d + k], gk, p[u]);
+        if (i0 + u < row_hi) p[u] = fma(gptr(pr.M)[(int64_t)(i0 + u) * d + k], gk, p[u]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -346,10 +353,10 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(
     if (lane < 4 && i0 + lane < row_hi) {
       const int i = i0 + lane;
       const double pi = lane == 0 ? p[0] : lane == 1 ? p[1] : lane == 2 ? p[2] : p[3];
-      const double bi = st.beta[i];
-      const double bn = bi + pr.mu * pi + pr.eta * (bi - st.beta_prev[i]);
-      st.beta_next[i] = bn;
-      pr.beta_out[i] = bn;
+      const double bi = gptr(st.beta)[i];
+      const double bn = bi + pr.mu * pi + pr.eta * (bi - gptr(st.beta_prev)[i]);
+      *gptr(st.beta_next + i) = bn;
+      *gptr(pr.beta_out + i) = bn;
       bad |= !isfinite(bn);
     }
   }
@@ -360,9 +367,9 @@ __global__ void batched_init_kernel(const BatchProblem* __restrict__ probs) {
   const BatchProblem pr = probs[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= pr.d) return;
-  const double v = pr.beta0 ? pr.beta0[i] : 0.0;
-  if (pr.beta_init) pr.beta_init[i] = v;
-  pr.beta_out[i] = v;
+  const double v = pr.beta0 ? gptr(pr.beta0)[i] : 0.0;
+  if (pr.beta_init) *gptr(pr.beta_init + i) = v;
+  *gptr(pr.beta_out + i) = v;
 }
 
 template <typename T, int VEC>

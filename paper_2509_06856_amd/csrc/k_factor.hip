@@ -28,11 +28,13 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 
 // One 64 x 64 output tile of C = alpha op(A) op(B) + beta C over k in
 // [kb0, kend); with `part` the raw sums go to split slot `zpart` instead.
-__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha,
-                                          const double* __restrict__ A, int64_t lda, int transA,
-                                          const double* __restrict__ B, int64_t ldb, int transB,
-                                          double beta, double* __restrict__ C, int64_t ldc,
-                                          double* __restrict__ part, int zpart, int64_t i0,
+// (the pointer types are generic, or global ones from a batched kernel's
+// job descriptors)
+template <typename CP, typename MP>
+__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha, CP __restrict__ A,
+                                          int64_t lda, int transA, CP __restrict__ B, int64_t ldb,
+                                          int transB, double beta, MP __restrict__ C, int64_t ldc,
+                                          MP __restrict__ part, int zpart, int64_t i0,
                                           int64_t j0, int64_t kb0, int64_t kend) {
   __shared__ double As[kKStep][kTile + 1];
   __shared__ double Bs[kKStep][kTile + 1];
@@ -123,8 +125,9 @@ __global__ __launch_bounds__(256) void factor_gemm_batched_kernel(const FactorJo
   if (i0 >= d || j0 >= d) return;
   const int64_t kper = round_up(ceil_div(jb.rows, (int64_t)splits), kKStep);
   const int64_t kb0 = sp * kper;
-  gemm_tile(d, d, 1.0, jb.Ad, d, 1, jb.Ad, d, 0, 0.0, jb.G, d, splits > 1 ? jb.part : nullptr, sp,
-            i0, j0, kb0, min(jb.rows, kb0 + kper));
+  gemm_tile(d, d, 1.0, gptr((const double*)jb.Ad), d, 1, gptr((const double*)jb.Ad), d, 0, 0.0,
+            gptr(jb.G), d, splits > 1 ? gptr(jb.part) : nullptr, sp, i0, j0, kb0,
+            min(jb.rows, kb0 + kper));
 }
 
 // G = sum of the job's split slots, in split order (blockIdx.y = job)
@@ -134,8 +137,8 @@ __global__ void factor_reduce_batched_kernel(const FactorJob* __restrict__ jobs,
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     double t = 0.0;
-    for (int q = 0; q < splits; ++q) t += jb.part[(int64_t)q * n + e];
-    jb.G[e] = t;
+    for (int q = 0; q < splits; ++q) t += gptr(jb.part)[(int64_t)q * n + e];
+    *gptr(jb.G + e) = t;
   }
 }
 
@@ -351,9 +354,9 @@ __global__ void convert_scale_batched_kernel(const FactorJob* __restrict__ jobs,
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / jb.d, k = e % jb.d;
-    const double v = is_f32 ? (double)static_cast<const float*>(jb.A)[i * jb.lda + k]
-                            : static_cast<const double*>(jb.A)[i * jb.lda + k];
-    jb.Ad[e] = jb.scale * v;
+    const double v = is_f32 ? (double)gptr(static_cast<const float*>(jb.A))[i * jb.lda + k]
+                            : gptr(static_cast<const double*>(jb.A))[i * jb.lda + k];
+    *gptr(jb.Ad + e) = jb.scale * v;
   }
 }
 
@@ -394,9 +397,9 @@ __device__ __forceinline__ void gj_invert32(double (&col)[kGJ], int lane, bool* 
   }
 }
 
-__device__ __forceinline__ void gj_panel(int d, int k0, double* __restrict__ G,
-                                         double* __restrict__ colp, int* __restrict__ info,
-                                         int bx) {
+template <typename DP, typename IP>
+__device__ __forceinline__ void gj_panel(int d, int k0, DP __restrict__ G, DP __restrict__ colp,
+                                         IP __restrict__ info, int bx) {
   __shared__ double Pinv[kGJ][kGJ + 1];
   __shared__ double Rp[kGJ][kGJChunk + 1];
   const int t = threadIdx.x;
@@ -454,12 +457,13 @@ __global__ __launch_bounds__(256) void gj_panel_batched_kernel(const FactorJob* 
                                                                int k0) {
   const FactorJob jb = jobs[blockIdx.y];
   if (k0 >= jb.d || (int)blockIdx.x * kGJChunk >= jb.d) return;
-  gj_panel(jb.d, k0, jb.M, jb.colp, jb.info, blockIdx.x);
+  gj_panel(jb.d, k0, gptr(jb.M), gptr(jb.colp), jb.info, blockIdx.x);
 }
 
 // one 32 x 32 output tile per block (by = row tile, bx = column tile)
-__device__ __forceinline__ void gj_update(int d, int k0, double* __restrict__ G,
-                                          const double* __restrict__ colp, int bx, int by) {
+template <typename DP, typename CP>
+__device__ __forceinline__ void gj_update(int d, int k0, DP __restrict__ G, CP __restrict__ colp,
+                                          int bx, int by) {
   __shared__ double Cp[kGJ][kGJ + 1];  // colp rows of this tile
   __shared__ double Rw[kGJ][kGJ + 1];  // new row panel columns of this tile
   const int kw = min(kGJ, d - k0);
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(256) void gj_update_batched_kernel(const FactorJob*
   const FactorJob jb = jobs[blockIdx.z];
   const int nt = (int)ceil_div(jb.d, kGJ);
   if (k0 >= jb.d || (int)blockIdx.x >= nt || (int)blockIdx.y >= nt) return;
-  gj_update(jb.d, k0, jb.M, jb.colp, blockIdx.x, blockIdx.y);
+  gj_update(jb.d, k0, gptr(jb.M), gptr((const double*)jb.colp), blockIdx.x, blockIdx.y);
 }
 
 // G += coef trace(G) I (one block): the diagonal shift of shifted CholeskyQR

@@ -93,13 +93,13 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
   const int64_t hi_part = hi << (P.s0 + B);
   const int col_base = ct * CT;
   if constexpr ((MODE & kFirst) != 0) {
-    for (int k = threadIdx.x; k < (1 << B); k += NT) s_pi[k] = P.pi_sgn[hi_part | k];
+    for (int k = threadIdx.x; k < (1 << B); k += NT) s_pi[k] = gptr(P.pi_sgn)[hi_part | k];
   }
   if constexpr ((MODE & kLast) != 0) {
     const int64_t gb = g << B;
     for (int k = threadIdx.x; k < (1 << B); k += NT) {
-      s_slot[k] = P.slotA[gb + k];
-      s_slot[(1 << B) + k] = P.slotH[gb + k];
+      s_slot[k] = gptr(P.slotA)[gb + k];
+      s_slot[(1 << B) + k] = gptr(P.slotH)[gb + k];
     }
   }
   if constexpr ((MODE & (kFirst | kLast)) != 0) __syncthreads();
@@ -135,7 +135,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
         const uintptr_t ax = reinterpret_cast<uintptr_t>(P.X + srow * P.ldx + col);
         const uintptr_t ay = reinterpret_cast<uintptr_t>(P.Y + srow);
         const T* addr = reinterpret_cast<const T*>(col < P.d ? ax : ay);
-        raw[k] = __builtin_bit_cast(U, __builtin_nontemporal_load(addr));
+        raw[k] = __builtin_bit_cast(U, __builtin_nontemporal_load(gptr(addr)));
         negm |= (uint64_t)neg << k;
         keepm |= (uint64_t)(in_rows && col <= P.d) << k;
       }
@@ -153,7 +153,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
       for (int k = 0; k < RA; ++k) {
         const int64_t pos = q + (k << BB);
         const int64_t j = (MODE & kGroupOrder) ? ((g << B) | pos) : (hi_part | (pos << P.s0) | lo);
-        v[ia][k] = __builtin_nontemporal_load(P.Z + j * P.ldz + col);
+        v[ia][k] = __builtin_nontemporal_load(gptr(P.Z + j * P.ldz + col));
       }
     }
 #pragma unroll
@@ -211,8 +211,8 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
           for (int k = 0; k < RB; ++k) {
             const int32_t sa = s_slot[(qq << BB) + k];
             const int32_t sh = s_slot[(1 << B) + (qq << BB) + k];
-            if (sa >= 0) __builtin_nontemporal_store(w[k], P.A + (int64_t)sa * P.lda + col);
-            if (sh >= 0) P.Ahat[(int64_t)sh * P.ldah + col] = w[k];
+            if (sa >= 0) __builtin_nontemporal_store(w[k], gptr(P.A + (int64_t)sa * P.lda + col));
+            if (sh >= 0) *gptr(P.Ahat + (int64_t)sh * P.ldah + col) = w[k];
           }
         }
       } else {
@@ -222,7 +222,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
           // group order: the first pass (s0 = 0) holds rows (g, pos), which
           // the last pass's group pos reads at slot g
           const int64_t j = (MODE & kGroupOrder) ? ((pos << P.zb) | g) : (hi_part | (pos << P.s0) | lo);
-          __builtin_nontemporal_store(w[k], P.Z + j * P.ldz + col);
+          __builtin_nontemporal_store(w[k], gptr(P.Z + j * P.ldz + col));
         }
       }
     }
@@ -296,12 +296,12 @@ __device__ __forceinline__ void srht_index_range(int64_t j0, int64_t stride, int
                                                  int32_t* __restrict__ pi_sgn,
                                                  int32_t* __restrict__ slotA) {
   prp_each<false>(j0, npad, stride, seed, rng::kStreamP, p,
-                  [&](int64_t j, uint64_t src) { pi_sgn[j] = (int32_t)src; });
+                  [&](int64_t j, uint64_t src) { gptr(pi_sgn)[j] = (int32_t)src; });
   // the signs D over the same indices (each thread rereads its own writes)
   for (int64_t j = j0; j < npad; j += stride)
-    if (rng::rademacher(seed, (uint64_t)j) < 0) pi_sgn[j] = ~pi_sgn[j];
+    if (rng::rademacher(seed, (uint64_t)j) < 0) gptr(pi_sgn)[j] = ~gptr(pi_sgn)[j];
   prp_each<true>(j0, npad, stride, seed, rng::kStreamS, p, [&](int64_t j, uint64_t t) {
-    slotA[last_pass_index(j, s0_last, b_last)] = t < (uint64_t)mK ? (int32_t)t : -1;
+    gptr(slotA)[last_pass_index(j, s0_last, b_last)] = t < (uint64_t)mK ? (int32_t)t : -1;
   });
 }
 
@@ -598,7 +598,7 @@ __global__ void srht_index_batched_kernel(const SrhtIndexJob* __restrict__ jobs)
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   srht_index_range(j0, stride, jb.npad, jb.p, jb.seed, jb.mK, jb.s0_last, jb.b_last, jb.pi_sgn,
                    jb.slotA);
-  for (int64_t j = j0; j < jb.npad; j += stride) jb.slotH[j] = -1;
+  for (int64_t j = j0; j < jb.npad; j += stride) gptr(jb.slotH)[j] = -1;
 }
 
 // every Hessian sample of every job (after the kernel above)
@@ -607,7 +607,7 @@ __global__ void srht_hat_batched_kernel(const SrhtIndexJob* __restrict__ jobs) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < jb.r;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = (int64_t)rng::prp((uint64_t)t, jb.seed, rng::kStreamShat, jb.p);
-    jb.slotH[last_pass_index(j, jb.s0_last, jb.b_last)] = (int32_t)t;
+    gptr(jb.slotH)[last_pass_index(j, jb.s0_last, jb.b_last)] = (int32_t)t;
   }
 }
 
