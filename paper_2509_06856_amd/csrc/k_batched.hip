@@ -31,30 +31,15 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // pointers, not flat ones (the descriptors holding the pointers come from
 // memory, so the compiler cannot infer it)
 template <typename T, int VEC>
-__device__ __forceinline__ void load_vec_g(const T* p, T (&v)[VEC]) {
+__device__ __forceinline__ void load_vec(const T* p, T (&v)[VEC]) {
   if constexpr (VEC == 1) {
-    v[0] = __builtin_nontemporal_load((const SLSE_GLOBAL T*)p);
+    v[0] = __builtin_nontemporal_load(gptr(p));
   } else if constexpr (sizeof(T) == 4) {
     f32x4 x = __builtin_nontemporal_load((const SLSE_GLOBAL f32x4*)p);
 #pragma unroll
     for (int i = 0; i < 4; ++i) v[i] = x[i];
   } else {
     f64x2 x = __builtin_nontemporal_load((const SLSE_GLOBAL f64x2*)p);
-    v[0] = x[0];
-    v[1] = x[1];
-  }
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[VEC]) {
-  if constexpr (VEC == 1) {
-    v[0] = __builtin_nontemporal_load(p);
-  } else if constexpr (sizeof(T) == 4) {
-    f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = x[i];
-  } else {
-    f64x2 x = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
     v[0] = x[0];
     v[1] = x[1];
   }
@@ -189,8 +174,8 @@ __device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr
 #pragma unroll
       for (int u = 0; u < RU; ++u) {
 #pragma unroll
-        for (int k = 0; k < CH; ++k) load_vec_g<T, VEC>(xp + u * xs + k * lpr * VEC, x[u][k]);
-        y[u] = __builtin_nontemporal_load((const SLSE_GLOBAL T*)(yp + u * ys));
+        for (int k = 0; k < CH; ++k) load_vec<T, VEC>(xp + u * xs + k * lpr * VEC, x[u][k]);
+        y[u] = __builtin_nontemporal_load(gptr(yp + u * ys));
       }
       rows_update<T, VEC, CH, RU>(x, y, bv, lpr, acc, rr);
     }
@@ -210,7 +195,7 @@ __device__ __forceinline__ void batched_tile(const BatchStep& st, int d, int lpr
       for (int k = 0; k < CH; ++k) {
         const int col0 = (k * lpr + l) * VEC;
         if (ok && full[k]) {
-          load_vec_g<T, VEC>(xr + col0, x[u][k]);
+          load_vec<T, VEC>(xr + col0, x[u][k]);
         } else {
 #pragma unroll
           for (int v = 0; v < VEC; ++v) x[u][k][v] = (ok && col0 + v < d) ? gptr(xr)[col0 + v] : (T)0;
