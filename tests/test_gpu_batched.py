@@ -152,3 +152,29 @@ def test_batched_rank_deficient_problem_is_singular(G):
     with pytest.raises(L.SlseError) as e:
         G.solve_batched([dev(p0.X), dev(X1)], [dev(p0.Y), dev(p1.Y)], ps)
     assert e.value.status == L.SLSE_ESINGULAR
+
+
+def test_batched_mixed_widths_and_tiny_problems_equal_single_solves(G):
+    # FP64 rows of 200 and 130 values take two and four 16-byte vectors per
+    # lane (the guarded loop, since lane groups overhang the row), 64 values
+    # fill the lane groups exactly (the unguarded loop); problems of 300 and
+    # 257 rows are shorter than one tile floor; one problem dominates the bytes
+    shapes = [(120000, 64), (9000, 200), (6000, 130), (300, 4), (257, 16), (4000, 64)]
+    Xs, Ys, ps, singles = [], [], [], []
+    for k, (n, d) in enumerate(shapes):
+        p = make_problem("plain_small", n=n, d=d, seed=1200 + k)
+        prm = _params(G, n, d, 1300 + k, s_max=6)
+        Xs.append(dev(p.X))
+        Ys.append(dev(p.Y))
+        ps.append(prm)
+        b, _ = G.solve(Xs[-1], Ys[-1], prm)
+        singles.append(b.cpu().numpy())
+    for call in range(2):
+        betas, infos = G.solve_batched(Xs, Ys, ps)
+        for b, shape in enumerate(shapes):
+            assert infos[b]["status"] == "SLSE_OK", (call, shape)
+            assert OS.rel_err(betas[b].cpu().numpy(), singles[b]) < 1e-13, (call, shape)
+    # a batch of one
+    beta1, info1 = G.solve_batched(Xs[1:2], Ys[1:2], ps[1:2])
+    assert info1[0]["status"] == "SLSE_OK"
+    assert OS.rel_err(beta1[0].cpu().numpy(), singles[1]) < 1e-13
