@@ -247,6 +247,9 @@ slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_param
  *              surrogate and use_graph fields are ignored).
  *  betas       host array of B device pointers (FP64, length d_b each).
  *  reps        host array of B reports, or NULL.
+ * Every problem of a batch shares one storage dtype and has d_b <= 512
+ * (d_b <= 256 when some problem's rows are not 16-byte aligned); EINVAL
+ * otherwise.
  * Returns the worst status of the batch.
  */
 slse_status slse_solve_batched(slse_ctx* ctx, int32_t B, const slse_problem* ps,

@@ -114,3 +114,27 @@ def test_context_lifecycle(G, L):
     assert torch.equal(b1, b2)
     c.close()
     c.close()  # idempotent
+
+
+def test_batched_argument_checks(G, L):
+    # host-side checks before any launch: one storage dtype per batch,
+    # d <= 512, and d <= 256 when some rows are not 16-byte aligned
+    p = make_problem("plain_small", n=4096, d=8)
+    X, Y = dev(p.X), dev(p.Y)
+    prm64 = G.Params(kind="srht", seed=1, m=[64, 128], a=[1, 1], r=48, s_max=2)
+    prm32 = G.Params(kind="srht", seed=1, m=[64, 128], a=[1, 1], r=48, s_max=2, precision="mixed")
+    with pytest.raises(L.SlseError) as e:
+        G.solve_batched([X, X.float()], [Y, Y.float()], [prm64, prm32])
+    assert e.value.status == L.SLSE_EINVAL and "dtype" in str(e.value)
+    Xw = torch.zeros((8192, 520), dtype=torch.float64, device="cuda:0")
+    Yw = torch.zeros(8192, dtype=torch.float64, device="cuda:0")
+    wide = G.Params(kind="srht", seed=1, m=[4096], a=[1], r=3120, s_max=2)
+    with pytest.raises(L.SlseError) as e:
+        G.solve_batched([Xw], [Yw], [wide])
+    assert e.value.status == L.SLSE_EINVAL and "512" in str(e.value)
+    Xu = torch.zeros((4096, 301), dtype=torch.float32, device="cuda:0")  # 1204-byte rows
+    Yu = torch.zeros(4096, dtype=torch.float32, device="cuda:0")
+    unaligned = G.Params(kind="srht", seed=1, m=[2048], a=[1], r=1806, s_max=2, precision="mixed")
+    with pytest.raises(L.SlseError) as e:
+        G.solve_batched([Xu], [Yu], [unaligned])
+    assert e.value.status == L.SLSE_EINVAL and "too large" in str(e.value)
