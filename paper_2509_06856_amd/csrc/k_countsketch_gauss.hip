@@ -497,28 +497,40 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 // ---------------------------------------------------------------------------
 // Gaussian sketch on the matrix cores: G and [X|Y] rounded to BF16 (nearest
 // even), products accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  Block
-// tile kMT sketch rows x kNT columns, one wave per 32 rows, kNT / 32
-// accumulators of 32 x 32 per wave; 16 data rows per step, G generated into
-// LDS by the block (one Philox block per thread per step), [X|Y] staged
-// transposed so that every lane reads its 8 consecutive k as one 16-byte load.
-// Two costs set the tile: every block of sketch rows stages [X|Y] again
-// (BF16 conversion, transposed LDS stores; measured about 3 ms per 2^22 x 513
-// pass) and every block of columns generates G again (about 15 ms per
-// 3072 x 2^22 entries), while the waves need four per SIMD to hide their
-// latencies.  512 x 160 (the largest block, five accumulators per wave within
-// 128 registers) measured best: 256 x 288 at two waves per SIMD was slower.
+// tile kMT sketch rows x kNT columns: waves in a kRG x kCG grid, each owning
+// 32 sketch rows and kNQ column tiles of 32 (kNQ accumulators of 32 x 32);
+// 16 kCG data rows per step, G generated into LDS by the block (one Philox
+// block per thread per step), [X|Y] staged transposed (16-byte loads of four
+// columns when rows are aligned) so that every lane reads its 8 consecutive
+// k as one 16-byte load.  Two costs set the tile: every block of sketch rows
+// stages [X|Y] again (BF16 conversion, transposed LDS stores) and every block
+// of columns generates G again (about 15 ms per 3072 x 2^22 entries), while
+// the waves need four per SIMD to hide their latencies.
 // Lane layout (checked by an in-bounds probe): lane l holds A[l%32][8(l/32)+j]
 // and B[8(l/32)+j][l%32], j < 8; accumulator r of lane l is
 // C[(r%4) + 8(r/4) + 4(l/32)][l%32].
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// 16 x 1 waves measured best (166 ms for two 3072-row sketches; 8 x 2 with
-// 32-row steps 182 ms, 4 x 4 with 64-row steps 265 ms)
-constexpr int kRG = 16;             // waves along the sketch rows (32 rows each)
-constexpr int kCG = 1;              // waves along the columns
-constexpr int kNQ = 5;              // 32-column tiles per wave
+// 8 x 2 waves (256 sketch rows x 320 columns, 32 data rows per step)
+// measured best for two 3072-row sketches of 2^22 x 513 once [X|Y] is staged
+// by 16-byte loads: 118 ms, against 124 ms for 16 x 1 (512 x 160), 133 ms
+// for 12 x 1 with six column tiles, 150 ms for 4 x 4 (one column block, 128
+// rows) and 181 ms for 8 x 1 with nine column tiles (two waves per SIMD)
+#ifndef SLSE_GAUSS_RG
+#define SLSE_GAUSS_RG 8
+#endif
+#ifndef SLSE_GAUSS_CG
+#define SLSE_GAUSS_CG 2
+#endif
+#ifndef SLSE_GAUSS_NQ
+#define SLSE_GAUSS_NQ 5
+#endif
+constexpr int kRG = SLSE_GAUSS_RG;  // waves along the sketch rows (32 rows each)
+constexpr int kCG = SLSE_GAUSS_CG;  // waves along the columns
+constexpr int kNQ = SLSE_GAUSS_NQ;  // 32-column tiles per wave
 constexpr int kMT = 32 * kRG;       // sketch rows per block
 constexpr int kNT = 32 * kNQ * kCG; // columns per block
 constexpr int kGThreads = 64 * kRG * kCG;
@@ -551,6 +563,8 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   constexpr int NQ = kNQ;
   const int rg = wave % kRG;  // 32-row group
   const int cg = wave / kRG;  // column group
+  // FP32 rows on 16-byte boundaries: [X|Y] staged by vector loads
+  const bool vec4 = sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldx % 4 == 0;
   f32x16_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -572,18 +586,46 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 #pragma unroll
       for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
     }
-    for (int e = threadIdx.x; e < kKT * kNT; e += kGThreads) {  // [X|Y] tile, stored transposed
-      const int jj = e / kNT, cc = e % kNT;
-      const int64_t j = j0 + jj;
-      const int col = c0 + cc;
-      float v = 0.0f;
-      if (j < j_end) {
-        if (col < d)
-          v = (float)X[j * ldx + col];
-        else if (col == d)
-          v = (float)Y[j];
+    if (vec4) {  // [X|Y] tile, stored transposed: four columns per 16-byte load
+      constexpr int NV = kNT / 4;
+      for (int e = threadIdx.x; e < kKT * NV; e += kGThreads) {
+        const int jj = e / NV, cv = e % NV;
+        const int64_t j = j0 + jj;
+        const int col = c0 + 4 * cv;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (j < j_end) {
+          if constexpr (sizeof(T) == 4) {
+            if (col + 4 <= d) {
+              const f32x4_t x = *reinterpret_cast<const f32x4_t*>(X + j * ldx + col);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = x[i];
+            }
+          }
+          if (col + 4 > d) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int c = col + i;
+              v[i] = c < d ? (float)X[j * ldx + c] : (c == d ? (float)Y[j] : 0.0f);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Ws[4 * cv + i][jj] = to_bf16_rne(v[i]);
       }
-      Ws[cc][jj] = to_bf16_rne(v);
+    } else {
+      for (int e = threadIdx.x; e < kKT * kNT; e += kGThreads) {  // [X|Y] tile, stored transposed
+        const int jj = e / kNT, cc = e % kNT;
+        const int64_t j = j0 + jj;
+        const int col = c0 + cc;
+        float v = 0.0f;
+        if (j < j_end) {
+          if (col < d)
+            v = (float)X[j * ldx + col];
+          else if (col == d)
+            v = (float)Y[j];
+        }
+        Ws[cc][jj] = to_bf16_rne(v);
+      }
     }
     __syncthreads();
 #pragma unroll
