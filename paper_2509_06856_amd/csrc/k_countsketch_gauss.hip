@@ -514,16 +514,15 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// 8 x 2 waves (256 sketch rows x 320 columns, 32 data rows per step)
-// measured best for two 3072-row sketches of 2^22 x 513 once [X|Y] is staged
-// by 16-byte loads: 118 ms, against 124 ms for 16 x 1 (512 x 160), 133 ms
-// for 12 x 1 with six column tiles, 150 ms for 4 x 4 (one column block, 128
-// rows) and 181 ms for 8 x 1 with nine column tiles (two waves per SIMD)
+// 4 x 4 waves (128 sketch rows x 640 columns: every column of a d <= 639
+// problem in one block, so G is generated once; 64 data rows per step)
+// measured best for two 3072-row sketches of 2^22 x 513 with staged tiles:
+// 77 ms, against 84 ms for 8 x 2 (256 x 320) and 119 ms for 16 x 1 (512 x 160)
 #ifndef SLSE_GAUSS_RG
-#define SLSE_GAUSS_RG 8
+#define SLSE_GAUSS_RG 4
 #endif
 #ifndef SLSE_GAUSS_CG
-#define SLSE_GAUSS_CG 2
+#define SLSE_GAUSS_CG 4
 #endif
 #ifndef SLSE_GAUSS_NQ
 #define SLSE_GAUSS_NQ 5
@@ -544,12 +543,40 @@ __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
   return __builtin_bit_cast(__bf16, (uint16_t)u);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d, const T* __restrict__ X,
-                                                         int64_t ldx, const T* __restrict__ Y,
-                                                         uint64_t seed, uint64_t stream, int64_t m,
-                                                         int splits, float* __restrict__ part,
-                                                         int64_t ldp) {
+// [X|Y] in BF16 (nearest even), cut into tiles of kKT data rows x kNT
+// columns stored column by column (tile[c][k]), tiles ordered by column block
+// then data-row chunk: the layout of the kernel's LDS tile, so that every
+// block copies its tiles with 16-byte loads instead of converting and
+// transposing [X|Y] again.  Rows past N and columns past d are zeros.
+constexpr int kStageThreads = 256;
+__global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
+    int64_t N, int d, const float* __restrict__ X, int64_t ldx, const float* __restrict__ Y,
+    int64_t nchunks, __bf16* __restrict__ tiles) {
+  const int64_t chunk = blockIdx.x;
+  const int cb = blockIdx.y;
+  const int64_t j0 = chunk * kKT;
+  __bf16* t = tiles + ((int64_t)cb * nchunks + chunk) * (kNT * kKT);
+  // item (column cc, 8 data rows from 8 q): eight loads, one 16-byte store
+  for (int e = threadIdx.x; e < kNT * (kKT / 8); e += kStageThreads) {
+    const int cc = e % kNT, q = e / kNT;
+    const int col = cb * kNT + cc;
+    bf16x8_t w;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t j = j0 + 8 * q + r;
+      float v = 0.0f;
+      if (j < N) v = col < d ? X[j * ldx + col] : (col == d ? Y[j] : 0.0f);
+      w[r] = to_bf16_rne(v);
+    }
+    *reinterpret_cast<bf16x8_t*>(t + (int64_t)cc * kKT + 8 * q) = w;
+  }
+}
+
+__global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
+                                                         const __bf16* __restrict__ tiles,
+                                                         int64_t nchunks, uint64_t seed,
+                                                         uint64_t stream, int64_t m, int splits,
+                                                         float* __restrict__ part, int64_t ldp) {
   __shared__ __attribute__((aligned(16))) __bf16 Gs[kMT][kKP];
   __shared__ __attribute__((aligned(16))) __bf16 Ws[kNT][kKP];
   const int lane = threadIdx.x & 63;
@@ -563,8 +590,7 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   constexpr int NQ = kNQ;
   const int rg = wave % kRG;  // 32-row group
   const int cg = wave / kRG;  // column group
-  // FP32 rows on 16-byte boundaries: [X|Y] staged by vector loads
-  const bool vec4 = sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldx % 4 == 0;
+  const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
   f32x16_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -586,45 +612,12 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 #pragma unroll
       for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
     }
-    if (vec4) {  // [X|Y] tile, stored transposed: four columns per 16-byte load
-      constexpr int NV = kNT / 4;
-      for (int e = threadIdx.x; e < kKT * NV; e += kGThreads) {
-        const int jj = e / NV, cv = e % NV;
-        const int64_t j = j0 + jj;
-        const int col = c0 + 4 * cv;
-        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (j < j_end) {
-          if constexpr (sizeof(T) == 4) {
-            if (col + 4 <= d) {
-              const f32x4_t x = *reinterpret_cast<const f32x4_t*>(X + j * ldx + col);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) v[i] = x[i];
-            }
-          }
-          if (col + 4 > d) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int c = col + i;
-              v[i] = c < d ? (float)X[j * ldx + c] : (c == d ? (float)Y[j] : 0.0f);
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Ws[4 * cv + i][jj] = to_bf16_rne(v[i]);
-      }
-    } else {
-      for (int e = threadIdx.x; e < kKT * kNT; e += kGThreads) {  // [X|Y] tile, stored transposed
-        const int jj = e / kNT, cc = e % kNT;
-        const int64_t j = j0 + jj;
-        const int col = c0 + cc;
-        float v = 0.0f;
-        if (j < j_end) {
-          if (col < d)
-            v = (float)X[j * ldx + col];
-          else if (col == d)
-            v = (float)Y[j];
-        }
-        Ws[cc][jj] = to_bf16_rne(v);
+    {  // [X|Y] tile: a copy of the staged BF16 tile (16-byte pieces)
+      const __bf16* tb = tcol + (j0 / kKT) * (kNT * kKT);
+      for (int e = threadIdx.x; e < kNT * (kKT / 8); e += kGThreads) {
+        const int cc = e / (kKT / 8), pc = e % (kKT / 8);
+        *reinterpret_cast<bf16x8_t*>(&Ws[cc][8 * pc]) =
+            *reinterpret_cast<const bf16x8_t*>(tb + (int64_t)cc * kKT + 8 * pc);
       }
     }
     __syncthreads();
@@ -828,19 +821,40 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   fold_levels<T>(a, A, offK, s);
 }
 
-template <typename T>
-void gaussian_mfma_t(const GaussianArgs& a, hipStream_t s) {
+// BF16 path scratch: the staged tiles (shared by the two sketches of one
+// [X|Y]: they depend only on N and d), then, at a 256-byte boundary, the split
+// partial sums
+size_t gauss_partial_bytes(const GaussianArgs& a) {
+  const size_t es = (a.t == SLSE_F64 && !a.bf16) ? 8 : 4;
+  return (size_t)a.splits * (size_t)a.m * (size_t)round_up(a.d + 1, 4) * es;
+}
+size_t gauss_tile_bytes(const GaussianArgs& a) {
+  if (!a.bf16) return 0;
+  return (size_t)ceil_div(a.d + 1, kNT) * (size_t)ceil_div(std::max<int64_t>(a.N, 1), kKT) *
+         (size_t)(kNT * kKT) * sizeof(__bf16);
+}
+
+void gaussian_mfma(const GaussianArgs& a, hipStream_t s) {
   const int cols = a.d + 1;
   const int64_t ldp = round_up(cols, 4);
+  const int64_t nchunks = ceil_div(std::max<int64_t>(a.N, 1), kKT);
+  __bf16* tiles = reinterpret_cast<__bf16*>(a.partial);
+  float* part = reinterpret_cast<float*>(reinterpret_cast<char*>(a.partial) +
+                                         round_up((int64_t)gauss_tile_bytes(a), 256));
+  if (!a.tiles_ready) {
+    gauss_stage_kernel<<<dim3((unsigned)nchunks, (unsigned)ceil_div(cols, kNT)), kStageThreads,
+                         0, s>>>(a.N, a.d, static_cast<const float*>(a.X), a.ldx,
+                                 static_cast<const float*>(a.Y), nchunks, tiles);
+    SLSE_LAUNCH_CHECK();
+  }
   // blockIdx.x is the sketch-row block: the blocks that read the same data
   // rows and columns run side by side and share them through the caches
   dim3 grid((unsigned)ceil_div(a.m, kMT), (unsigned)ceil_div(cols, kNT), (unsigned)a.splits);
-  gauss_mfma_kernel<T><<<grid, kGThreads, 0, s>>>(a.N, a.d, static_cast<const T*>(a.X), a.ldx,
-                                            static_cast<const T*>(a.Y), a.seed, a.stream_id, a.m,
-                                            a.splits, a.partial, ldp);
+  gauss_mfma_kernel<<<grid, kGThreads, 0, s>>>(a.N, a.d, tiles, nchunks, a.seed, a.stream_id, a.m,
+                                               a.splits, part, ldp);
   SLSE_LAUNCH_CHECK();
   gauss_reduce_kernel<float, float><<<grid1(a.m * cols), 256, 0, s>>>(
-      a.partial, a.splits, a.m, cols, ldp, static_cast<float*>(a.A), a.lda);
+      part, a.splits, a.m, cols, ldp, static_cast<float*>(a.A), a.lda);
   SLSE_LAUNCH_CHECK();
 }
 
@@ -884,14 +898,14 @@ void gaussian_plan(GaussianArgs& a) {
 }
 
 size_t gaussian_scratch_bytes(const GaussianArgs& a) {
-  const size_t es = (a.t == SLSE_F64 && !a.bf16) ? 8 : 4;
-  return (size_t)a.splits * (size_t)a.m * (size_t)round_up(a.d + 1, 4) * es;
+  const size_t t = gauss_tile_bytes(a);
+  return t ? (size_t)round_up((int64_t)t, 256) + gauss_partial_bytes(a) : gauss_partial_bytes(a);
 }
 
 void launch_gaussian(const GaussianArgs& a, hipStream_t s) {
   if (a.bf16) {
     if (a.t != SLSE_F32) fail(SLSE_EUNSUPPORTED, "gaussian: BF16 products need F32 data");
-    gaussian_mfma_t<float>(a, s);
+    gaussian_mfma(a, s);
     return;
   }
   if (a.t == SLSE_F64)

@@ -208,6 +208,7 @@ struct GaussianArgs {
   double* partial64 = nullptr;
   int splits = 0;
   bool bf16 = false;          // BF16 operands on the matrix cores, FP32 accumulation
+  bool tiles_ready = false;   // BF16: the scratch already holds this [X|Y]'s staged tiles
 };
 size_t gaussian_scratch_bytes(const GaussianArgs& a);
 void gaussian_plan(GaussianArgs& a);

@@ -279,6 +279,8 @@ void enqueue_sketch(const SketchShape& s, uint64_t seed, const void* X, int64_t 
     gh.A = Ahat;
     gh.lda = ldah;
     launch_gaussian(ga, st);
+    // the BF16 tiles of [X|Y] staged for S serve S_hat too (same scratch, same stream)
+    gh.tiles_ready = ga.bf16 && gh.bf16 && ga.partial == gh.partial;
     launch_gaussian(gh, st);
   }
 }
