@@ -597,6 +597,24 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kKT) {
+    {  // [X|Y] tile: the staged BF16 tile copied straight into LDS (16 bytes
+       // per lane, placed linearly from the wave's LDS base; no registers),
+       // issued first so that the copy overlaps the generation of G.  An LDS
+       // row of Ws is kKP / 8 slots; its padding slot gets any valid bytes.
+      constexpr int kRowSlots = kKP / 8;
+      constexpr int kCopies = kNT * kRowSlots / 64;  // wave-wide copies per tile
+      static_assert(kKT % 8 == 0 && (kNT * kRowSlots) % 64 == 0, "whole wave-wide copies");
+      const __bf16* tb = tcol + (j0 / kKT) * (kNT * kKT);
+      for (int g = wave; g < kCopies; g += kGThreads / 64) {
+        const int sl = 64 * g + lane;
+        const int cc = sl / kRowSlots, pc = sl % kRowSlots;
+        const __bf16* src = tb + (int64_t)cc * kKT + 8 * (pc < kKT / 8 ? pc : 0);
+        __builtin_amdgcn_global_load_lds(
+            (const SLSE_GLOBAL void*)src,
+            (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(&Ws[0][0]) + 1024 * g),
+            16, 0, 0);
+      }
+    }
     {  // G tile: thread -> (row block of 8, data row)
       static_assert(kMT / 8 * kKT == kGThreads, "one Philox block per thread per step");
       const int kb = threadIdx.x / kKT;  // group of 8 sketch rows
@@ -612,14 +630,7 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 #pragma unroll
       for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
     }
-    {  // [X|Y] tile: a copy of the staged BF16 tile (16-byte pieces)
-      const __bf16* tb = tcol + (j0 / kKT) * (kNT * kKT);
-      for (int e = threadIdx.x; e < kNT * (kKT / 8); e += kGThreads) {
-        const int cc = e / (kKT / 8), pc = e % (kKT / 8);
-        *reinterpret_cast<bf16x8_t*>(&Ws[cc][8 * pc]) =
-            *reinterpret_cast<const bf16x8_t*>(tb + (int64_t)cc * kKT + 8 * pc);
-      }
-    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's copies are in LDS
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < kKT / 16; ++ks) {
