@@ -549,16 +549,23 @@ __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
 // block copies its tiles with 16-byte loads instead of converting and
 // transposing [X|Y] again.  Rows past N and columns past d are zeros.
 constexpr int kStageThreads = 256;
+// columns held by the tiles of column block cb: whole 32-column MFMA tiles up
+// to the last one with a column of [X|Y] (cols = d + 1)
+__host__ __device__ inline int gauss_tile_cols(int cols, int cb) {
+  const int left = (int)round_up(cols, 32) - cb * kNT;
+  return left < kNT ? left : kNT;
+}
 __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
     int64_t N, int d, const float* __restrict__ X, int64_t ldx, const float* __restrict__ Y,
     int64_t nchunks, __bf16* __restrict__ tiles) {
   const int64_t chunk = blockIdx.x;
   const int cb = blockIdx.y;
   const int64_t j0 = chunk * kKT;
-  __bf16* t = tiles + ((int64_t)cb * nchunks + chunk) * (kNT * kKT);
+  const int wc = gauss_tile_cols(d + 1, cb);
+  __bf16* t = tiles + (int64_t)cb * nchunks * (kNT * kKT) + chunk * (wc * kKT);
   // item (column cc, 8 data rows from 8 q): eight loads, one 16-byte store
-  for (int e = threadIdx.x; e < kNT * (kKT / 8); e += kStageThreads) {
-    const int cc = e % kNT, q = e / kNT;
+  for (int e = threadIdx.x; e < wc * (kKT / 8); e += kStageThreads) {
+    const int cc = e % wc, q = e / wc;
     const int col = cb * kNT + cc;
     bf16x8_t w;
 #pragma unroll
@@ -591,6 +598,7 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   const int rg = wave % kRG;  // 32-row group
   const int cg = wave / kRG;  // column group
   const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
+  const int wc = gauss_tile_cols(d + 1, blockIdx.y);  // columns of this block's tiles
   f32x16_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -602,13 +610,15 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
        // issued first so that the copy overlaps the generation of G.  An LDS
        // row of Ws is kKP / 8 slots; its padding slot gets any valid bytes.
       constexpr int kRowSlots = kKP / 8;
-      constexpr int kCopies = kNT * kRowSlots / 64;  // wave-wide copies per tile
       static_assert(kKT % 8 == 0 && (kNT * kRowSlots) % 64 == 0, "whole wave-wide copies");
-      const __bf16* tb = tcol + (j0 / kKT) * (kNT * kKT);
-      for (int g = wave; g < kCopies; g += kGThreads / 64) {
+      const int copies = (wc * kRowSlots + 63) / 64;  // wave-wide copies of this tile
+      const __bf16* tb = tcol + (j0 / kKT) * (wc * kKT);
+      for (int g = wave; g < copies; g += kGThreads / 64) {
         const int sl = 64 * g + lane;
         const int cc = sl / kRowSlots, pc = sl % kRowSlots;
-        const __bf16* src = tb + (int64_t)cc * kKT + 8 * (pc < kKT / 8 ? pc : 0);
+        // rows past the tile (the last copy's tail) and padding slots read
+        // the tile's first bytes; those LDS slots are never used
+        const __bf16* src = cc < wc ? tb + (int64_t)cc * kKT + 8 * (pc < kKT / 8 ? pc : 0) : tb;
         __builtin_amdgcn_global_load_lds(
             (const SLSE_GLOBAL void*)src,
             (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(&Ws[0][0]) + 1024 * g),
@@ -638,6 +648,7 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
       const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[rg * 32 + (lane & 31)][kk]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
+        if ((cg * NQ + q) * 32 >= wc) continue;  // a column tile past [X|Y]
         const bf16x8_t b =
             *reinterpret_cast<const bf16x8_t*>(&Ws[(cg * NQ + q) * 32 + (lane & 31)][kk]);
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
