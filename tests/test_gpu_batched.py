@@ -178,3 +178,27 @@ def test_batched_mixed_widths_and_tiny_problems_equal_single_solves(G):
     beta1, info1 = G.solve_batched(Xs[1:2], Ys[1:2], ps[1:2])
     assert info1[0]["status"] == "SLSE_OK"
     assert OS.rel_err(beta1[0].cpu().numpy(), singles[1]) < 1e-13
+
+
+def test_batched_f32_gaussian_bf16_reaches_ols(G):
+    # FP32 problems in the mixed form take the BF16 Gaussian sketch: each
+    # problem stages its own [X|Y] tiles in the shared scratch (S and S_hat of
+    # one problem share them).  Every problem reaches its OLS solution (the
+    # oracle's, on the same rounded data), as the single solves do; batched and
+    # single iterates differ only by summation order
+    shapes = [(3000, 37), (2500, 70), (4000, 16)]
+    Xs, Ys, ps, refs = [], [], [], []
+    for k, (n, d) in enumerate(shapes):
+        p = make_problem("plain_small", n=n, d=d, seed=1400 + k)
+        X32 = p.X.astype(np.float32)
+        Y32 = p.Y.astype(np.float32)
+        Xs.append(dev(X32))
+        Ys.append(dev(Y32))
+        ps.append(_params(G, n, d, 1500 + k, s_max=40, kind="gaussian", precision="mixed"))
+        refs.append(O.ols_refined(X32.astype(np.float64), Y32.astype(np.float64))[0])
+    betas, infos = G.solve_batched(Xs, Ys, ps)
+    for b, shape in enumerate(shapes):
+        single, _ = G.solve(Xs[b], Ys[b], ps[b])
+        assert infos[b]["status"] == "SLSE_OK", shape
+        assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-10, shape
+        assert OS.rel_err(single.cpu().numpy(), refs[b]) < 1e-10, shape
