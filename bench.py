@@ -483,6 +483,8 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only loop the fused residual-gradient kernel (backward: the rank-2 "
                          "adjoint pass), then a copy of X (for counter runs)")
+    ap.add_argument("--gaussian-only", action="store_true",
+                    help="only run three BF16 Gaussian sketch pairs (for a profiler)")
     ap.add_argument("--sketch-only", action="store_true",
                     help="only loop the SRHT and CountSketch sketches, then a copy of X "
                          "(for counter runs)")
@@ -542,6 +544,15 @@ def main():
             Z = X.clone()
         torch.cuda.synchronize()
         log(f"copy reference: {X.numel() * X.element_size()} bytes read and written per launch")
+        return
+    if args.gaussian_only:
+        # three BF16 Gaussian sketch pairs (S and S_hat of r = 6d rows each)
+        if not mixed:
+            raise SystemExit("--gaussian-only needs the FP32 (mixed) workload")
+        for _ in range(3):
+            G.sketch_apply(X, Y, "gaussian", params.seed, [6 * d], 6 * d, bf16=True)
+        torch.cuda.synchronize()
+        log(f"gaussian_bf16: 3 sketch pairs of N={N}, {6 * d} + {6 * d} rows")
         return
     if args.kernel_only:
         beta0 = torch.from_numpy(beta_star).to(dev)

@@ -563,19 +563,42 @@ __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
   const int64_t j0 = chunk * kKT;
   const int wc = gauss_tile_cols(d + 1, cb);
   __bf16* t = tiles + (int64_t)cb * nchunks * (kNT * kKT) + chunk * (wc * kKT);
-  // item (column cc, 8 data rows from 8 q): eight loads, one 16-byte store
-  for (int e = threadIdx.x; e < wc * (kKT / 8); e += kStageThreads) {
-    const int cc = e % wc, q = e / wc;
-    const int col = cb * kNT + cc;
-    bf16x8_t w;
+  // FP32 rows on 16-byte boundaries: four columns per load
+  const bool vec4 = (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldx % 4 == 0;
+  // item (4 columns from 4 c4, 8 data rows from 8 q): eight row loads, four
+  // 16-byte stores (the 8 k values of each column); consecutive threads take
+  // consecutive column groups of one row
+  const int ncg = wc / 4;
+  for (int e = threadIdx.x; e < ncg * (kKT / 8); e += kStageThreads) {
+    const int c4 = e % ncg, q = e / ncg;
+    const int col = cb * kNT + 4 * c4;
+    float v[8][4];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int64_t j = j0 + 8 * q + r;
-      float v = 0.0f;
-      if (j < N) v = col < d ? X[j * ldx + col] : (col == d ? Y[j] : 0.0f);
-      w[r] = to_bf16_rne(v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[r][i] = 0.0f;
+      if (j < N) {
+        if (vec4 && col + 4 <= d) {
+          const f32x4_t x = *reinterpret_cast<const f32x4_t*>(X + j * ldx + col);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[r][i] = x[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = col + i;
+            v[r][i] = c < d ? X[j * ldx + c] : (c == d ? Y[j] : 0.0f);
+          }
+        }
+      }
     }
-    *reinterpret_cast<bf16x8_t*>(t + (int64_t)cc * kKT + 8 * q) = w;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bf16x8_t w;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = to_bf16_rne(v[r][i]);
+      *reinterpret_cast<bf16x8_t*>(t + (int64_t)(4 * c4 + i) * kKT + 8 * q) = w;
+    }
   }
 }
 
