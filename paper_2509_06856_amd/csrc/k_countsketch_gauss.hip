@@ -499,13 +499,14 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 // even), products accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  Block
 // tile kMT sketch rows x kNT columns: waves in a kRG x kCG grid, each owning
 // 32 sketch rows and kNQ column tiles of 32 (kNQ accumulators of 32 x 32);
-// 16 kCG data rows per step, G generated into LDS by the block (one Philox
-// block per thread per step), [X|Y] staged transposed (16-byte loads of four
-// columns when rows are aligned) so that every lane reads its 8 consecutive
-// k as one 16-byte load.  Two costs set the tile: every block of sketch rows
-// stages [X|Y] again (BF16 conversion, transposed LDS stores) and every block
-// of columns generates G again (about 15 ms per 3072 x 2^22 entries), while
-// the waves need four per SIMD to hide their latencies.
+// 16 kCG data rows per step.  G is generated into LDS by the block (one
+// Philox block per thread per step).  [X|Y] is converted to BF16 once, by a
+// stage pass, into tiles laid out as the kernel's LDS tile (transposed, so
+// that every lane reads its 8 consecutive k as one 16-byte load); each step
+// copies its tile into LDS while it generates G.  Every block of columns
+// generates G again (about 15 ms per 3072 x 2^22 entries), so one block
+// covers every column of [X|Y] when d < 640; the waves need four per SIMD
+// to hide their latencies.
 // Lane layout (checked by an in-bounds probe): lane l holds A[l%32][8(l/32)+j]
 // and B[8(l/32)+j][l%32], j < 8; accumulator r of lane l is
 // C[(r%4) + 8(r/4) + 4(l/32)][l%32].
