@@ -528,10 +528,14 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 #ifndef SLSE_GAUSS_NQ
 #define SLSE_GAUSS_NQ 5
 #endif
-constexpr int kRG = SLSE_GAUSS_RG;  // waves along the sketch rows (32 rows each)
+#ifndef SLSE_GAUSS_RW
+#define SLSE_GAUSS_RW 1
+#endif
+constexpr int kRG = SLSE_GAUSS_RG;  // waves along the sketch rows
 constexpr int kCG = SLSE_GAUSS_CG;  // waves along the columns
 constexpr int kNQ = SLSE_GAUSS_NQ;  // 32-column tiles per wave
-constexpr int kMT = 32 * kRG;       // sketch rows per block
+constexpr int kRW = SLSE_GAUSS_RW;  // 32-row tiles per wave
+constexpr int kMT = 32 * kRW * kRG; // sketch rows per block
 constexpr int kNT = 32 * kNQ * kCG; // columns per block
 constexpr int kGThreads = 64 * kRG * kCG;
 constexpr int kKT = 8 * kGThreads / kMT;  // data rows per step: one Philox block per thread
@@ -619,15 +623,17 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   const int64_t j_begin = (int64_t)split * per;
   const int64_t j_end = min(N, j_begin + per);
   constexpr int NQ = kNQ;
-  const int rg = wave % kRG;  // 32-row group
+  const int rg = wave % kRG;  // row group (kRW tiles of 32 rows)
   const int cg = wave / kRG;  // column group
   const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
   const int wc = gauss_tile_cols(d + 1, blockIdx.y);  // columns of this block's tiles
-  f32x16_t acc[NQ];
+  f32x16_t acc[kRW][NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int w = 0; w < kRW; ++w)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[w][q][r] = 0.0f;
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kKT) {
     {  // [X|Y] tile: the staged BF16 tile copied straight into LDS (16 bytes
        // per lane, placed linearly from the wave's LDS base; no registers),
@@ -669,25 +675,32 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 #pragma unroll
     for (int ks = 0; ks < kKT / 16; ++ks) {
       const int kk = 16 * ks + 8 * (lane >> 5);
-      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&Gs[rg * 32 + (lane & 31)][kk]);
+      bf16x8_t a[kRW];
+#pragma unroll
+      for (int w = 0; w < kRW; ++w)
+        a[w] = *reinterpret_cast<const bf16x8_t*>(&Gs[(rg * kRW + w) * 32 + (lane & 31)][kk]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if ((cg * NQ + q) * 32 >= wc) continue;  // a column tile past [X|Y]
         const bf16x8_t b =
             *reinterpret_cast<const bf16x8_t*>(&Ws[(cg * NQ + q) * 32 + (lane & 31)][kk]);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+#pragma unroll
+        for (int w = 0; w < kRW; ++w)
+          acc[w][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[w], b, acc[w][q], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int w = 0; w < kRW; ++w)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t k = k0 + rg * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
-      const int col = c0 + (cg * NQ + q) * 32 + (lane & 31);
-      if (k < m && col <= d) part[((int64_t)split * m + k) * ldp + col] = acc[q][r];
-    }
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t k = k0 + (rg * kRW + w) * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
+        const int col = c0 + (cg * NQ + q) * 32 + (lane & 31);
+        if (k < m && col <= d) part[((int64_t)split * m + k) * ldp + col] = acc[w][q][r];
+      }
 }
 
 __global__ void debug_gauss_kernel(uint64_t seed, uint64_t stream, int64_t k0, int64_t nk,
