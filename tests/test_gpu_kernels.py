@@ -277,11 +277,13 @@ def test_gaussian_sketch_parity(G, dtype):
     assert np.all(np.abs(Ah.cpu().numpy() - ref["Ahat"]) <= tol)
 
 
-@pytest.mark.parametrize("N,d", [(3000, 37), (2500, 200), (1500, 520)])
+@pytest.mark.parametrize("N,d", [(3000, 37), (2500, 200), (1500, 520), (1500, 700)])
 def test_gaussian_sketch_bf16_mfma_parity(G, N, d):
     # BF16 operands (G and [X|Y] rounded to nearest even), FP32 accumulation on
     # the matrix cores; compared with the oracle on the same rounded operands.
-    # d = 200 and 520 take the wide tiles (every column in one block)
+    # Staged tiles hold the 32-column tiles with data: 64 columns at d = 37,
+    # every column in one block up to d = 639, two column blocks at d = 700
+    # (640 + 64 columns)
     g = np.random.default_rng(6 + d)
     X = g.standard_normal((N, d)).astype(np.float32)
     Y = g.standard_normal(N).astype(np.float32)
