@@ -271,6 +271,14 @@ slse_status slse_solve_batched(slse_ctx* ctx, int32_t B, const slse_problem* ps,
 slse_status slse_debug_stream(slse_ctx* ctx, int32_t what, uint64_t seed, int32_t stream_id,
                               int64_t aux, int64_t start, int64_t count, int64_t* out,
                               void* stream);
+/* Tiles of one batched step, as slse_solve_batched cuts them (host only, no
+ * device work): problem b has n[b] rows (0: idle) of row_bytes[b] bytes and
+ * a main loop of step_rows[b] rows per block step; slots = grid x tiles per
+ * block; min_tile_bytes is the smallest tile.  Writes tile_rows[b] and
+ * ntiles[b] (host arrays of B).  EINVAL on null pointers or sizes <= 0. */
+slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* row_bytes,
+                                   const int64_t* step_rows, int64_t slots, int64_t min_tile_bytes,
+                                   int32_t* tile_rows, int32_t* ntiles);
 /* Gaussian sketch entries G[k0 + a, j0 + b] (a < nk, b < nj) of stream 7 (S) or 8 (S_hat),
  * written row-major to `out` (device, FP64) as the library computes them in FP32. */
 slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int64_t k0,

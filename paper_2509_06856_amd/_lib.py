@@ -120,6 +120,7 @@ SIGNATURES = {
                                    ctypes.POINTER(slse_report), c_vp]),
     "slse_debug_stream": (c_i32, [c_vp, c_i32, c_u64, c_i32, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "slse_debug_gaussian": (c_i32, [c_vp, c_u64, c_i32, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
+    "slse_debug_batch_tiles": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
 }
 
 _lib = None

@@ -964,6 +964,64 @@ int batch_lpr(int d, bool vec, slse_dtype t) {
   return lpr;
 }
 
+// Tiles of one batched step.  Problem b has n[b] rows (0: idle) of
+// row_bytes[b] bytes; the pass's main loop covers step_rows[b] rows per block
+// step.  The step's bytes are cut into about `slots` tiles of equal size (no
+// smaller than min_tile_bytes), shared out over the problems by largest
+// remainder, so the grid's strided walk gives every block about the same
+// bytes; a problem's rows are split evenly over its tiles, rounded up to
+// whole main-loop steps (only its last tile has a remainder).  Every problem
+// gets between ceil(n / 2^20) and ceil(n / 256) tiles (the partial pool holds
+// ceil(n / 256) rows per problem).
+void split_step_tiles(int B, const int64_t* n, const int64_t* row_bytes, const int64_t* step_rows,
+                      int64_t slots, int64_t min_tile_bytes, int* tile_rows, int* ntiles) {
+  double total = 0.0;
+  for (int b = 0; b < B; ++b) total += (double)std::max<int64_t>(n[b], 0) * row_bytes[b];
+  int64_t want = 0;
+  if (total > 0.0)
+    want = std::clamp<int64_t>((int64_t)std::ceil(total / (double)std::max<int64_t>(min_tile_bytes, 1)),
+                               1, std::max<int64_t>(slots, 1));
+  int64_t given = 0;
+  std::vector<int64_t> lo(B, 0), cap(B, 0), tiles(B, 0);
+  std::vector<double> frac(B, -1.0);
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) {
+    if (n[b] <= 0) continue;
+    lo[b] = ceil_div(n[b], (int64_t)kBatchTileCeil);
+    cap[b] = ceil_div(n[b], (int64_t)kBatchTileFloor);
+    const double q = (double)n[b] * row_bytes[b] * (double)want / total;
+    tiles[b] = std::clamp<int64_t>((int64_t)q, lo[b], cap[b]);
+    frac[b] = q - std::floor(q);
+    given += tiles[b];
+  }
+  // one tile more for the largest remainders, or (when the one-tile minimum
+  // of small problems overshot) one fewer for the smallest
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return frac[x] > frac[y]; });
+  for (int i = 0; i < B && given < want; ++i) {
+    const int b = order[i];
+    if (frac[b] < 0.0 || tiles[b] >= cap[b]) continue;
+    ++tiles[b];
+    ++given;
+  }
+  for (int i = B - 1; i >= 0 && given > want; --i) {
+    const int b = order[i];
+    if (frac[b] < 0.0 || tiles[b] <= lo[b]) continue;
+    --tiles[b];
+    --given;
+  }
+  for (int b = 0; b < B; ++b) {
+    if (n[b] <= 0) {
+      tile_rows[b] = 1;
+      ntiles[b] = 0;
+      continue;
+    }
+    const int64_t sr = std::max<int64_t>(step_rows[b], 1);
+    tile_rows[b] = (int)std::min<int64_t>(round_up(ceil_div(n[b], tiles[b]), sr), n[b]);
+    ntiles[b] = (int)ceil_div(n[b], (int64_t)tile_rows[b]);
+  }
+}
+
 // Per-(step, problem) descriptors and tile prefix sums for a tile size.
 void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params* qs,
                         double* const* betas) {
@@ -1006,65 +1064,29 @@ void build_batch_tables(BatchPlan& bp, const slse_problem* ps, const slse_params
     for (int j = 0; j < qs[b].s_max; ++j) add(ps[b].X, ps[b].ldx, ps[b].Y, 1, ps[b].N, 1.0);
     (void)betas;
   }
-  // Tiles per (step, problem): a step's bytes of [X|Y] are cut into about
-  // grid x items tiles of equal size (no smaller than batch_min_tile_bytes()),
-  // shared out over the problems by largest remainder, so the grid's strided
-  // walk gives every block about the same bytes; a problem's rows are split
-  // evenly over its tiles.
+  // Tiles per (step, problem): split_step_tiles
   const int64_t es = (int64_t)dtype_size(bp.t);
   const int64_t slots = (int64_t)bp.grid * bp.items;
-  std::vector<double> frac(B);
-  std::vector<int> order(B);
+  std::vector<int64_t> n(B), row_bytes(B), step_rows(B);
+  std::vector<int> tile_rows(B), ntiles(B);
+  for (int b = 0; b < B; ++b) {
+    const BatchProblem& pr = bp.h_probs[b];
+    row_bytes[b] = (ps[b].d + 1) * es;
+    step_rows[b] = (int64_t)(kBatchThreads / 64) * (64 / pr.lpr) * (kBatchSlots / pr.ch);
+  }
   for (int t = 0; t < bp.T; ++t) {
     BatchStep* row = &bp.h_steps[(size_t)t * B];
     double total = 0.0;
-    for (int b = 0; b < B; ++b) total += (double)std::max<int64_t>(row[b].n, 0) * (ps[b].d + 1) * es;
+    for (int b = 0; b < B; ++b) {
+      n[b] = std::max<int64_t>(row[b].n, 0);
+      total += (double)n[b] * row_bytes[b];
+    }
     bp.h_bytes[t] = total;
-    int64_t want = 0;
-    if (total > 0.0)
-      want = std::clamp<int64_t>((int64_t)std::ceil(total / (double)batch_min_tile_bytes()), 1, slots);
-    int64_t given = 0;
-    std::vector<int64_t> lo(B, 0), cap(B, 0), tiles(B, 0);
+    split_step_tiles(B, n.data(), row_bytes.data(), step_rows.data(), slots,
+                     batch_min_tile_bytes(), tile_rows.data(), ntiles.data());
     for (int b = 0; b < B; ++b) {
-      frac[b] = -1.0;
-      if (row[b].n <= 0) continue;
-      lo[b] = ceil_div(row[b].n, (int64_t)kBatchTileCeil);
-      cap[b] = ceil_div(row[b].n, (int64_t)kBatchTileFloor);
-      const double q = (double)row[b].n * (ps[b].d + 1) * es * (double)want / total;
-      tiles[b] = std::clamp<int64_t>((int64_t)q, lo[b], cap[b]);
-      frac[b] = q - std::floor(q);
-      given += tiles[b];
-    }
-    // one tile more for the largest remainders, or (when the one-tile minimum
-    // of small problems overshot) one fewer for the smallest
-    for (int b = 0; b < B; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return frac[x] > frac[y]; });
-    for (int i = 0; i < B && given < want; ++i) {
-      const int b = order[i];
-      if (frac[b] < 0.0 || tiles[b] >= cap[b]) continue;
-      ++tiles[b];
-      ++given;
-    }
-    for (int i = B - 1; i >= 0 && given > want; --i) {
-      const int b = order[i];
-      if (frac[b] < 0.0 || tiles[b] <= lo[b]) continue;
-      --tiles[b];
-      --given;
-    }
-    for (int b = 0; b < B; ++b) {
-      BatchStep& st = row[b];
-      if (st.n <= 0) {
-        st.tile_rows = 1;
-        st.ntiles = 0;
-        continue;
-      }
-      // whole steps of the pass's unguarded main loop per tile (only the
-      // problem's last tile has a remainder)
-      const BatchProblem& pr = bp.h_probs[b];
-      const int64_t step_rows =
-          (int64_t)(kBatchThreads / 64) * (64 / pr.lpr) * (kBatchSlots / pr.ch);
-      st.tile_rows = (int)std::min<int64_t>(round_up(ceil_div(st.n, tiles[b]), step_rows), st.n);
-      st.ntiles = (int)ceil_div(st.n, (int64_t)st.tile_rows);
+      row[b].tile_rows = tile_rows[b];
+      row[b].ntiles = ntiles[b];
     }
   }
   for (int t = 0; t < bp.T; ++t) {
@@ -1762,6 +1784,23 @@ slse_status slse_debug_stream(slse_ctx* ctx, int32_t what, uint64_t seed, int32_
     if (what == 6 || what == 7) require(aux >= 1, "bucket count must be positive");
     DeviceGuard g(ctx->device);
     launch_debug_stream(what, seed, stream_id, aux, start, count, out, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* row_bytes,
+                                   const int64_t* step_rows, int64_t slots, int64_t min_tile_bytes,
+                                   int32_t* tile_rows, int32_t* ntiles) {
+  return guarded([&]() -> slse_status {
+    require(B >= 0 && (B == 0 || (n && row_bytes && step_rows && tile_rows && ntiles)),
+            "null pointer");
+    for (int b = 0; b < B; ++b) require(n[b] >= 0 && row_bytes[b] > 0 && step_rows[b] > 0, "bad sizes");
+    std::vector<int> tr(B), nt(B);
+    split_step_tiles(B, n, row_bytes, step_rows, slots, min_tile_bytes, tr.data(), nt.data());
+    for (int b = 0; b < B; ++b) {
+      tile_rows[b] = tr[b];
+      ntiles[b] = nt[b];
+    }
     return SLSE_OK;
   });
 }
