@@ -572,28 +572,32 @@ __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
   const bool vec4 = (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldx % 4 == 0;
   // item (4 columns from 4 c4, 8 data rows from 8 q): eight row loads, four
   // 16-byte stores (the 8 k values of each column); consecutive threads take
-  // consecutive column groups of one row
+  // the row groups of one column group, so that each store instruction
+  // fills whole 128-byte column segments of the tile
   const int ncg = wc / 4;
-  for (int e = threadIdx.x; e < ncg * (kKT / 8); e += kStageThreads) {
-    const int c4 = e % ncg, q = e / ncg;
+  constexpr int NQG = kKT / 8;
+  for (int e = threadIdx.x; e < ncg * NQG; e += kStageThreads) {
+    const int q = e % NQG, c4 = e / NQG;
     const int col = cb * kNT + 4 * c4;
     float v[8][4];
+    const int64_t jq = j0 + 8 * q;
+    if (vec4 && col + 4 <= d && jq + 8 <= N) {
+      // the common case: eight whole 16-byte loads, all in flight at once
+      f32x4_t x[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int64_t j = j0 + 8 * q + r;
+      for (int r = 0; r < 8; ++r) x[r] = *reinterpret_cast<const f32x4_t*>(X + (jq + r) * ldx + col);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[r][i] = 0.0f;
-      if (j < N) {
-        if (vec4 && col + 4 <= d) {
-          const f32x4_t x = *reinterpret_cast<const f32x4_t*>(X + j * ldx + col);
+      for (int r = 0; r < 8; ++r)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[r][i] = x[i];
-        } else {
+        for (int i = 0; i < 4; ++i) v[r][i] = x[r][i];
+    } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = col + i;
-            v[r][i] = c < d ? X[j * ldx + c] : (c == d ? Y[j] : 0.0f);
-          }
+      for (int r = 0; r < 8; ++r) {
+        const int64_t j = jq + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = col + i;
+          v[r][i] = j < N ? (c < d ? X[j * ldx + c] : (c == d ? Y[j] : 0.0f)) : 0.0f;
         }
       }
     }
