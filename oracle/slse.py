@@ -31,6 +31,8 @@ ROW_BLOCK = 1 << 16
 
 
 def default_params(d, r):
+    """(mu, eta) = ((1 - d/r)^2, d/r), the step sizes of the experiments (Sec. 5,
+    following the M-IHS choice)."""
     eta = d / r
     return (1.0 - eta) ** 2, eta
 
@@ -66,12 +68,37 @@ def mihs_step(beta, beta_prev, g, R, mu, eta):
     return beta + mu * apply_precond(R, g) + eta * (beta - beta_prev)
 
 
+def stop_estimate(R, g, beta_next):
+    """Estimate of the relative error of beta_t that a step can report for free:
+    ||H_hat^{-1} g_t|| / ||beta_{t+1}||.  At the fixed point of eq. (99) the
+    full-data gradient is X^T X (beta_hat - beta_t), so with H_hat ~ X^T X the
+    numerator approximates ||beta_hat - beta_t||.  A zero denominator leaves
+    the bare numerator."""
+    num = float(np.linalg.norm(apply_precond(R, g)))
+    den = float(np.linalg.norm(beta_next))
+    return num / den if den > 0.0 else num
+
+
+def prediction_error(X, beta, beta_ref, row_block=ROW_BLOCK):
+    """Delta = ||X (beta - beta_ref)||^2, the error measure of the experiments
+    (Sec. 5, with beta_ref the true coefficient vector), streamed over row
+    blocks in float64."""
+    e = np.asarray(beta, np.float64) - np.asarray(beta_ref, np.float64)
+    tot = 0.0
+    for i0 in range(0, X.shape[0], row_block):
+        v = np.asarray(X[i0:i0 + row_block], np.float64) @ e
+        tot += float(v @ v)
+    return tot
+
+
 def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
              momentum_reset=False, sk=None, **sketch_kw):
     """Run Alg. 2 and return (beta_T, trajectory, info).
 
-    trajectory[t] is beta_t for t = 0..T (T = sum(a) + s).  `sk` may pass a
-    precomputed oracle sketch (same seed and sizes) to avoid recomputing it.
+    trajectory[t] is beta_t for t = 0..T (T = sum(a) + s).  info["surrogate"][t]
+    is stop_estimate of step t (the step from beta_t to beta_{t+1}, with the
+    scaled sketched gradient in stage 1).  `sk` may pass a precomputed oracle
+    sketch (same seed and sizes) to avoid recomputing it.
     """
     d = X.shape[1]
     if mu is None or eta is None:
@@ -84,6 +111,7 @@ def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
     beta = np.zeros(d) if beta0 is None else np.asarray(beta0, np.float64).copy()
     beta_prev = beta.copy()
     traj = [beta.copy()]
+    sur = []
     for i, (mi, ai) in enumerate(zip(sk["m"], a)):
         Ai = sk["A"][sk["offset"][i]: sk["offset"][i] + mi]
         if momentum_reset:
@@ -91,14 +119,42 @@ def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
         for _ in range(ai):
             g = sketched_grad(Ai, d, sk["scale"][i], beta)
             beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
+            sur.append(stop_estimate(R, g, beta))
             traj.append(beta.copy())
     if momentum_reset:
         beta_prev = beta.copy()
     for _ in range(s):
         g = full_grad(X, Y, beta)
         beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
+        sur.append(stop_estimate(R, g, beta))
         traj.append(beta.copy())
-    return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta)
+    return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta, surrogate=sur)
+
+
+def ihs(X, Y, seed, kind, r, steps, beta0=None, **sketch_kw):
+    """Iterative Hessian sketch with the Hessian sketch drawn anew at every
+    step (the IHS update of Sec. 1, the baseline that SLSE-FRS improves on):
+
+        beta_{t+1} = beta_t + H_t^{-1} X^T (Y - X beta_t),
+        H_t = (S_t X)^T S_t X,
+
+    i.e. eq. (99) with mu = 1, eta = 0 and a fresh S_t of r rows per step.
+    Step t draws S_t with sketch key seed + t and uses the Hessian-sketch rows
+    (Ahat) of that key, so every step's sketch is independent of the others.
+    The sketch call also forms one nested level, which IHS does not use; its
+    size is the power of 2 >= r (a valid level for every sketch family).
+    Returns (beta_T, trajectory)."""
+    d = X.shape[1]
+    level = 1 << max(0, (int(r) - 1).bit_length())
+    beta = np.zeros(d) if beta0 is None else np.asarray(beta0, np.float64).copy()
+    traj = [beta.copy()]
+    for t in range(steps):
+        sk = make_sketch(kind, X, Y, seed + t, [level], r, **sketch_kw)
+        R = precond_factor(sk["Ahat"], d, sk["hat_scale"])
+        g = full_grad(X, Y, beta)
+        beta = beta + apply_precond(R, g)
+        traj.append(beta.copy())
+    return beta, traj
 
 
 def iteration_lower_bounds(m, d, omega):
