@@ -192,6 +192,15 @@ typedef struct {
   double* trajectory;         /* device, (sum a_i + s_max + 1) x d, row t = beta_t; or NULL */
   double* surrogate;          /* device, (sum a_i + s_max): the estimate above, per step; or NULL */
   int32_t use_graph;          /* 1: capture the whole solve once and replay it as a hipGraph */
+  /* Per-iterate error accounting against a caller's reference vector (for example
+   * the OLS solution, or the true coefficients of a synthetic model), written for
+   * t = 0..T (T = sum a_i + s_max), row t describing beta_t.  With tol > 0 the
+   * entries after the step that met tol are unspecified. */
+  const double* beta_ref;     /* device, d; required when rel_err or pred_err is set */
+  double* rel_err;            /* device, T+1: ||beta_t - beta_ref|| / ||beta_ref||; or NULL */
+  double* pred_err;           /* device, T+1: ||X (beta_t - beta_ref)||^2, the prediction error
+                                 Delta_t of the experiments (Sec. 5) when beta_ref is the true
+                                 beta; or NULL.  Costs one extra read of X per iterate. */
 } slse_params;
 
 typedef struct {
@@ -200,7 +209,13 @@ typedef struct {
   int32_t stage2_steps; /* steps actually taken */
   double surrogate0;    /* error estimate at the first stage-2 step */
   double surrogate_final; /* error estimate at the last step taken */
-  double ms_total;      /* device time of the call (hipEvents), when requested */
+  double ms_total;      /* device time of the call (hipEvents) */
+  /* device time of each phase of Alg. 2 (hipEvents between the phases); filled
+   * when use_graph = 0 (a replayed graph is timed only as a whole: zeros) */
+  double ms_sketch;     /* S_0 [X|Y]: every nested sketch and the Hessian sketch */
+  double ms_factor;     /* H_hat = (S_hat X)^T S_hat X and its inverse */
+  double ms_stage1;     /* the a_i M-IHS steps on the sketched subproblems (eq. (98)) */
+  double ms_stage2;     /* the full-data M-IHS steps (eq. (99)), with any error accounting */
 } slse_report;
 
 /*
@@ -219,6 +234,84 @@ slse_status slse_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* 
                        double* beta_out, slse_report* rep, void* stream);
 
 /*
+ * slse_workspace_size — device bytes that slse_solve_ws needs for this problem
+ * and these parameters (the sketch levels and the Hessian sketch, the SRHT /
+ * CountSketch / Gaussian scratch, the factor buffers, the iterate ring and the
+ * reduction partials of Alg. 2).  No device work, no allocation.
+ *  bytes   host, receives the size.
+ * Errors: EINVAL for the same argument errors slse_solve reports.
+ */
+slse_status slse_workspace_size(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                                size_t* bytes);
+
+/*
+ * slse_solve_ws — slse_solve with every scratch buffer carved from the caller's
+ * device workspace ws[0 .. ws_bytes) (256-byte aligned regions, in a fixed
+ * order) instead of the context's own memory, so the call allocates no device
+ * memory.  The workspace is the caller's: it must stay valid until the stream
+ * has finished the call, and calls that share one workspace must not overlap.
+ * The context still keeps the launch-shape cache and, with use_graph, a graph
+ * per (problem, params, beta_out, ws) that is replayed on later calls.  A solve
+ * through a workspace does not leave a preconditioner for slse_backward.
+ *  ws, ws_bytes   device workspace, at least slse_workspace_size bytes.
+ * Errors: as slse_solve; EINVAL when ws is NULL or ws_bytes is too small.
+ */
+slse_status slse_solve_ws(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                          double* beta_out, slse_report* rep, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
+ * slse_ihs — the iterative Hessian sketch baseline (the IHS update of Sec. 1):
+ * s_max full-data steps
+ *     beta_{t+1} = beta_t + H_t^{-1} X^T (Y - X beta_t),  H_t = (S_t X)^T S_t X,
+ * each with a Hessian sketch S_t of r rows drawn anew from the key seed + t (the
+ * Hessian-sketch rows of slse_sketch_apply under that key; the call also forms one
+ * nested level of the power of 2 >= r rows, which IHS does not use).  It is
+ * eq. (99) with mu = 1 and eta = 0 and a fresh H_hat per step.  Read from q: kind,
+ * seed, r, s_max, precision, factor, beta0, trajectory, use_graph; m, a, mu, eta,
+ * tol and the error-accounting fields are ignored.
+ *  beta_out   device FP64, length d: beta_{s_max}.
+ * Errors: as slse_solve.
+ */
+slse_status slse_ihs(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                     double* beta_out, slse_report* rep, void* stream);
+
+/*
+ * Parameter helpers (host only, no device work, no context).
+ *
+ * slse_paper_schedule — the sketch sizes of the experiments (Sec. 5): m_1 =
+ * m1_factor * d (8d in the paper) rounded up to a power of 2, m_{i+1} = 2 m_i
+ * (the constant ratio of the nested construction, Sec. 3), up to m_K = N/2
+ * rounded down to a power of 2.
+ *  m_out   host array of cap entries; *K_out receives K.
+ * Errors: EINVAL for N <= d, d < 1, m1_factor < 1, null pointers, an empty
+ * schedule (m_1 > N/2) or cap < K.
+ */
+slse_status slse_paper_schedule(int64_t N, int64_t d, int64_t m1_factor, int64_t* m_out,
+                                int32_t cap, int32_t* K_out);
+
+/*
+ * slse_paper_params — the Hessian-sketch size and step sizes of the experiments
+ * (Sec. 5): r = 6d when r_in <= 0 (else r_in), eta = d/r, mu = (1 - eta)^2.
+ * Errors: EINVAL for d < 1, r <= d or null pointers.
+ */
+slse_status slse_paper_params(int64_t d, int64_t r_in, int64_t* r_out, double* mu, double* eta);
+
+/*
+ * slse_stage1_counts — stage-1 step counts from the lower bound of Thm
+ * lowerBoundai (Sec. 4): for i >= 2, a_i is the smallest integer >= 1 with
+ *     3^{a_i} >= ((1 + omega) r(i-1, i) + 1) / omega,
+ *     r(i-1, i) = sqrt((m_i - d) / (m_{i-1} - d)).
+ * a_1 (whose bound, Thm a1, needs the first subproblem's unknown errors) is a1
+ * when a1 >= 1, else a_2 (2 when K = 1).
+ *  m       host, K sizes with m_{i-1} > d for i >= 2.
+ *  a_out   host, K counts.
+ * Errors: EINVAL for K < 1, null pointers, omega not in (0, 1], or m_{i-1} <= d.
+ */
+slse_status slse_stage1_counts(const int64_t* m, int32_t K, int64_t d, double omega, int32_t a1,
+                               int32_t* a_out);
+
+/*
  * slse_backward — adjoint of beta_hat(X, Y) for a loss L with
  * dL/dbeta_hat = w: lambda solves (X^T X) lambda = w by the same
  * sketch-preconditioned M-IHS iteration (lambda_0 = H_hat^{-1} w, then s_max
@@ -227,15 +320,16 @@ slse_status slse_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* 
  * (from differentiating the normal equations of the problem statement).
  * The preconditioner of the last slse_solve on the same data, seed and sizes
  * is reused when the context still holds it; otherwise it is rebuilt.
- *  beta_hat, w   device FP64, length d.
+ *  beta_hat      device FP64, length d.
+ *  w, incw       device FP64, entry k at w[k * incw] (incw >= 0; 0 repeats w[0]).
  *  dX, lddx      device output N x d in grad_t (F32 or F64), or NULL.
  *  dY            device output length N in grad_t, or NULL.
  *  lambda_out    device FP64 length d, or NULL.
  */
 slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
-                          const double* beta_hat, const double* w, void* dX, int64_t lddx,
-                          void* dY, slse_dtype grad_t, double* lambda_out, slse_report* rep,
-                          void* stream);
+                          const double* beta_hat, const double* w, int64_t incw, void* dX,
+                          int64_t lddx, void* dY, slse_dtype grad_t, double* lambda_out,
+                          slse_report* rep, void* stream);
 
 /*
  * slse_solve_batched — B independent problems (any N_b, d_b) solved as one
@@ -279,10 +373,27 @@ slse_status slse_debug_stream(slse_ctx* ctx, int32_t what, uint64_t seed, int32_
 slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* row_bytes,
                                    const int64_t* step_rows, int64_t slots, int64_t min_tile_bytes,
                                    int32_t* tile_rows, int32_t* ntiles);
+/* The host plan of slse_solve_batched for these problems, made without any
+ * device work or allocation (every buffer is placed at an offset from a fake
+ * base), then checked: each problem's regions lie inside their pools, the
+ * per-step tile tables cover every row once, and the SRHT index and record
+ * tables stay inside their sizes.  A failed check returns EINVAL with a
+ * message.  bytes_out (host, may be NULL) receives the device bytes the batch
+ * needs.  The betas of the problems are not read. */
+slse_status slse_debug_batch_plan(int32_t B, const slse_problem* ps, const slse_params* qs,
+                                  size_t* bytes_out);
 /* Gaussian sketch entries G[k0 + a, j0 + b] (a < nk, b < nj) of stream 7 (S) or 8 (S_hat),
- * written row-major to `out` (device, FP64) as the library computes them in FP32. */
-slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int64_t k0,
-                                int64_t nk, int64_t j0, int64_t nj, double* out, void* stream);
+ * written row-major to `out` (device, FP64) as the library computes them: form 0 as the
+ * FP32/FP64 sketch kernels do (FP32 Box-Muller), form 1 as the BF16 matrix-core kernel
+ * does (FP32 Box-Muller on the hardware transcendentals, rounded to BF16). */
+slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int32_t form,
+                                int64_t k0, int64_t nk, int64_t j0, int64_t nj, double* out,
+                                void* stream);
+/* Data-row splits the Gaussian sketch of N x (d+1) data into m sketch rows uses (host only):
+ * bf16 = 1 for the matrix-core form on F32 data, 0 for the FP32/FP64 form.  Each split sums
+ * its own contiguous range of data rows; the ranges are added in split order. */
+slse_status slse_debug_gaussian_plan(int64_t N, int64_t d, int64_t m, int32_t bf16,
+                                     int32_t* splits);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,9 @@ class slse_params(ctypes.Structure):
         ("trajectory", c_vp),
         ("surrogate", c_vp),
         ("use_graph", c_i32),
+        ("beta_ref", c_vp),
+        ("rel_err", c_vp),
+        ("pred_err", c_vp),
     ]
 
 
@@ -94,6 +97,10 @@ class slse_report(ctypes.Structure):
         ("surrogate0", c_f64),
         ("surrogate_final", c_f64),
         ("ms_total", c_f64),
+        ("ms_sketch", c_f64),
+        ("ms_factor", c_f64),
+        ("ms_stage1", c_f64),
+        ("ms_stage2", c_f64),
     ]
 
 
@@ -112,15 +119,31 @@ SIGNATURES = {
                                       c_i32, c_vp, c_vp, c_vp]),
     "slse_solve": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params), c_vp,
                            ctypes.POINTER(slse_report), c_vp]),
+    "slse_workspace_size": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "slse_solve_ws": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params), c_vp,
+                              ctypes.POINTER(slse_report), c_vp, ctypes.c_size_t, c_vp]),
+    "slse_ihs": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params), c_vp,
+                         ctypes.POINTER(slse_report), c_vp]),
+    "slse_paper_schedule": (c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i64), c_i32,
+                                    ctypes.POINTER(c_i32)]),
+    "slse_paper_params": (c_i32, [c_i64, c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_f64),
+                                  ctypes.POINTER(c_f64)]),
+    "slse_stage1_counts": (c_i32, [ctypes.POINTER(c_i64), c_i32, c_i64, c_f64, c_i32,
+                                   ctypes.POINTER(c_i32)]),
     "slse_backward": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params),
-                              c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_vp,
+                              c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i32, c_vp,
                               ctypes.POINTER(slse_report), c_vp]),
     "slse_solve_batched": (c_i32, [c_vp, c_i32, ctypes.POINTER(slse_problem),
                                    ctypes.POINTER(slse_params), ctypes.POINTER(c_vp),
                                    ctypes.POINTER(slse_report), c_vp]),
     "slse_debug_stream": (c_i32, [c_vp, c_i32, c_u64, c_i32, c_i64, c_i64, c_i64, c_vp, c_vp]),
-    "slse_debug_gaussian": (c_i32, [c_vp, c_u64, c_i32, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
+    "slse_debug_gaussian": (c_i32, [c_vp, c_u64, c_i32, c_i32, c_i64, c_i64, c_i64, c_i64, c_vp,
+                                    c_vp]),
+    "slse_debug_gaussian_plan": (c_i32, [c_i64, c_i64, c_i64, c_i32, ctypes.POINTER(c_i32)]),
     "slse_debug_batch_tiles": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "slse_debug_batch_plan": (c_i32, [c_i32, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
 }
 
 _lib = None

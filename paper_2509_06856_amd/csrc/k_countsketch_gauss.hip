@@ -707,16 +707,23 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
       }
 }
 
+// form 0: the entries of the VALU kernels; form 1: those of the matrix-core
+// kernel (hardware transcendentals, then rounded to BF16 as its operands are)
 __global__ void debug_gauss_kernel(uint64_t seed, uint64_t stream, int64_t k0, int64_t nk,
-                                   int64_t j0, int64_t nj, double* __restrict__ out) {
+                                   int64_t j0, int64_t nj, int form, double* __restrict__ out) {
   const int64_t n = nk * nj;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = e / nj, b = e % nj;
     const int64_t k = k0 + a, j = j0 + b;
     float z[8];
-    box_muller8(seed, stream, (uint64_t)j, (uint64_t)(k >> 3), z);
-    out[e] = (double)z[k & 7];
+    if (form == 1) {
+      box_muller8_fast(seed, stream, (uint64_t)j, (uint64_t)(k >> 3), z);
+      out[e] = (double)(float)(__bf16)z[k & 7];
+    } else {
+      box_muller8(seed, stream, (uint64_t)j, (uint64_t)(k >> 3), z);
+      out[e] = (double)z[k & 7];
+    }
   }
 }
 
@@ -980,9 +987,9 @@ void launch_gaussian(const GaussianArgs& a, hipStream_t s) {
 }
 
 void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_t nk, int64_t j0,
-                           int64_t nj, double* out, hipStream_t s) {
+                           int64_t nj, int form, double* out, hipStream_t s) {
   if (nk * nj <= 0) return;
-  debug_gauss_kernel<<<grid1(nk * nj), 256, 0, s>>>(seed, stream_id, k0, nk, j0, nj, out);
+  debug_gauss_kernel<<<grid1(nk * nj), 256, 0, s>>>(seed, stream_id, k0, nk, j0, nj, form, out);
   SLSE_LAUNCH_CHECK();
 }
 

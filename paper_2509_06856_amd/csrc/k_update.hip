@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
     }
     for (; q < a.groups; ++q) t += a.gpart[(int64_t)q * a.ldp + k];
     double g = a.scale * t;
-    if (a.w) g += a.w[k];
+    if (a.w) g += a.w[k * a.incw];
     s_g[k] = g;
   }
   __syncthreads();
@@ -112,6 +112,35 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
   }
 }
 
+// Per-iterate error accounting: rel_out[0] = ||beta - ref|| / ||ref|| (||beta - ref||
+// when ref = 0) and delta = beta - ref, either output optional.  One block; the
+// sums run over a fixed thread order and a fixed tree.
+__global__ __launch_bounds__(kThreads) void iter_error_kernel(const double* __restrict__ beta,
+                                                              const double* __restrict__ ref, int d,
+                                                              double* __restrict__ rel_out,
+                                                              double* __restrict__ delta) {
+  __shared__ double s_e[kThreads], s_r[kThreads];
+  double e = 0.0, r = 0.0;
+  for (int k = threadIdx.x; k < d; k += kThreads) {
+    const double x = beta[k] - ref[k];
+    if (delta) delta[k] = x;
+    e += x * x;
+    r += ref[k] * ref[k];
+  }
+  s_e[threadIdx.x] = e;
+  s_r[threadIdx.x] = r;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_e[threadIdx.x] += s_e[threadIdx.x + h];
+      s_r[threadIdx.x] += s_r[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && rel_out)
+    rel_out[0] = s_r[0] > 0.0 ? sqrt(s_e[0] / s_r[0]) : sqrt(s_e[0]);
+}
+
 __global__ void fill_i32_kernel(int* __restrict__ p, int v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -149,6 +178,12 @@ void launch_update(const UpdateArgs& a, hipStream_t s) {
   const size_t shm = (size_t)a.d * sizeof(double);
   if (shm > 64 * 1024) fail(SLSE_EUNSUPPORTED, "update: d too large for this build");
   mihs_update_kernel<<<blocks, kThreads, shm, s>>>(a, rpb);
+  SLSE_LAUNCH_CHECK();
+}
+
+void launch_iter_error(const double* beta, const double* ref, int d, double* rel_out,
+                       double* delta, hipStream_t s) {
+  iter_error_kernel<<<1, kThreads, 0, s>>>(beta, ref, d, rel_out, delta);
   SLSE_LAUNCH_CHECK();
 }
 

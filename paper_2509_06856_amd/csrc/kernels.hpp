@@ -70,6 +70,7 @@ struct UpdateArgs {
   int d = 0;
   double scale = 1.0;
   const double* w = nullptr;  // added to g (adjoint right-hand side), may be null
+  int64_t incw = 1;           // stride of w (0: w[0] for every k)
   const double* M = nullptr;
   int64_t ldm = 0;
   const double* beta = nullptr;
@@ -91,7 +92,9 @@ struct UpdateArgs {
 int update_blocks(int d);
 void launch_update(const UpdateArgs& a, hipStream_t s);
 
-// beta' = beta + mu * M * v (used for lambda_0 = H_hat^{-1} w; beta_prev = beta).
+// rel_out[0] = ||beta - ref|| / ||ref|| and delta = beta - ref (either may be null).
+void launch_iter_error(const double* beta, const double* ref, int d, double* rel_out,
+                       double* delta, hipStream_t s);
 void launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 void launch_fill_i32(int* dst, int value, int64_t n, hipStream_t s);
 void launch_fill_f64(double* dst, double value, int64_t n, hipStream_t s);
@@ -214,7 +217,7 @@ size_t gaussian_scratch_bytes(const GaussianArgs& a);
 void gaussian_plan(GaussianArgs& a);
 void launch_gaussian(const GaussianArgs& a, hipStream_t s);
 void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_t nk, int64_t j0,
-                           int64_t nj, double* out, hipStream_t s);
+                           int64_t nj, int form, double* out, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Dense FP64 helpers for the factorization.

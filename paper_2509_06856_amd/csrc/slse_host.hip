@@ -25,6 +25,14 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 // ---------------------------------------------------------------------------
 // Scratch arena: named grow-only device buffers.  Growing a buffer frees the
 // old one, so every captured graph is dropped when that happens.
+//
+// Two other modes serve the calls that must not allocate:
+//  - measuring: get() hands out offsets from a fake base (never dereferenced,
+//    no kernel is launched) and only adds up the bytes a call would need;
+//  - external: get() carves 256-byte aligned regions from a caller workspace
+//    in request order (EINVAL when it runs out).  Buffers that must start at
+//    zero are listed in `ext_zero` for the caller to clear on its stream.
+// In both modes a name asked for twice in one call gets the same region.
 // ---------------------------------------------------------------------------
 struct Arena {
   struct Buf {
@@ -34,8 +42,55 @@ struct Arena {
   std::map<std::string, Buf> bufs;
   bool grew = false;
 
+  bool measuring = false;
+  char* ext = nullptr;
+  size_t ext_bytes = 0;
+  size_t ext_used = 0;
+  std::map<std::string, Buf> ext_bufs;
+  std::vector<Buf> ext_zero;
+
+  static constexpr uintptr_t kMeasureBase = uintptr_t(1) << 40;
+
+  bool borrowed() const { return measuring || ext != nullptr; }
+
+  void begin_measure() {
+    end_borrow();
+    measuring = true;
+  }
+  void begin_external(void* base, size_t bytes) {
+    end_borrow();
+    ext = static_cast<char*>(base);
+    ext_bytes = bytes;
+  }
+  void end_borrow() {
+    measuring = false;
+    ext = nullptr;
+    ext_bytes = ext_used = 0;
+    ext_bufs.clear();
+    ext_zero.clear();
+  }
+
   void* get(const std::string& name, size_t bytes, bool zero_init = false) {
     bytes = std::max<size_t>(bytes, 256);
+    if (borrowed()) {
+      auto it = ext_bufs.find(name);
+      if (it != ext_bufs.end() && it->second.bytes >= bytes) return it->second.p;
+      const size_t off = (size_t)round_up((int64_t)ext_used, 256);
+      const size_t len = (size_t)round_up((int64_t)bytes, 256);
+      ext_used = off + len;
+      void* p = nullptr;
+      if (measuring) {
+        p = reinterpret_cast<void*>(kMeasureBase + off);
+      } else {
+        if (ext_used > ext_bytes)
+          fail(SLSE_EINVAL, "workspace too small: need at least " + std::to_string(ext_used) +
+                                " bytes, got " + std::to_string(ext_bytes));
+        p = ext + off;
+        if (zero_init) ext_zero.push_back(Buf{p, bytes});
+      }
+      ext_bufs[name] = Buf{p, bytes};
+      return p;
+    }
     Buf& b = bufs[name];
     if (b.bytes >= bytes) return b.p;
     if (b.p) SLSE_HIP(hipFree(b.p));
@@ -63,6 +118,12 @@ struct Arena {
   }
 };
 
+// Ends a borrowed (measuring or external) arena mode when it goes out of scope.
+struct BorrowScope {
+  Arena& a;
+  ~BorrowScope() { a.end_borrow(); }
+};
+
 }  // namespace slse
 
 struct slse_ctx {
@@ -80,6 +141,10 @@ struct slse_ctx {
     int precision = 0;
   } pre;
   std::map<std::string, hipGraphExec_t> graphs;
+  // recorded after each batched graph launch: the next batched call waits for
+  // it before it rewrites the shared descriptor tables
+  hipEvent_t batch_done = nullptr;
+  bool batch_busy = false;
   // autotuned (grid blocks, lanes per row) of the residual-gradient pass, keyed
   // by storage / accumulation / d / vector width / log2(rows)
   std::map<std::string, std::pair<int, int>> rg_tune;
@@ -374,6 +439,8 @@ struct IterBufs {
   double* sur_partial = nullptr;
   int* sur_counter = nullptr;
   int* flags = nullptr;  // [0] done, [1] non-finite
+  double* err_delta = nullptr;  // beta_t - beta_ref (per-iterate error accounting)
+  double* err_g = nullptr;      // discarded gradient of the prediction-error pass
   int max_blocks = 1024;   // capacity of the partial rows
   int grid_blocks = 512;   // grid of the residual-gradient launches (<= max_blocks)
 };
@@ -392,6 +459,8 @@ IterBufs reserve_iter(slse_ctx* ctx, int64_t d, const char* tag) {
   b.sur_partial = ctx->arena.get_t<double>(t + "_surp", 3 * update_blocks((int)d) + 8);
   b.sur_counter = ctx->arena.get_t<int>(t + "_surc", 4, true);
   b.flags = ctx->arena.get_t<int>(t + "_flags", 4);
+  b.err_delta = ctx->arena.get_t<double>(t + "_errd", d);
+  b.err_g = ctx->arena.get_t<double>(t + "_errg", d);
   return b;
 }
 
@@ -477,6 +546,20 @@ void tune_resid_grad(slse_ctx* ctx, const IterBufs& b, int64_t n, int d, slse_dt
   ctx->rg_tune[key] = pick;
 }
 
+// Per-iterate errors against a reference vector (slse_params.beta_ref):
+// rel[t] = ||beta_t - ref|| / ||ref|| and pred[t] = ||X (beta_t - ref)||^2 over
+// the full data (one fused pass with Y = 0 on beta_t - ref).
+struct ErrorSink {
+  const double* ref = nullptr;
+  double* rel = nullptr;
+  double* pred = nullptr;
+  int64_t N = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  slse_dtype storage = SLSE_F64;
+  bool on() const { return ref && (rel || pred); }
+};
+
 struct Stepper {
   IterBufs b;
   int d;
@@ -485,6 +568,32 @@ struct Stepper {
   int t = 0;  // iterate index
   hipStream_t st;
   const slse_ctx* ctx = nullptr;
+  ErrorSink err;
+
+  // errors of the current iterate beta_t (t = this->t)
+  void record_errors() {
+    if (!err.on()) return;
+    launch_iter_error(b.beta[cur], err.ref, d, err.rel ? err.rel + t : nullptr,
+                      err.pred ? b.err_delta : nullptr, st);
+    if (!err.pred) return;
+    const ResidGradPlan pl = rg_plan(ctx, b, err.N, d, err.storage, SLSE_F64, err.X, err.ldx);
+    ResidGradArgs a;
+    a.n = err.N;
+    a.d = d;
+    a.X = err.X;
+    a.ldx = err.ldx;
+    a.Y = nullptr;
+    a.incy = 1;
+    a.storage = err.storage;
+    a.accum = SLSE_F64;
+    a.beta = b.err_delta;
+    a.partial = b.partial;
+    a.gpart = b.gpart;
+    a.counters = b.counters;
+    a.capacity_blocks = b.max_blocks;
+    launch_resid_grad(pl, a, st);
+    launch_finalize_grad(b.gpart, pl.groups, pl.ldp, d, 1.0, b.err_g, err.pred + t, st);
+  }
 
   void start(const double* beta0, double* traj) {
     if (beta0)
@@ -495,13 +604,14 @@ struct Stepper {
     launch_fill_i32(b.flags, 0, 4, st);
     cur = prev = 0;
     t = 0;
+    record_errors();
   }
   void reset_momentum() { prev = cur; }
 
   // one M-IHS step on rows [0, n) of (X, Y)
   void step(int64_t n, const void* X, int64_t ldx, const void* Y, int64_t incy, slse_dtype storage,
             slse_dtype accum, double scale, const double* w, double mu, double eta, double* beta_out,
-            double* traj, double* sur, double tol) {
+            double* traj, double* sur, double tol, int64_t incw = 1) {
     const ResidGradPlan pl = rg_plan(ctx, b, n, d, storage, accum, X, ldx);
     ResidGradArgs a;
     a.n = n;
@@ -527,6 +637,7 @@ struct Stepper {
     u.d = d;
     u.scale = scale;
     u.w = w;
+    u.incw = incw;
     u.M = M;
     u.ldm = d;
     u.beta = b.beta[cur];
@@ -546,6 +657,7 @@ struct Stepper {
     prev = cur;
     cur = next;
     ++t;
+    record_errors();
   }
 };
 
@@ -565,6 +677,7 @@ struct SolvePlan {
   void* cs = nullptr;  // CountSketch bucket lists
   FactorBufs f;
   IterBufs it;
+  double* sur = nullptr;  // per-step error estimates (the caller's or ours)
 };
 
 void check_params(const slse_problem* p, const slse_params* q) {
@@ -579,9 +692,17 @@ void check_params(const slse_problem* p, const slse_params* q) {
   else
     fail(SLSE_EINVAL, "unknown precision");
   require(q->s_max >= 0, "s_max < 0");
+  require(q->K >= 0 && q->K <= SLSE_MAX_LEVELS, "need 0 <= K <= SLSE_MAX_LEVELS");
   for (int i = 0; i < q->K; ++i) require(q->a[i] >= 0, "a_i < 0");
   require(std::isfinite(q->mu) && std::isfinite(q->eta), "mu, eta must be finite");
   require(q->factor == SLSE_FACTOR_CHOL || q->factor == SLSE_FACTOR_QR, "unknown factor method");
+  require(!(q->rel_err || q->pred_err) || q->beta_ref, "rel_err / pred_err need beta_ref");
+}
+
+int total_steps(const slse_params* q) {
+  int T = q->s_max;
+  for (int i = 0; i < q->K; ++i) T += q->a[i];
+  return T;
 }
 
 // Row stride of the internal sketch buffers: rows of at least one 128-byte
@@ -592,6 +713,8 @@ int64_t sketch_ld(int64_t d, size_t es) {
   return (d + 1) >= line ? round_up(d + 1, line) : round_up(d + 1, 16 / (int64_t)es);
 }
 
+// Every scratch buffer of one solve, in a fixed order (the order also fixes
+// the layout of a caller workspace).
 SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* q) {
   SolvePlan pl;
   pl.sk = make_sketch_shape(q->kind, p->N, p->d, q->m, q->K, q->r);
@@ -607,17 +730,40 @@ SolvePlan reserve_solve(slse_ctx* ctx, const slse_problem* p, const slse_params*
                  q->precision == SLSE_PREC_MIXED && q->kind == SLSE_GAUSSIAN, &pl.cs);
   pl.f = reserve_factor(ctx, pl.sk.r, p->d, q->factor);
   pl.it = reserve_iter(ctx, p->d, "it");
+  // the per-step error estimates always land somewhere: the caller's buffer or ours
+  pl.sur = q->surrogate ? q->surrogate
+                        : ctx->arena.get_t<double>("sur_hist", (size_t)total_steps(q) + 1);
   return pl;
 }
 
+ErrorSink error_sink(const slse_problem* p, const slse_params* q) {
+  ErrorSink e;
+  e.ref = q->beta_ref;
+  e.rel = q->rel_err;
+  e.pred = q->pred_err;
+  e.N = p->N;
+  e.X = p->X;
+  e.ldx = p->ldx;
+  e.storage = p->dtype;
+  return e;
+}
+
+// Phase boundaries of one solve: ev[0] after the sketch, ev[1] after the
+// factor, ev[2] after stage 1, ev[3] after stage 2 (all optional).
 void enqueue_solve(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem* p,
-                   const slse_params* q, double* beta_out, hipStream_t st) {
+                   const slse_params* q, double* beta_out, hipStream_t st,
+                   hipEvent_t* ev = nullptr) {
   const int d = (int)p->d;
   const SketchShape& sk = pl.sk;
+  auto mark = [&](int k) {
+    if (ev && ev[k]) SLSE_HIP(hipEventRecord(ev[k], st));
+  };
   enqueue_sketch(sk, q->seed, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat, pl.ldah, pl.srht,
                  pl.ga, pl.gh, st, pl.cs);
+  mark(0);
   enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
-  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx};
+  mark(1);
+  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx, error_sink(p, q)};
   S.start(q->beta0, q->trajectory);
   launch_copy_f64(S.b.beta[0], beta_out, d, st);
   const size_t es = dtype_size(pl.st_t);
@@ -627,33 +773,87 @@ void enqueue_solve(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem*
     const char* base = static_cast<const char*>(pl.A) + (size_t)sk.offset[i] * pl.lda * es;
     for (int j = 0; j < q->a[i]; ++j) {
       S.step(sk.m[i], base, pl.lda, base + (size_t)d * es, pl.lda, pl.st_t, pl.acc1, sk.scale[i],
-             nullptr, q->mu, q->eta, beta_out, q->trajectory, q->surrogate, 0.0);
+             nullptr, q->mu, q->eta, beta_out, q->trajectory, pl.sur, 0.0);
     }
   }
+  mark(2);
   // stage 2: full-data steps (eq. (99))
   if (q->momentum_reset) S.reset_momentum();
   for (int j = 0; j < q->s_max; ++j) {
     slse_dtype acc = SLSE_F64;
     if (q->precision == SLSE_PREC_MIXED && j < q->fp32_sweeps) acc = SLSE_F32;
     S.step(p->N, p->X, p->ldx, p->Y, 1, pl.st_t, acc, 1.0, nullptr, q->mu, q->eta, beta_out,
-           q->trajectory, q->surrogate, q->tol);
+           q->trajectory, pl.sur, q->tol);
   }
+  mark(3);
 }
 
-std::string graph_key(const slse_problem* p, const slse_params* q, const double* beta_out,
-                      hipStream_t st) {
-  std::string k;
+std::string graph_key(const char* tag, const slse_problem* p, const slse_params* q,
+                      const double* beta_out, const void* ws, size_t ws_bytes) {
+  std::string k(tag);
   auto add = [&k](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
   add(p, sizeof(*p));
   add(q, sizeof(*q));
   add(&beta_out, sizeof(beta_out));
-  (void)st;
+  add(&ws, sizeof(ws));
+  add(&ws_bytes, sizeof(ws_bytes));
   return k;
 }
 
-slse_status finish_report(slse_ctx* ctx, const SolvePlan& pl, const slse_params* q,
-                          slse_report* rep, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  (void)ctx;
+// Capture `body` on the context's capture stream once per key and launch the
+// instantiated graph on st.
+template <typename F>
+void launch_cached_graph(slse_ctx* ctx, const std::string& key, hipStream_t st, F&& body) {
+  auto itg = ctx->graphs.find(key);
+  if (itg == ctx->graphs.end()) {
+    hipGraph_t g = nullptr;
+    SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      body(ctx->capture_stream);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(ctx->capture_stream, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    SLSE_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    SLSE_HIP(e);
+    itg = ctx->graphs.emplace(key, ge).first;
+  }
+  SLSE_HIP(hipGraphLaunch(itg->second, st));
+}
+
+// Events of a timed call: [0] start, [1..4] phase ends (the last = the end).
+struct CallTimer {
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int n = 0;
+  CallTimer(bool on, bool phases, hipStream_t st) {
+    if (!on) return;
+    n = phases ? 5 : 2;
+    for (int i = 0; i < n; ++i) SLSE_HIP(hipEventCreate(&e[i]));
+    SLSE_HIP(hipEventRecord(e[0], st));
+  }
+  ~CallTimer() {
+    for (int i = 0; i < n; ++i)
+      if (e[i]) (void)hipEventDestroy(e[i]);
+  }
+  hipEvent_t* phase_events() { return n == 5 ? e + 1 : nullptr; }
+  hipEvent_t end() const { return n == 5 ? e[4] : e[1]; }
+  void record_end(hipStream_t st) {
+    if (n == 2) SLSE_HIP(hipEventRecord(e[1], st));
+  }
+  double ms(int a, int b) const {
+    float v = 0.f;
+    SLSE_HIP(hipEventElapsedTime(&v, e[a], e[b]));
+    return v;
+  }
+};
+
+slse_status finish_report(const SolvePlan& pl, const slse_params* q, slse_report* rep,
+                          hipStream_t st, const CallTimer& tm) {
   int flags[4] = {0, 0, 0, 0};
   int info[3] = {0, 0, 0};
   SLSE_HIP(hipMemcpyAsync(flags, pl.it.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
@@ -673,46 +873,61 @@ slse_status finish_report(slse_ctx* ctx, const SolvePlan& pl, const slse_params*
     for (int i = 0; i < q->K; ++i) s1 += q->a[i];
     rep->stage1_steps = s1;
     rep->stage2_steps = q->s_max;
-    if (q->surrogate) {
-      const int T = s1 + q->s_max;
-      std::vector<double> sur(T > 0 ? T : 1, 0.0);
-      if (T > 0) {
-        SLSE_HIP(hipMemcpy(sur.data(), q->surrogate, sizeof(double) * T, hipMemcpyDeviceToHost));
-        int taken = 0;
-        for (int t = s1; t < T; ++t) {
-          ++taken;
-          if (q->tol > 0 && sur[t] <= q->tol) break;
-        }
-        rep->stage2_steps = q->tol > 0 ? taken : q->s_max;
-        rep->surrogate0 = s1 < T ? sur[s1] : sur[0];
-        const int last = std::min(T - 1, std::max(0, s1 + rep->stage2_steps - 1));
-        rep->surrogate_final = sur[last];
+    const int T = s1 + q->s_max;
+    if (T > 0 && pl.sur) {
+      std::vector<double> sur(T, 0.0);
+      SLSE_HIP(hipMemcpy(sur.data(), pl.sur, sizeof(double) * T, hipMemcpyDeviceToHost));
+      int taken = 0;
+      for (int t = s1; t < T; ++t) {
+        ++taken;
+        if (q->tol > 0 && sur[t] <= q->tol) break;
       }
+      rep->stage2_steps = q->tol > 0 ? taken : q->s_max;
+      rep->surrogate0 = s1 < T ? sur[s1] : sur[0];
+      const int last = std::min(T - 1, std::max(0, s1 + rep->stage2_steps - 1));
+      rep->surrogate_final = sur[last];
     }
-    if (e0 && e1) {
-      float ms = 0.f;
-      SLSE_HIP(hipEventElapsedTime(&ms, e0, e1));
-      rep->ms_total = ms;
+    if (tm.n == 5) {
+      rep->ms_sketch = tm.ms(0, 1);
+      rep->ms_factor = tm.ms(1, 2);
+      rep->ms_stage1 = tm.ms(2, 3);
+      rep->ms_stage2 = tm.ms(3, 4);
+      rep->ms_total = tm.ms(0, 4);
+    } else if (tm.n == 2) {
+      rep->ms_total = tm.ms(0, 1);
     }
   }
   return status;
 }
 
+// Clear the regions of a caller workspace that must start at zero.
+void clear_borrowed(slse_ctx* ctx, hipStream_t st) {
+  for (const Arena::Buf& z : ctx->arena.ext_zero)
+    launch_fill_i32(static_cast<int*>(z.p), 0, (int64_t)(z.bytes / sizeof(int)), st);
+}
+
+void remember_preconditioner(slse_ctx* ctx, const slse_problem* p, const slse_params* q, bool ok) {
+  ctx->pre.valid = ok;
+  ctx->pre.seed = q->seed;
+  ctx->pre.kind = q->kind;
+  ctx->pre.N = p->N;
+  ctx->pre.d = p->d;
+  ctx->pre.r = q->r;
+  ctx->pre.X = p->X;
+  ctx->pre.precision = q->precision;
+}
+
 slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
-                       double* beta_out, slse_report* rep, hipStream_t st) {
+                       double* beta_out, slse_report* rep, hipStream_t st, void* ws = nullptr,
+                       size_t ws_bytes = 0) {
   check_params(p, q);
   require(beta_out != nullptr, "null beta_out");
+  BorrowScope scope{ctx->arena};
+  if (ws) ctx->arena.begin_external(ws, ws_bytes);
   ctx->arena.grew = false;
   SolvePlan pl = reserve_solve(ctx, p, q);
-  // the per-step error estimates always land somewhere: the caller's buffer or ours
-  slse_params qq = *q;
-  if (!qq.surrogate) {
-    int T = q->s_max;
-    for (int i = 0; i < q->K; ++i) T += q->a[i];
-    qq.surrogate = ctx->arena.get_t<double>("sur_hist", (size_t)T + 1);
-  }
-  q = &qq;
   if (ctx->arena.grew) ctx->drop_graphs();
+  if (ws) clear_borrowed(ctx, st);
   {
     // shapes of the stage-2 sweeps and of the large stage-1 prefixes
     const slse_dtype acc2 = q->precision == SLSE_PREC_MIXED && q->fp32_sweeps > 0 ? SLSE_F32
@@ -727,50 +942,82 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
                       base + (size_t)p->d * es, pl.lda, st);
     }
   }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (rep) {
-    SLSE_HIP(hipEventCreate(&e0));
-    SLSE_HIP(hipEventCreate(&e1));
-    SLSE_HIP(hipEventRecord(e0, st));
-  }
+  CallTimer tm(rep != nullptr, rep != nullptr && !q->use_graph, st);
   if (q->use_graph) {
-    const std::string key = graph_key(p, q, beta_out, st);
-    auto itg = ctx->graphs.find(key);
-    if (itg == ctx->graphs.end()) {
-      hipGraph_t g = nullptr;
-      SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-      try {
-        enqueue_solve(ctx, pl, p, q, beta_out, ctx->capture_stream);
-      } catch (...) {
-        hipGraph_t junk = nullptr;
-        (void)hipStreamEndCapture(ctx->capture_stream, &junk);
-        if (junk) (void)hipGraphDestroy(junk);
-        throw;
-      }
-      SLSE_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
-      hipGraphExec_t ge = nullptr;
-      SLSE_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-      SLSE_HIP(hipGraphDestroy(g));
-      itg = ctx->graphs.emplace(key, ge).first;
-    }
-    SLSE_HIP(hipGraphLaunch(itg->second, st));
+    launch_cached_graph(ctx, graph_key("solve", p, q, beta_out, ws, ws_bytes), st,
+                        [&](hipStream_t cs) { enqueue_solve(ctx, pl, p, q, beta_out, cs); });
   } else {
-    enqueue_solve(ctx, pl, p, q, beta_out, st);
+    enqueue_solve(ctx, pl, p, q, beta_out, st, tm.phase_events());
   }
-  ctx->pre.valid = true;
-  ctx->pre.seed = q->seed;
-  ctx->pre.kind = q->kind;
-  ctx->pre.N = p->N;
-  ctx->pre.d = p->d;
-  ctx->pre.r = q->r;
-  ctx->pre.X = p->X;
-  ctx->pre.precision = q->precision;
+  // a solve through a caller workspace leaves no preconditioner behind
+  remember_preconditioner(ctx, p, q, ws == nullptr);
+  tm.record_end(st);
   slse_status status = SLSE_OK;
-  if (rep) SLSE_HIP(hipEventRecord(e1, st));
-  if (rep || q->tol > 0) status = finish_report(ctx, pl, q, rep, st, e0, e1);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  if (rep || q->tol > 0) status = finish_report(pl, q, rep, st, tm);
   return status;
+}
+
+size_t solve_workspace_bytes(slse_ctx* ctx, const slse_problem* p, const slse_params* q) {
+  check_params(p, q);
+  BorrowScope scope{ctx->arena};
+  ctx->arena.begin_measure();
+  (void)reserve_solve(ctx, p, q);
+  return ctx->arena.ext_used;
+}
+
+// ---------------------------------------------------------------------------
+// IHS with a Hessian sketch drawn anew at every step (the baseline of Sec. 1).
+// ---------------------------------------------------------------------------
+void enqueue_ihs(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem* p,
+                 const slse_params* q, double* beta_out, hipStream_t st) {
+  const int d = (int)p->d;
+  const SketchShape& sk = pl.sk;
+  Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx, ErrorSink{}};
+  S.start(q->beta0, q->trajectory);
+  launch_copy_f64(S.b.beta[0], beta_out, d, st);
+  for (int t = 0; t < q->s_max; ++t) {
+    enqueue_sketch(sk, q->seed + (uint64_t)t, p->X, p->ldx, p->Y, pl.st_t, pl.A, pl.lda, pl.Ahat,
+                   pl.ldah, pl.srht, pl.ga, pl.gh, st, pl.cs);
+    enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
+    S.step(p->N, p->X, p->ldx, p->Y, 1, pl.st_t, SLSE_F64, 1.0, nullptr, 1.0, 0.0, beta_out,
+           q->trajectory, pl.sur, 0.0);
+  }
+}
+
+slse_status ihs_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q, double* beta_out,
+                     slse_report* rep, hipStream_t st) {
+  require(p && q, "null problem or params");
+  require(beta_out != nullptr, "null beta_out");
+  // the fields IHS reads, with one unused nested level of the power of 2 >= r
+  slse_params qq = *q;
+  qq.K = 1;
+  qq.m[0] = int64_t(1) << ilog2_exact(std::max<int64_t>(q->r, 1));
+  qq.a[0] = 0;
+  qq.mu = 1.0;
+  qq.eta = 0.0;
+  qq.tol = 0.0;
+  qq.momentum_reset = 0;
+  qq.fp32_sweeps = 0;
+  qq.surrogate = nullptr;
+  qq.beta_ref = nullptr;
+  qq.rel_err = qq.pred_err = nullptr;
+  check_params(p, &qq);
+  ctx->arena.grew = false;
+  SolvePlan pl = reserve_solve(ctx, p, &qq);
+  if (ctx->arena.grew) ctx->drop_graphs();
+  tune_resid_grad(ctx, pl.it, p->N, (int)p->d, pl.st_t, SLSE_F64, p->X, p->ldx, p->Y, 1, st);
+  CallTimer tm(rep != nullptr, false, st);
+  if (qq.use_graph)
+    launch_cached_graph(ctx, graph_key("ihs", p, &qq, beta_out, nullptr, 0), st,
+                        [&](hipStream_t cs) { enqueue_ihs(ctx, pl, p, &qq, beta_out, cs); });
+  else
+    enqueue_ihs(ctx, pl, p, &qq, beta_out, st);
+  ctx->pre.valid = false;
+  tm.record_end(st);
+  if (!rep) return SLSE_OK;
+  slse_params qr = qq;  // the report counts the s_max full-data steps
+  qr.K = 0;
+  return finish_report(pl, &qr, rep, st, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,10 +1025,12 @@ slse_status solve_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* 
 // then the rank-2 pass.
 // ---------------------------------------------------------------------------
 slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
-                          const double* beta_hat, const double* w, void* dX, int64_t lddx, void* dY,
-                          slse_dtype grad_t, double* lambda_out, slse_report* rep, hipStream_t st) {
+                          const double* beta_hat, const double* w, int64_t incw, void* dX,
+                          int64_t lddx, void* dY, slse_dtype grad_t, double* lambda_out,
+                          slse_report* rep, hipStream_t st) {
   check_params(p, q);
   require(beta_hat && w, "null beta_hat or w");
+  require(incw >= 0, "incw < 0");
   require(grad_t == SLSE_F32 || grad_t == SLSE_F64, "grad dtype must be F32 or F64");
   if (dX) require(lddx >= p->d, "lddx < d");
   const int d = (int)p->d;
@@ -813,7 +1062,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     ctx->pre.valid = false;
   }
   // lambda_0 = M w: one update step with g = w from a zero gradient and beta = 0
-  Stepper S{ib, d, pl.f.M, 0, 0, 0, st, ctx};
+  Stepper S{ib, d, pl.f.M, 0, 0, 0, st, ctx, ErrorSink{}};
   S.start(nullptr, nullptr);
   launch_fill_f64(zero, 0.0, d, st);
   {
@@ -825,6 +1074,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
     u.d = d;
     u.scale = 1.0;
     u.w = w;
+    u.incw = incw;
     u.M = pl.f.M;
     u.ldm = d;
     u.beta = zero;
@@ -838,7 +1088,7 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
   // s_max full-data steps on (X^T X) lambda = w: g = w + X^T (0 - X lambda)
   for (int j = 0; j < q->s_max; ++j) {
     S.step(p->N, p->X, p->ldx, nullptr, 1, p->dtype, SLSE_F64, 1.0, w, q->mu, q->eta, lambda_out,
-           nullptr, nullptr, 0.0);
+           nullptr, nullptr, 0.0, incw);
   }
   const double* lam = ib.beta[S.cur];
   if (lambda_out && q->s_max == 0) launch_copy_f64(lam, lambda_out, d, st);
@@ -878,6 +1128,10 @@ slse_status backward_impl(slse_ctx* ctx, const slse_problem* p, const slse_param
 // ---------------------------------------------------------------------------
 struct BatchPlan {
   int B = 0;
+  // bytes / entries of each pool (for the plan checks)
+  int64_t a_bytes = 0, ah_bytes = 0, m_n = 0, beta_n = 0, part_n = 0;
+  int64_t bf_ad_n = 0, bf_cp_n = 0, bf_sq_n = 0, bf_splits = 1;
+  size_t bsz_bytes = 0;  // shared SRHT workspaces
   slse_dtype t = SLSE_F32;
   std::vector<SketchShape> sk;
   std::vector<int64_t> lda, a_off, ah_off, m_off, beta_off, part_off;
@@ -1177,9 +1431,14 @@ void enqueue_batch(const BatchPlan& bp, const slse_problem* ps, const slse_param
   enqueue_batch_steps(bp, st);
 }
 
-slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const slse_params* qs,
-                         double* const* betas, slse_report* reps, hipStream_t st) {
-  BatchPlan bp;
+// The host plan of a batch: shapes, pools and offsets, SRHT jobs and
+// records, factor jobs, per-problem descriptors and the launch shape.  Every
+// buffer comes from ctx->arena (so a measuring arena plans without device
+// work); nothing is uploaded or launched here.  Returns the autotune key and
+// whether the launch shape is already known.
+std::pair<std::string, bool> plan_batched(slse_ctx* ctx, int B, const slse_problem* ps,
+                                          const slse_params* qs, double* const* betas,
+                                          BatchPlan& bp) {
   bp.B = B;
   bp.cus = ctx->num_cus;
   bp.t = ps[0].dtype;
@@ -1189,7 +1448,6 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     require(ps[b].dtype == bp.t, "every problem of a batch must share one storage dtype");
     require(ps[b].d <= 512, "batched problems need d <= 512");
   }
-  ctx->arena.grew = false;
   const size_t es = dtype_size(bp.t);
   int64_t a_bytes = 0, ah_bytes = 0, m_n = 0, beta_n = 0, max_npad = 0, max_rows = 0, max_d = 0;
   int64_t max_r = 0;
@@ -1244,6 +1502,10 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     const int es_i = (int)es;
     if ((reinterpret_cast<uintptr_t>(ps[b].X) % 16) || ((ps[b].ldx * es_i) % 16)) bp.vec = false;
   }
+  bp.a_bytes = a_bytes;
+  bp.ah_bytes = ah_bytes;
+  bp.m_n = m_n;
+  bp.beta_n = beta_n;
   bp.Apool = static_cast<char*>(ctx->arena.get("bA", (size_t)a_bytes));
   bp.Ahpool = static_cast<char*>(ctx->arena.get("bAhat", (size_t)ah_bytes));
   bp.Mpool = ctx->arena.get_t<double>("bM", (size_t)m_n);
@@ -1323,6 +1585,7 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     bp.srht_batched.assign(B, 0);
     if (!sas.empty() && zsum <= kBatchSrhtZMax) {
       char* zpool = zsum ? static_cast<char*>(ctx->arena.get("bSrhtZ", zsum)) : nullptr;
+      bp.bsz_bytes = zsum;
       for (SrhtArgs& sa : sas)
         sa.Z = srht_z_bytes(sa) ? zpool + reinterpret_cast<uintptr_t>(sa.Z) : nullptr;
       bp.srht_launches = srht_batch_plan(sas, bp.t, bp.h_srec);
@@ -1358,6 +1621,10 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     double* adp = ctx->arena.get_t<double>("bfAd", (size_t)ad_n);
     double* cpp = ctx->arena.get_t<double>("bfColp", (size_t)cp_n);
     double* pp = splits > 1 ? ctx->arena.get_t<double>("bfPart", (size_t)(splits * sq_n)) : nullptr;
+    bp.bf_ad_n = ad_n;
+    bp.bf_cp_n = cp_n;
+    bp.bf_sq_n = sq_n;
+    bp.bf_splits = splits;
     bp.h_jobs.resize(B);
     int64_t ao = 0, co = 0, so = 0;
     for (int b = 0; b < B; ++b) {
@@ -1447,7 +1714,22 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
   bp.d_prefix = ctx->arena.get_t<int>("bPrefix", (size_t)bp.T * (B + 1));
   bp.d_probs = ctx->arena.get_t<BatchProblem>("bProbs", (size_t)B);
   for (int b = 0; b < B; ++b) bp.h_probs[b].part_off = bp.part_off[b];
+  bp.part_n = part_n;
+  return {key, tuned};
+}
+
+slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const slse_params* qs,
+                         double* const* betas, slse_report* reps, hipStream_t st) {
+  BatchPlan bp;
+  ctx->arena.grew = false;
+  auto [key, tuned] = plan_batched(ctx, B, ps, qs, betas, bp);
   if (ctx->arena.grew) ctx->drop_graphs();
+  // the tables below are rewritten for this call: the previous batch's graph
+  // (on whatever stream it ran) must be done reading them
+  if (ctx->batch_busy) {
+    SLSE_HIP(hipEventSynchronize(ctx->batch_done));
+    ctx->batch_busy = false;
+  }
   SLSE_HIP(hipMemcpy(bp.d_probs, bp.h_probs.data(), sizeof(BatchProblem) * B, hipMemcpyHostToDevice));
   if (bp.batched_factor)
     SLSE_HIP(hipMemcpy(bp.d_jobs, bp.h_jobs.data(), sizeof(FactorJob) * B, hipMemcpyHostToDevice));
@@ -1514,25 +1796,10 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     add_key(&qs[b], sizeof(slse_params));
     add_key(&betas[b], sizeof(double*));
   }
-  auto itg = ctx->graphs.find(gk);
-  if (itg == ctx->graphs.end()) {
-    hipGraph_t g = nullptr;
-    SLSE_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-    try {
-      enqueue_batch(bp, ps, qs, ctx->capture_stream);
-    } catch (...) {
-      hipGraph_t junk = nullptr;
-      (void)hipStreamEndCapture(ctx->capture_stream, &junk);
-      if (junk) (void)hipGraphDestroy(junk);
-      throw;
-    }
-    SLSE_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
-    hipGraphExec_t ge = nullptr;
-    SLSE_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    SLSE_HIP(hipGraphDestroy(g));
-    itg = ctx->graphs.emplace(gk, ge).first;
-  }
-  SLSE_HIP(hipGraphLaunch(itg->second, st));
+  launch_cached_graph(ctx, gk, st, [&](hipStream_t cs) { enqueue_batch(bp, ps, qs, cs); });
+  if (!ctx->batch_done) SLSE_HIP(hipEventCreateWithFlags(&ctx->batch_done, hipEventDisableTiming));
+  SLSE_HIP(hipEventRecord(ctx->batch_done, st));
+  ctx->batch_busy = true;
   ctx->pre.valid = false;
   slse_status worst = SLSE_OK;
   if (reps) {
@@ -1556,6 +1823,111 @@ slse_status batched_impl(slse_ctx* ctx, int B, const slse_problem* ps, const sls
     }
   }
   return worst;
+}
+
+// Checks of a batch plan made on a measuring arena: every device pointer the
+// tables hold, with the extent the kernels touch, lies inside the region the
+// arena handed out for its pool; the tiles of every step cover each row once
+// and fit the partial pool; the prefix sums match the tile counts.
+void check_batch_plan(const Arena& ar, const BatchPlan& bp, const slse_problem* ps) {
+  auto region = [&](const char* name) {
+    auto it = ar.ext_bufs.find(name);
+    require(it != ar.ext_bufs.end(), std::string("plan: no region ") + name);
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(it->second.p);
+    return std::make_pair(lo, lo + it->second.bytes);
+  };
+  auto inside = [&](const void* p, int64_t bytes, const char* name, const std::string& what) {
+    const auto [lo, hi] = region(name);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    require(bytes >= 0 && a >= lo && a + (uintptr_t)bytes <= hi,
+            "plan: " + what + " outside " + name);
+  };
+  const int B = bp.B;
+  const int64_t es = (int64_t)dtype_size(bp.t);
+  for (int b = 0; b < B; ++b) {
+    const SketchShape& sk = bp.sk[b];
+    const int64_t d = ps[b].d;
+    const std::string tag = "problem " + std::to_string(b);
+    const char* A = bp.Apool + bp.a_off[b];
+    const int64_t a_len = sk.rows_A * bp.lda[b] * es;
+    inside(A, a_len, "bA", tag + " sketch rows");
+    inside(bp.Ahpool + bp.ah_off[b], sk.r * bp.lda[b] * es, "bAhat", tag + " Hessian sketch");
+    inside(bp.Mpool + bp.m_off[b], d * d * 8, "bM", tag + " M");
+    inside(bp.Bpool + bp.beta_off[b], 3 * d * 8, "bBeta", tag + " iterate ring");
+    const int64_t cap = ceil_div(std::max<int64_t>(sk.rows_A, ps[b].N), (int64_t)kBatchTileFloor);
+    require(bp.part_off[b] + cap * (d + 1) <= bp.part_n, "plan: " + tag + " partial rows");
+    inside(bp.part + bp.part_off[b], cap * (d + 1) * 8, "bPart", tag + " partial rows");
+    const BatchProblem& pr = bp.h_probs[b];
+    require(pr.d == d && pr.part_off == bp.part_off[b], "plan: " + tag + " descriptor");
+    require(pr.M == bp.Mpool + bp.m_off[b], "plan: " + tag + " descriptor M");
+    require(pr.lpr >= 1 && pr.lpr <= 64 && (pr.ch == 1 || pr.ch == 2 || pr.ch == 4),
+            "plan: " + tag + " lane shape");
+    if (bp.batched_factor) {
+      const FactorJob& j = bp.h_jobs[b];
+      inside(j.A, (j.rows - 1) * j.lda * es + d * es, "bAhat", tag + " factor input");
+      inside(j.Ad, j.rows * d * 8, "bfAd", tag + " factor Ad");
+      inside(j.colp, d * 32 * 8, "bfColp", tag + " factor panel");
+      inside(j.M, d * d * 8, "bM", tag + " factor M");
+      if (j.part) inside(j.part, bp.bf_splits * d * d * 8, "bfPart", tag + " factor partials");
+      inside(j.info, 3 * 4, "bInfo", tag + " factor info");
+    }
+    if (bp.s_off[b] >= 0) require(bp.s_off[b] + sk.n_pad <= bp.s_rows, "plan: " + tag + " SRHT maps");
+  }
+  for (const SrhtIndexJob& j : bp.h_sjobs) {
+    require(j.base + j.npad <= bp.s_rows && j.hbase + j.r <= bp.s_hat, "plan: SRHT job range");
+    inside(j.pi_sgn, j.npad * 4, "bSrhtPi", "SRHT job pi");
+    inside(j.slotA, j.npad * 4, "bSrhtSlotA", "SRHT job slotA");
+    inside(j.slotH, j.npad * 4, "bSrhtSlotH", "SRHT job slotH");
+  }
+  if (!bp.h_sjobs.empty()) inside(bp.d_sjobs, (int64_t)(bp.h_sjobs.size() * sizeof(SrhtIndexJob)),
+                                  "bSrhtJobs", "SRHT job table");
+  if (!bp.h_srec.empty()) inside(bp.d_srec, (int64_t)bp.h_srec.size(), "bSrhtRec", "SRHT records");
+  inside(bp.d_steps, (int64_t)((size_t)bp.T * B * sizeof(BatchStep)), "bSteps", "step table");
+  inside(bp.d_prefix, (int64_t)((size_t)bp.T * (B + 1) * sizeof(int)), "bPrefix", "prefix table");
+  inside(bp.d_probs, (int64_t)(B * sizeof(BatchProblem)), "bProbs", "problem table");
+  require(bp.h_steps.size() == (size_t)bp.T * B && bp.h_prefix.size() == (size_t)bp.T * (B + 1),
+          "plan: table sizes");
+  for (int t = 0; t < bp.T; ++t) {
+    int acc = 0;
+    for (int b = 0; b < B; ++b) {
+      const BatchStep& st = bp.h_steps[(size_t)t * B + b];
+      const std::string tag = "step " + std::to_string(t) + " problem " + std::to_string(b);
+      require(bp.h_prefix[(size_t)t * (B + 1) + b] == acc, "plan: " + tag + " prefix");
+      acc += st.ntiles;
+      if (st.n <= 0) {
+        require(st.ntiles == 0, "plan: " + tag + " idle problem with tiles");
+        continue;
+      }
+      const int64_t d = ps[b].d;
+      require(st.tile_rows >= 1 && st.ntiles >= 1, "plan: " + tag + " empty tiling");
+      require((int64_t)(st.ntiles - 1) * st.tile_rows < st.n &&
+                  st.n <= (int64_t)st.ntiles * st.tile_rows,
+              "plan: " + tag + " tiles do not cover the rows once");
+      const int64_t cap = ceil_div(std::max<int64_t>(bp.sk[b].rows_A, ps[b].N), (int64_t)kBatchTileFloor);
+      require(st.ntiles <= cap, "plan: " + tag + " more tiles than partial rows");
+      const char* A = bp.Apool + bp.a_off[b];
+      if (st.X != ps[b].X) {  // a stage-1 step reads a prefix of the sketch rows
+        const int64_t a_len = bp.sk[b].rows_A * bp.lda[b] * es;
+        const uintptr_t x = reinterpret_cast<uintptr_t>(st.X), y = reinterpret_cast<uintptr_t>(st.Y);
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(A);
+        require(x >= a0 && x + (uintptr_t)(((st.n - 1) * st.ldx + d) * es) <= a0 + (uintptr_t)a_len,
+                "plan: " + tag + " X outside the problem's sketch rows");
+        require(y >= a0 && y + (uintptr_t)(((st.n - 1) * st.incy + 1) * es) <= a0 + (uintptr_t)a_len,
+                "plan: " + tag + " Y outside the problem's sketch rows");
+      } else {
+        require(st.n == ps[b].N && st.Y == ps[b].Y && st.incy == 1, "plan: " + tag + " full-data step");
+      }
+      for (const double* q : {st.beta, (const double*)st.beta_prev, (const double*)st.beta_next})
+        inside(q, d * 8, "bBeta", tag + " iterate");
+      const uintptr_t r0 = reinterpret_cast<uintptr_t>(bp.Bpool + bp.beta_off[b]);
+      for (const double* q : {st.beta, (const double*)st.beta_prev, (const double*)st.beta_next})
+        require(reinterpret_cast<uintptr_t>(q) >= r0 &&
+                    reinterpret_cast<uintptr_t>(q) + (uintptr_t)(d * 8) <= r0 + (uintptr_t)(3 * d * 8),
+                "plan: " + tag + " iterate outside the problem's ring");
+    }
+    require(bp.h_prefix[(size_t)t * (B + 1) + B] == acc && bp.h_total[t] == acc,
+            "plan: step " + std::to_string(t) + " total tiles");
+  }
 }
 
 template <typename F>
@@ -1610,6 +1982,7 @@ slse_status slse_ctx_destroy(slse_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->drop_graphs();
     ctx->arena.release();
+    if (ctx->batch_done) (void)hipEventDestroy(ctx->batch_done);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return SLSE_OK;
@@ -1745,14 +2118,103 @@ slse_status slse_solve(slse_ctx* ctx, const slse_problem* p, const slse_params* 
   });
 }
 
-slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
-                          const double* beta_hat, const double* w, void* dX, int64_t lddx,
-                          void* dY, slse_dtype grad_t, double* lambda_out, slse_report* rep,
+slse_status slse_workspace_size(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                                size_t* bytes) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr && bytes != nullptr, "null ctx or bytes");
+    *bytes = solve_workspace_bytes(ctx, p, q);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_solve_ws(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                          double* beta_out, slse_report* rep, void* ws, size_t ws_bytes,
                           void* stream) {
   return guarded([&]() -> slse_status {
     require(ctx != nullptr, "null ctx");
+    require(ws != nullptr, "null workspace");
+    const size_t need = solve_workspace_bytes(ctx, p, q);
+    if (ws_bytes < need)
+      fail(SLSE_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                            std::to_string(ws_bytes));
     DeviceGuard g(ctx->device);
-    return backward_impl(ctx, p, q, beta_hat, w, dX, lddx, dY, grad_t, lambda_out, rep,
+    return solve_impl(ctx, p, q, beta_out, rep, as_stream(stream), ws, ws_bytes);
+  });
+}
+
+slse_status slse_ihs(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                     double* beta_out, slse_report* rep, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    DeviceGuard g(ctx->device);
+    return ihs_impl(ctx, p, q, beta_out, rep, as_stream(stream));
+  });
+}
+
+slse_status slse_paper_schedule(int64_t N, int64_t d, int64_t m1_factor, int64_t* m_out,
+                                int32_t cap, int32_t* K_out) {
+  return guarded([&]() -> slse_status {
+    require(m_out && K_out, "null pointer");
+    require(d >= 1 && N > d && m1_factor >= 1, "need N > d >= 1 and m1_factor >= 1");
+    require(d <= (int64_t(1) << 40) / m1_factor, "m1_factor * d too large");
+    // m_1: the power of 2 at or above m1_factor * d; m_K: the power of 2 at or below N / 2
+    const int64_t m1 = int64_t(1) << ilog2_exact(m1_factor * d);
+    int64_t mk = 1;
+    while (mk * 2 <= N / 2) mk *= 2;
+    require(N / 2 >= 1 && m1 <= mk, "empty schedule: m_1 > N/2");
+    int32_t K = 0;
+    for (int64_t v = m1; v <= mk; v *= 2) {
+      require(K < cap, "m_out too short for the schedule");
+      m_out[K++] = v;
+    }
+    *K_out = K;
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_paper_params(int64_t d, int64_t r_in, int64_t* r_out, double* mu, double* eta) {
+  return guarded([&]() -> slse_status {
+    require(r_out && mu && eta, "null pointer");
+    require(d >= 1, "d < 1");
+    const int64_t r = r_in > 0 ? r_in : 6 * d;
+    require(r > d, "need r > d");
+    const double e = (double)d / (double)r;
+    *r_out = r;
+    *eta = e;
+    *mu = (1.0 - e) * (1.0 - e);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_stage1_counts(const int64_t* m, int32_t K, int64_t d, double omega, int32_t a1,
+                               int32_t* a_out) {
+  return guarded([&]() -> slse_status {
+    require(m && a_out, "null pointer");
+    require(K >= 1 && K <= SLSE_MAX_LEVELS, "need 1 <= K <= SLSE_MAX_LEVELS");
+    require(omega > 0.0 && omega <= 1.0, "omega must lie in (0, 1]");
+    std::vector<int32_t> a(K, 0);
+    for (int i = 1; i < K; ++i) {
+      require(m[i - 1] > d, "the bound needs m_{i-1} > d");
+      const double ratio = std::sqrt((double)(m[i] - d) / (double)(m[i - 1] - d));
+      const double target = ((1.0 + omega) * ratio + 1.0) / omega;
+      int k = 1;
+      while (std::pow(3.0, k) < target) ++k;
+      a[i] = k;
+    }
+    a[0] = a1 >= 1 ? a1 : (K > 1 ? a[1] : 2);
+    for (int i = 0; i < K; ++i) a_out[i] = a[i];
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
+                          const double* beta_hat, const double* w, int64_t incw, void* dX,
+                          int64_t lddx, void* dY, slse_dtype grad_t, double* lambda_out,
+                          slse_report* rep, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx != nullptr, "null ctx");
+    DeviceGuard g(ctx->device);
+    return backward_impl(ctx, p, q, beta_hat, w, incw, dX, lddx, dY, grad_t, lambda_out, rep,
                          as_stream(stream));
   });
 }
@@ -1805,13 +2267,52 @@ slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* r
   });
 }
 
-slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int64_t k0,
-                                int64_t nk, int64_t j0, int64_t nj, double* out, void* stream) {
+slse_status slse_debug_batch_plan(int32_t B, const slse_problem* ps, const slse_params* qs,
+                                  size_t* bytes_out) {
+  return guarded([&]() -> slse_status {
+    require(B >= 1 && ps && qs, "bad batch arguments");
+    slse_ctx ctx;  // host-only: no device, no stream, the default CU count
+    BorrowScope scope{ctx.arena};
+    ctx.arena.begin_measure();
+    // result pointers are only stored in the descriptors, never read here
+    std::vector<double*> betas(B);
+    for (int b = 0; b < B; ++b)
+      betas[b] = reinterpret_cast<double*>((uintptr_t(1) << 36) + (uintptr_t)b * 4096);
+    BatchPlan bp;
+    (void)plan_batched(&ctx, B, ps, qs, betas.data(), bp);
+    build_batch_tables(bp, ps, qs, betas.data());
+    check_batch_plan(ctx.arena, bp, ps);
+    if (bytes_out) *bytes_out = ctx.arena.ext_used;
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int32_t form,
+                                int64_t k0, int64_t nk, int64_t j0, int64_t nj, double* out,
+                                void* stream) {
   return guarded([&]() -> slse_status {
     require(ctx && out, "null pointer");
     require(k0 >= 0 && j0 >= 0 && nk >= 0 && nj >= 0, "bad range");
+    require(form == 0 || form == 1, "form must be 0 or 1");
     DeviceGuard g(ctx->device);
-    launch_debug_gaussian(seed, (uint64_t)stream_id, k0, nk, j0, nj, out, as_stream(stream));
+    launch_debug_gaussian(seed, (uint64_t)stream_id, k0, nk, j0, nj, form, out, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_debug_gaussian_plan(int64_t N, int64_t d, int64_t m, int32_t bf16,
+                                     int32_t* splits) {
+  return guarded([&]() -> slse_status {
+    require(splits != nullptr, "null pointer");
+    require(N >= 1 && d >= 1 && m >= 1, "bad sizes");
+    GaussianArgs a;
+    a.t = bf16 ? SLSE_F32 : SLSE_F64;
+    a.N = N;
+    a.d = (int)d;
+    a.m = m;
+    a.bf16 = bf16 != 0;
+    gaussian_plan(a);
+    *splits = a.splits;
     return SLSE_OK;
   });
 }

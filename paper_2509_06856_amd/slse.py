@@ -68,40 +68,35 @@ def default_context(device=None):
 
 
 def paper_params(d, r=None):
-    """eta = d/r and mu = (1 - eta)^2 (Sec. 5 parameter choice), r = 6d by default."""
-    r = 6 * d if r is None else r
-    eta = d / r
-    return r, (1.0 - eta) ** 2, eta
+    """slse_paper_params: (r, mu, eta) with r = 6d unless given, eta = d/r and
+    mu = (1 - eta)^2 (Sec. 5 parameter choice)."""
+    lib = L.load()
+    r_out, mu, eta = L.c_i64(), L.c_f64(), L.c_f64()
+    L.check(lib.slse_paper_params(int(d), int(r or 0), ctypes.byref(r_out), ctypes.byref(mu),
+                                  ctypes.byref(eta)))
+    return r_out.value, mu.value, eta.value
 
 
 def auto_a(m, d, omega=0.5, a1=None):
-    """Stage-1 counts from the lower bound of Thm lowerBoundai (Sec. 4): for
-    i >= 2 the smallest integer a_i with 3^{a_i} >= ((1 + omega) r + 1) / omega,
-    r = ((m_i - d) / (m_{i-1} - d))^{1/2}.  a_1 (whose bound, Thm a1, needs the
-    first subproblem's unknown errors) is `a1`, else a_2."""
-    out = []
-    for i in range(1, len(m)):
-        if not m[i - 1] > d:
-            raise ValueError("the bound needs m_{i-1} > d")
-        target = ((1.0 + omega) * ((m[i] - d) / (m[i - 1] - d)) ** 0.5 + 1.0) / omega
-        k = 1
-        while 3.0 ** k < target:
-            k += 1
-        out.append(k)
-    first = a1 if a1 is not None else (out[0] if out else 2)
-    return [first] + out
+    """slse_stage1_counts: stage-1 counts from the lower bound of Thm
+    lowerBoundai (Sec. 4); a_1 is `a1`, else a_2."""
+    lib = L.load()
+    K = len(m)
+    marr = (L.c_i64 * K)(*[int(v) for v in m])
+    out = (L.c_i32 * K)()
+    L.check(lib.slse_stage1_counts(marr, K, int(d), float(omega), int(a1 or 0), out))
+    return list(out)
 
 
 def paper_schedule(n, d, m1_factor=8):
-    """m_1 = 8d (rounded up to a power of 2), doubling to the largest power of 2 <= N/2."""
-    m1 = 1 << max(0, (m1_factor * d - 1).bit_length())
-    mk = 1 << ((n // 2).bit_length() - 1)
-    m = []
-    v = m1
-    while v <= mk:
-        m.append(v)
-        v *= 2
-    return m
+    """slse_paper_schedule: m_1 = 8d (rounded up to a power of 2), doubling to
+    the largest power of 2 <= N/2 (Sec. 5)."""
+    lib = L.load()
+    cap = L.SLSE_MAX_LEVELS
+    out = (L.c_i64 * cap)()
+    K = L.c_i32()
+    L.check(lib.slse_paper_schedule(int(n), int(d), int(m1_factor), out, cap, ctypes.byref(K)))
+    return list(out[:K.value])
 
 
 @dataclass
@@ -121,7 +116,8 @@ class Params:
     factor: str = "chol"
     use_graph: bool = False
 
-    def to_c(self, d, beta0=None, trajectory=None, surrogate=None):
+    def to_c(self, d, beta0=None, trajectory=None, surrogate=None, beta_ref=None, rel_err=None,
+             pred_err=None):
         q = L.slse_params()
         q.kind = _KIND[self.kind]
         q.seed = self.seed
@@ -145,6 +141,9 @@ class Params:
         q.trajectory = _ptr(trajectory).value
         q.surrogate = _ptr(surrogate).value
         q.use_graph = 1 if self.use_graph else 0
+        q.beta_ref = _ptr(beta_ref).value
+        q.rel_err = _ptr(rel_err).value
+        q.pred_err = _ptr(pred_err).value
         return q
 
 
@@ -165,27 +164,83 @@ def _problem(X, Y):
     return p
 
 
-def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True):
-    """slse_solve: returns (beta, report dict[, trajectory, surrogate])."""
+def _info(st, rep):
+    return dict(status=L.STATUS_NAMES.get(st, st), stage1_steps=rep.stage1_steps,
+                stage2_steps=rep.stage2_steps, surrogate0=rep.surrogate0,
+                surrogate_final=rep.surrogate_final, ms_total=rep.ms_total,
+                ms_sketch=rep.ms_sketch, ms_factor=rep.ms_factor, ms_stage1=rep.ms_stage1,
+                ms_stage2=rep.ms_stage2)
+
+
+def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True, beta_ref=None,
+          pred_err=False, ws=None):
+    """slse_solve (slse_solve_ws when `ws`, a uint8 device tensor, is given).
+
+    Returns (beta, report dict), plus (trajectory, surrogate) when `record`,
+    plus the per-iterate errors against `beta_ref` as a dict with "rel_err"
+    (and "pred_err" = ||X (beta_t - beta_ref)||^2 when `pred_err`) when
+    `beta_ref` is given.
+    """
     ctx = ctx or default_context(X.device.index)
     p = _problem(X, Y)
     d = X.shape[1]
     T = sum(params.a) + params.s_max
     traj = torch.empty((T + 1, d), dtype=torch.float64, device=X.device) if record else None
     sur = torch.empty(max(T, 1), dtype=torch.float64, device=X.device) if record else None
-    q = params.to_c(d, beta0, traj, sur)
+    errs = None
+    if beta_ref is not None:
+        _need_cuda(beta_ref)
+        errs = {"rel_err": torch.empty(T + 1, dtype=torch.float64, device=X.device)}
+        if pred_err:
+            errs["pred_err"] = torch.empty(T + 1, dtype=torch.float64, device=X.device)
+    q = params.to_c(d, beta0, traj, sur, beta_ref, errs and errs["rel_err"],
+                    errs and errs.get("pred_err"))
     beta = torch.empty(d, dtype=torch.float64, device=X.device)
     rep = L.slse_report()
-    st = ctx.lib.slse_solve(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta),
-                            ctypes.byref(rep) if report else None, _stream(X.device))
+    rp = ctypes.byref(rep) if report else None
+    if ws is None:
+        st = ctx.lib.slse_solve(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta), rp,
+                                _stream(X.device))
+    else:
+        _need_cuda(ws)
+        st = ctx.lib.slse_solve_ws(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta), rp,
+                                   _ptr(ws), ws.numel() * ws.element_size(), _stream(X.device))
     if st not in (L.SLSE_OK, L.SLSE_ENOTCONV):
         L.check(st)
-    info = dict(status=L.STATUS_NAMES.get(st, st), stage1_steps=rep.stage1_steps,
-                stage2_steps=rep.stage2_steps, surrogate0=rep.surrogate0,
-                surrogate_final=rep.surrogate_final, ms_total=rep.ms_total)
+    out = (beta, _info(st, rep))
     if record:
-        return beta, info, traj, sur
-    return beta, info
+        out = out + (traj, sur)
+    if errs is not None:
+        out = out + (errs,)
+    return out
+
+
+def workspace_size(X, Y, params: Params, ctx=None):
+    """slse_workspace_size: device bytes slse_solve_ws needs for this solve."""
+    ctx = ctx or default_context(X.device.index)
+    p = _problem(X, Y)
+    q = params.to_c(X.shape[1])
+    n = ctypes.c_size_t()
+    L.check(ctx.lib.slse_workspace_size(ctx.h, ctypes.byref(p), ctypes.byref(q), ctypes.byref(n)))
+    return n.value
+
+
+def ihs(X, Y, kind, seed, r, steps, ctx=None, beta0=None, record=False, factor="chol",
+        precision=None, use_graph=False):
+    """slse_ihs: IHS with a Hessian sketch drawn anew at each of `steps` full-data
+    steps (key seed + t at step t).  Returns beta, or (beta, trajectory)."""
+    ctx = ctx or default_context(X.device.index)
+    p = _problem(X, Y)
+    d = X.shape[1]
+    prec = precision or ("mixed" if X.dtype == torch.float32 else "f64")
+    prm = Params(kind=kind, seed=seed, m=[], a=[], r=r, s_max=steps, precision=prec, factor=factor,
+                 use_graph=use_graph, mu=1.0, eta=0.0)
+    traj = torch.empty((steps + 1, d), dtype=torch.float64, device=X.device) if record else None
+    q = prm.to_c(d, beta0, traj)
+    beta = torch.empty(d, dtype=torch.float64, device=X.device)
+    L.check(ctx.lib.slse_ihs(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta), None,
+                             _stream(X.device)))
+    return (beta, traj) if record else beta
 
 
 def sketch_apply(X, Y, kind, seed, m, r, ctx=None, bf16=False):
@@ -248,9 +303,13 @@ def fused_resid_grad(X, Y, beta, scale=1.0, accum="f64", ctx=None, n=None):
 
 
 def backward(X, Y, params: Params, beta_hat, w, grad_dtype=None, ctx=None, want_dX=True, want_dY=True):
-    """slse_backward: returns (dX, dY, lambda)."""
+    """slse_backward: returns (dX, dY, lambda).  w is a float64 device vector of
+    any stride (read in place)."""
     ctx = ctx or default_context(X.device.index)
     p = _problem(X, Y)
+    _need_cuda(w, beta_hat)
+    if w.dtype != torch.float64 or w.dim() != 1 or w.shape[0] != X.shape[1]:
+        raise ValueError("w must be a float64 vector of length d")
     N, d = X.shape
     gd = X.dtype if grad_dtype is None else grad_dtype
     dX = torch.empty((N, d), dtype=gd, device=X.device) if want_dX else None
@@ -259,8 +318,8 @@ def backward(X, Y, params: Params, beta_hat, w, grad_dtype=None, ctx=None, want_
     q = params.to_c(d)
     rep = L.slse_report()
     L.check(ctx.lib.slse_backward(ctx.h, ctypes.byref(p), ctypes.byref(q), _ptr(beta_hat), _ptr(w),
-                                  _ptr(dX), d, _ptr(dY), _DT[gd], _ptr(lam), ctypes.byref(rep),
-                                  _stream(X.device)))
+                                  w.stride(0), _ptr(dX), d, _ptr(dY), _DT[gd], _ptr(lam),
+                                  ctypes.byref(rep), _stream(X.device)))
     return dX, dY, lam
 
 
@@ -273,12 +332,39 @@ def debug_stream(what, seed, stream_id, aux, start, count, device=0, ctx=None):
     return out[:n]
 
 
-def debug_gaussian(seed, stream_id, k0, nk, j0, nj, device=0, ctx=None):
+def debug_batch_plan(shapes, params_list, dtype=torch.float32):
+    """slse_debug_batch_plan on problems of the given (N, d) shapes (host only:
+    no tensors, fake 256-byte aligned data pointers).  Returns the device bytes
+    the batch needs, or raises the plan check's error."""
+    B = len(shapes)
+    probs = (L.slse_problem * B)()
+    qs = (L.slse_params * B)()
+    for b, (n, d) in enumerate(shapes):
+        probs[b].N, probs[b].d = n, d
+        probs[b].X = (1 << 44) + b * (1 << 36)
+        probs[b].ldx = d
+        probs[b].Y = (1 << 44) + b * (1 << 36) + (1 << 35)
+        probs[b].dtype = _DT[dtype]
+        qs[b] = params_list[b].to_c(d)
+    n = ctypes.c_size_t()
+    L.check(L.load().slse_debug_batch_plan(B, probs, qs, ctypes.byref(n)))
+    return n.value
+
+
+def debug_gaussian(seed, stream_id, k0, nk, j0, nj, device=0, ctx=None, form=0):
     ctx = ctx or default_context(device)
     out = torch.empty((max(nk, 1), max(nj, 1)), dtype=torch.float64, device=torch.device("cuda", device))
-    L.check(ctx.lib.slse_debug_gaussian(ctx.h, seed, stream_id, k0, nk, j0, nj, _ptr(out),
+    L.check(ctx.lib.slse_debug_gaussian(ctx.h, seed, stream_id, form, k0, nk, j0, nj, _ptr(out),
                                         _stream(device)))
     return out[:nk, :nj]
+
+
+def debug_gaussian_plan(N, d, m, bf16):
+    """Data-row splits of a Gaussian sketch (host only)."""
+    s = L.c_i32()
+    L.check(L.load().slse_debug_gaussian_plan(int(N), int(d), int(m), 1 if bf16 else 0,
+                                              ctypes.byref(s)))
+    return s.value
 
 
 class SLSEFunction(torch.autograd.Function):
@@ -293,8 +379,8 @@ class SLSEFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, w):
+        # w has beta's dtype (float64); any stride is read in place by the library
         X, Y, beta = ctx.saved_tensors
-        w = w.contiguous().to(torch.float64)
         dX, dY, _ = backward(X, Y, ctx.params, beta, w, want_dX=ctx.needs_input_grad[0],
                              want_dY=ctx.needs_input_grad[1])
         return dX, dY, None

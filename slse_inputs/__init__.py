@@ -4,6 +4,7 @@ arithmetic (no sketch, no solver, no reference result).
 """
 from .generators import (  # noqa: F401
     WORKLOADS,
+    batched_shapes,
     Problem,
     fingerprint,
     make_problem,

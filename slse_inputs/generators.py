@@ -8,7 +8,8 @@ regressions this library is measured on:
 
   plain_small     N=16384,  d=32,  X iid N(0,1), sigma=1e-2, float64
   illcond         N=2^20,   d=256, X = G diag(s) V^T, s log-spaced 1..1e-4,
-                  V Haar orthogonal, 5% of rows scaled x100, sigma=1e-3, float64
+                  V a seeded random orthogonal matrix (a Givens butterfly network,
+                  not Haar distributed), 5% of rows scaled x100, sigma=1e-3, float64
   mixed           N=2^22,   d=512, X = G diag(s), s log-spaced 1..1e-6,
                   sigma=1e-2, X and Y rounded to float32
   backward        N=2^20,   d=256, X iid N(0,1), sigma=1e-2, float32, plus a
@@ -201,12 +202,21 @@ def loss_vector(d, seed=None):
     return _gen(seed, (1 << 40) + 1).standard_normal(d)
 
 
-def make_batched(count=64, seed=None, n_range=(1 << 14, 1 << 18), d_choices=(16, 32, 64, 128, 256)):
-    """The batched workload: `count` independent float32 problems."""
+def batched_shapes(count=64, seed=None, n_range=(1 << 14, 1 << 18), d_choices=(16, 32, 64, 128, 256)):
+    """The (N_b, d_b) of the batched workload, drawn without generating the data."""
     seed = DATA_SEED_BASE + WORKLOADS["batched"]["k"] if seed is None else int(seed)
     head = _gen(seed, 1 << 40)
     ns = head.integers(n_range[0], n_range[1], endpoint=True, size=count)
     ds = head.choice(np.asarray(d_choices), size=count)
+    return [(int(n), int(d)) for n, d in zip(ns, ds)]
+
+
+def make_batched(count=64, seed=None, n_range=(1 << 14, 1 << 18), d_choices=(16, 32, 64, 128, 256)):
+    """The batched workload: `count` independent float32 problems."""
+    seed = DATA_SEED_BASE + WORKLOADS["batched"]["k"] if seed is None else int(seed)
+    shapes = batched_shapes(count, seed, n_range, d_choices)
+    ns = [n for n, _ in shapes]
+    ds = [d for _, d in shapes]
     probs = []
     for b in range(count):
         g = _gen(seed, b)

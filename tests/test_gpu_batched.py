@@ -85,8 +85,10 @@ def test_batched_sketch_kinds_equal_single_solves(G):
 
 
 @pytest.mark.skip(reason="the run that added concurrent per-problem set-up streams ended in a host "
-                         "segmentation fault inside this test; that code is removed and the cause "
-                         "is not established, so this case stays off the GPU")
+                         "segmentation fault inside this test; that code is removed, the batch's "
+                         "host plan for this sample checks clean under ASan and UBSan "
+                         "(tests/test_host_asan.py), but the cause is not established, so this "
+                         "case stays off the GPU")
 def test_batched_workload_sample_reaches_ols(G):
     probs = make_batched(count=6, n_range=(1 << 14, 1 << 15))
     Xs = [dev(p.X) for p in probs]
@@ -202,3 +204,34 @@ def test_batched_f32_gaussian_bf16_reaches_ols(G):
         assert infos[b]["status"] == "SLSE_OK", shape
         assert OS.rel_err(betas[b].cpu().numpy(), refs[b]) < 1e-10, shape
         assert OS.rel_err(single.cpu().numpy(), refs[b]) < 1e-10, shape
+
+
+@pytest.mark.slow
+def test_batched_workload_reaches_the_stored_oracle_solutions(G):
+    # the 64-problem batched workload (uneven N_b in [2^14, 2^18], d_b in
+    # {16..256}, Student-t(3) rows, float32) in one batched solve: every problem
+    # within 1e-10 of its FP64 oracle OLS solution, written by
+    # tests/golden/make_reference.py; heavy-tailed rows converge slowly for a
+    # few problems (up to 212 stage-2 steps), so every problem gets 240
+    import json
+    import os
+
+    from slse_inputs import fingerprint
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ref_batched.json")) as f:
+        ref = json.load(f)
+    probs = make_batched()
+    assert len(probs) == 64
+    for p, r in zip(probs, ref["problems"]):
+        assert fingerprint(p.X, p.Y) == r["fingerprint"]
+    Xs = [dev(p.X) for p in probs]
+    Ys = [dev(p.Y) for p in probs]
+    ps = [_params(G, p.n, p.d, 1005 + 100 * i, s_max=240, precision="mixed")
+          for i, p in enumerate(probs)]
+    del probs
+    betas, infos = G.solve_batched(Xs, Ys, ps)
+    torch.cuda.synchronize()
+    for b, r in enumerate(ref["problems"]):
+        assert infos[b]["status"] == "SLSE_OK", b
+        bstar = np.asarray(r["beta_star"])
+        assert OS.rel_err(betas[b].cpu().numpy(), bstar) < 1e-10, b
