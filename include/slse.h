@@ -164,6 +164,23 @@ slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const voi
                                   double scale, slse_dtype accum, double* g_out,
                                   double* rnorm2_out, void* stream);
 
+/*
+ * slse_fused_resid_grad_noalloc — slse_fused_resid_grad for callers that cannot
+ * allocate device memory (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, result and errors; the
+ * call allocates nothing: the pass's partial sums live in a fixed device array
+ * of the library (about 4.4 MB per device, held until the process ends) that
+ * slse_ctx_create locates on its device.  Limits: d <= 1024 (EINVAL above) and
+ * grids of at most 512 blocks (the tuned launch shape of slse_fused_resid_grad
+ * is reused when known and capped there).  Every call on one device uses the
+ * same array, so calls that overlap on a device (other streams, other host
+ * threads) race; the array keeps the last call's partials.
+ */
+slse_status slse_fused_resid_grad_noalloc(slse_ctx* ctx, int64_t n, int64_t d, const void* X,
+                                          int64_t ldx, const void* Y, slse_dtype storage,
+                                          const double* beta, double scale, slse_dtype accum,
+                                          double* g_out, double* rnorm2_out, void* stream);
+
 typedef struct {
   int64_t N, d;
   const void* X;

@@ -117,6 +117,8 @@ SIGNATURES = {
                             c_vp, c_i64, c_vp]),
     "slse_fused_resid_grad": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i32, c_vp, c_f64,
                                       c_i32, c_vp, c_vp, c_vp]),
+    "slse_fused_resid_grad_noalloc": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i32, c_vp,
+                                              c_f64, c_i32, c_vp, c_vp, c_vp]),
     "slse_solve": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params), c_vp,
                            ctypes.POINTER(slse_report), c_vp]),
     "slse_workspace_size": (c_i32, [c_vp, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params),

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1930,6 +1931,43 @@ void check_batch_plan(const Arena& ar, const BatchPlan& bp, const slse_problem* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free residual-gradient entry point
+// (slse_fused_resid_grad_noalloc): the group tickets, group partial rows and
+// block partial rows of one pass, for grids of up to kNoAllocBlocks blocks and
+// d <= kNoAllocMaxD.  Each device holds its own copy for the life of the
+// process, located once per device when a context is created on it; calls on
+// one device share it, so they must not overlap.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocBlocks = 512;
+constexpr int kNoAllocMaxD = 1024;
+constexpr int64_t kNoAllocLdp = 1032;  // partial row stride at d = kNoAllocMaxD: d + 1 rounded to 8
+constexpr int64_t kNoAllocGroups = kNoAllocBlocks / 32;
+constexpr size_t kNoAllocTicketBytes = 256;
+constexpr size_t kNoAllocGpartBytes = ((kNoAllocGroups * kNoAllocLdp * 8 + 255) / 256) * 256;
+constexpr size_t kNoAllocBytes =
+    kNoAllocTicketBytes + kNoAllocGpartBytes + (size_t)kNoAllocBlocks * kNoAllocLdp * 8;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// With `device` current: find this device's copy of `scratch` and clear its
+// tickets (every pass leaves them at zero again).
+void setup_noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  require(device >= 0 && device < kNoAllocMaxDevices, "device index above the scratch table");
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  SLSE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  require(p != nullptr, "no device address for the fixed scratch");
+  launch_fill_i32(static_cast<int*>(p), 0, (int64_t)(kNoAllocTicketBytes / sizeof(int)), nullptr);
+  SLSE_HIP(hipStreamSynchronize(nullptr));
+  g_scratch_ptr[device] = static_cast<char*>(p);
+}
+
 template <typename F>
 slse_status guarded(F&& f) {
   try {
@@ -1970,6 +2008,7 @@ slse_status slse_ctx_create(slse_ctx** out, int device) {
     SLSE_HIP(hipGetDeviceProperties(&prop, device));
     ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     SLSE_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    setup_noalloc_scratch(device);
     *out = ctx.release();
     return SLSE_OK;
   });
@@ -2105,6 +2144,57 @@ slse_status slse_fused_resid_grad(slse_ctx* ctx, int64_t n, int64_t d, const voi
     a.capacity_blocks = b.max_blocks;
     launch_resid_grad(pl, a, st);
     launch_finalize_grad(b.gpart, pl.groups, pl.ldp, (int)d, scale, g_out, rnorm2_out, st);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_fused_resid_grad_noalloc(slse_ctx* ctx, int64_t n, int64_t d, const void* X,
+                                          int64_t ldx, const void* Y, slse_dtype storage,
+                                          const double* beta, double scale, slse_dtype accum,
+                                          double* g_out, double* rnorm2_out, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && beta && g_out, "null pointer");
+    require(n >= 0 && d >= 1, "need n >= 0 and d >= 1");
+    if (d > kNoAllocMaxD)
+      fail(SLSE_EINVAL, "d = " + std::to_string(d) + " exceeds the fixed scratch of the "
+                        "allocation-free entry point (d <= " + std::to_string(kNoAllocMaxD) + ")");
+    require(n == 0 || X != nullptr, "null X");
+    require(ldx >= d, "ldx < d");
+    require(storage == SLSE_F32 || storage == SLSE_F64, "storage must be F32 or F64");
+    require(accum == SLSE_F32 || accum == SLSE_F64, "accum must be F32 or F64");
+    require(ctx->device >= 0 && ctx->device < kNoAllocMaxDevices, "bad device");
+    char* base = g_scratch_ptr[ctx->device];
+    require(base != nullptr, "the fixed scratch of this device is not set up");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = as_stream(stream);
+    if (n == 0) {
+      launch_fill_f64(g_out, 0.0, d, st);
+      if (rnorm2_out) launch_fill_f64(rnorm2_out, 0.0, 1, st);
+      return SLSE_OK;
+    }
+    // the launch shape of slse_fused_resid_grad (its tuned grid when known),
+    // capped at the blocks the fixed scratch holds; no tuning here
+    IterBufs b;
+    b.max_blocks = kNoAllocBlocks;
+    b.grid_blocks = std::min(kNoAllocBlocks, std::max(64, 2 * ctx->num_cus));
+    const ResidGradPlan pl = rg_plan(ctx, b, n, (int)d, storage, accum, X, ldx);
+    require(pl.blocks <= kNoAllocBlocks && pl.ldp <= kNoAllocLdp, "plan exceeds the fixed scratch");
+    ResidGradArgs a;
+    a.n = n;
+    a.d = (int)d;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.incy = 1;
+    a.storage = storage;
+    a.accum = accum;
+    a.beta = beta;
+    a.counters = reinterpret_cast<int*>(base);
+    a.gpart = reinterpret_cast<double*>(base + kNoAllocTicketBytes);
+    a.partial = reinterpret_cast<double*>(base + kNoAllocTicketBytes + kNoAllocGpartBytes);
+    a.capacity_blocks = kNoAllocBlocks;
+    launch_resid_grad(pl, a, st);
+    launch_finalize_grad(a.gpart, pl.groups, pl.ldp, (int)d, scale, g_out, rnorm2_out, st);
     return SLSE_OK;
   });
 }

@@ -302,6 +302,26 @@ def fused_resid_grad(X, Y, beta, scale=1.0, accum="f64", ctx=None, n=None):
     return g, rn
 
 
+def fused_resid_grad_noalloc(X, Y, beta, scale=1.0, accum="f64", ctx=None, n=None, g=None, rn=None):
+    """slse_fused_resid_grad_noalloc: the same pass with the library's fixed
+    scratch (no device allocation inside the call; g and rn may be passed in)."""
+    ctx = ctx or default_context(X.device.index)
+    _need_cuda(X, beta)
+    if X.stride(1) != 1 or X.dtype not in _DT:
+        raise ValueError("X must be row-major float32/float64")
+    if Y is not None and (Y.stride(0) != 1 or Y.dtype != X.dtype):
+        raise ValueError("Y must be contiguous with X's dtype")
+    n = X.shape[0] if n is None else n
+    d = X.shape[1]
+    g = torch.empty(d, dtype=torch.float64, device=X.device) if g is None else g
+    rn = torch.empty(1, dtype=torch.float64, device=X.device) if rn is None else rn
+    L.check(ctx.lib.slse_fused_resid_grad_noalloc(
+        ctx.h, n, d, _ptr(X), X.stride(0), _ptr(Y), _DT[X.dtype], _ptr(beta), scale,
+        _DT[torch.float64 if accum == "f64" else torch.float32], _ptr(g), _ptr(rn),
+        _stream(X.device)))
+    return g, rn
+
+
 def backward(X, Y, params: Params, beta_hat, w, grad_dtype=None, ctx=None, want_dX=True, want_dY=True):
     """slse_backward: returns (dX, dY, lambda).  w is a float64 device vector of
     any stride (read in place)."""
