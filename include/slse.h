@@ -399,6 +399,13 @@ slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* r
  * needs.  The betas of the problems are not read. */
 slse_status slse_debug_batch_plan(int32_t B, const slse_problem* ps, const slse_params* qs,
                                   size_t* bytes_out);
+/* Reference streams for measurement (no method arithmetic): mode 0 reads bytes of src
+ * with 16-byte non-temporal loads, one contiguous chunk per block, and writes one word per
+ * block to dst (device, >= 4 * blocks bytes); mode 1 copies src to dst (device, bytes).
+ * bytes a multiple of 16, src and dst 16-byte aligned; blocks <= 0 means one per compute
+ * unit. */
+slse_status slse_debug_bandwidth(slse_ctx* ctx, int32_t mode, const void* src, void* dst,
+                                 int64_t bytes, int32_t blocks, void* stream);
 /* Gaussian sketch entries G[k0 + a, j0 + b] (a < nk, b < nj) of stream 7 (S) or 8 (S_hat),
  * written row-major to `out` (device, FP64) as the library computes them: form 0 as the
  * FP32/FP64 sketch kernels do (FP32 Box-Muller), form 1 as the BF16 matrix-core kernel

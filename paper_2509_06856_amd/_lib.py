@@ -144,6 +144,7 @@ SIGNATURES = {
                                     c_vp]),
     "slse_debug_gaussian_plan": (c_i32, [c_i64, c_i64, c_i64, c_i32, ctypes.POINTER(c_i32)]),
     "slse_debug_batch_tiles": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "slse_debug_bandwidth": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i64, c_i32, c_vp]),
     "slse_debug_batch_plan": (c_i32, [c_i32, ctypes.POINTER(slse_problem), ctypes.POINTER(slse_params),
                                       ctypes.POINTER(ctypes.c_size_t)]),
 }

@@ -16,6 +16,7 @@ SOURCES = [
     "k_adjoint.hip",
     "k_countsketch_gauss.hip",
     "k_batched.hip",
+    "k_bandwidth.hip",
     "slse_host.hip",
 ]
 ARCH = os.environ.get("SLSE_ARCH", "gfx950")

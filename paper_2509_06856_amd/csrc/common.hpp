@@ -93,12 +93,8 @@ __device__ __forceinline__ T lane_group_sum(T v, int group) {
 
 // Block partials handed to the last block of a grid (or of a block group).
 // Each XCD has its own L2, so a plain store may sit in the writer's L2 where
-// a block on another XCD does not see it, and a device-scope fence would
-// write back and invalidate the whole L2 of every block that issues it.
-// Instead the partials are stored and loaded with device-scope (sc1) accesses,
-// which go past the non-coherent L2 level; the writer waits until its stores
-// have completed before it takes its ticket, and the last block issues its
-// loads after it has drawn the final ticket.
+// a block on another XCD does not see it.  The partials are stored and loaded
+// with agent-scope (sc1) accesses, which go past the non-coherent L2 level.
 __device__ __forceinline__ void store_device(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -107,5 +103,19 @@ __device__ __forceinline__ double load_device(const double* p) {
 }
 // wait for this thread's outstanding memory operations (stores included)
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The ticket of a hand-off.  After its partial stores, a wait for their
+// completion (wait_memory) and a block barrier, one thread per block draws a
+// ticket with release semantics at agent scope, so in the memory model the
+// block's stores happen before its ticket; the block that draws the last
+// ticket issues an agent-scope acquire fence (acquire_partials) before its
+// threads read the partials.  The release costs each block one write-back of
+// its L2's dirty lines (about 16 us per residual-gradient pass of 256 blocks).
+__device__ __forceinline__ int take_ticket(int* counter) {
+  return __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void acquire_partials() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
 
 }  // namespace slse

@@ -316,7 +316,10 @@ __global__ __launch_bounds__(kThreads) void resid_grad_kernel(
   const int group = blockIdx.x / kGroupSize;
   const int g0 = group * kGroupSize;
   const int gsz = min(kGroupSize, (int)gridDim.x - g0);
-  if (threadIdx.x == 0) s_ticket = atomicAdd(&counters[group], 1);
+  if (threadIdx.x == 0) {
+    s_ticket = take_ticket(&counters[group]);
+    if (s_ticket == gsz - 1) acquire_partials();
+  }
   __syncthreads();
   if (s_ticket == gsz - 1) {
     for (int col = threadIdx.x; col < d + 1; col += kThreads) {

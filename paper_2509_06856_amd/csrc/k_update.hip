@@ -78,7 +78,10 @@ __global__ __launch_bounds__(kThreads) void mihs_update_kernel(UpdateArgs a, int
   }
   wait_memory();
   __syncthreads();
-  if (threadIdx.x == 0) s_ticket = atomicAdd(a.sur_counter, 1);
+  if (threadIdx.x == 0) {
+    s_ticket = take_ticket(a.sur_counter);
+    if (s_ticket == (int)gridDim.x - 1) acquire_partials();
+  }
   __syncthreads();
   if (s_ticket != (int)gridDim.x - 1) return;
   // the last block: every thread sums a fixed subset of the block partials,

@@ -332,6 +332,10 @@ void launch_batched_init(const BatchProblem* probs, int B, int dmax, hipStream_t
 // --------------------------------------------------------------------------
 // Test hooks.
 // --------------------------------------------------------------------------
+// Reference streams (no method arithmetic): mode 0 reads `bytes` of src (one
+// word per block into dst[0..blocks)), mode 1 copies src to dst.
+void launch_stream_reference(int mode, const void* src, void* dst, int64_t bytes, int blocks,
+                             hipStream_t s);
 void launch_debug_stream(int what, uint64_t seed, int stream_id, int64_t aux, int64_t start,
                          int64_t count, int64_t* out, hipStream_t s);
 

@@ -2357,6 +2357,22 @@ slse_status slse_debug_batch_tiles(int32_t B, const int64_t* n, const int64_t* r
   });
 }
 
+slse_status slse_debug_bandwidth(slse_ctx* ctx, int32_t mode, const void* src, void* dst,
+                                 int64_t bytes, int32_t blocks, void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && src && dst, "null pointer");
+    require(mode == 0 || mode == 1, "mode must be 0 (read) or 1 (copy)");
+    require(bytes >= 0 && bytes % 16 == 0, "bytes must be a multiple of 16");
+    require(reinterpret_cast<uintptr_t>(src) % 16 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0,
+            "src and dst must be 16-byte aligned");
+    const int nb = blocks > 0 ? blocks : ctx->num_cus;
+    require(nb <= 65536, "too many blocks");
+    DeviceGuard g(ctx->device);
+    launch_stream_reference(mode, src, dst, bytes, nb, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
 slse_status slse_debug_batch_plan(int32_t B, const slse_problem* ps, const slse_params* qs,
                                   size_t* bytes_out) {
   return guarded([&]() -> slse_status {

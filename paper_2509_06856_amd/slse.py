@@ -379,6 +379,16 @@ def debug_gaussian(seed, stream_id, k0, nk, j0, nj, device=0, ctx=None, form=0):
     return out[:nk, :nj]
 
 
+def debug_bandwidth(mode, src, dst, nbytes=None, blocks=0, ctx=None):
+    """slse_debug_bandwidth: a plain streaming read (mode 0, one word per block
+    into dst) or copy (mode 1) of a device tensor's bytes."""
+    ctx = ctx or default_context(src.device.index)
+    _need_cuda(src, dst)
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    L.check(ctx.lib.slse_debug_bandwidth(ctx.h, mode, _ptr(src), _ptr(dst), nbytes - nbytes % 16,
+                                         blocks, _stream(src.device)))
+
+
 def debug_gaussian_plan(N, d, m, bf16):
     """Data-row splits of a Gaussian sketch (host only)."""
     s = L.c_i32()
