@@ -484,3 +484,44 @@ def test_backward_matches_oracle_adjoint(G):
     assert np.linalg.norm(lam.cpu().numpy() - rlam) / np.linalg.norm(rlam) < 1e-9
     assert np.linalg.norm(dX.cpu().numpy() - rX) / np.linalg.norm(rX) < 1e-6
     assert np.linalg.norm(dY.cpu().numpy() - rY) / np.linalg.norm(rY) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the widest rows the library takes (d = 1024, as in the paper's d = 2^10 case)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,accum", [(np.float64, "f64"), (np.float32, "f64")])
+@pytest.mark.parametrize("n,d", [(3001, 1024), (2000, 1000), (700, 1023)])
+def test_fused_resid_grad_widest_rows(G, n, d, dtype, accum):
+    g = np.random.default_rng(n + d)
+    X = g.standard_normal((n, d)).astype(dtype)
+    Y = g.standard_normal(n).astype(dtype)
+    beta = g.standard_normal(d)
+    gg, rn = G.fused_resid_grad(dev(X), dev(Y), dev(beta), scale=0.5, accum=accum)
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    ref = 0.5 * OS.full_grad(Xd, Yd, beta)
+    assert np.all(np.abs(gg.cpu().numpy() - ref) <= _grad_bound(Xd, Yd, beta, U64, 0.5))
+
+
+def test_srht_widest_rows(G):
+    N, d, m, r = 3000, 1024, [2048, 4096], 1100
+    g = np.random.default_rng(9)
+    X = g.standard_normal((N, d))
+    Y = g.standard_normal(N)
+    A, Ah, lay = G.sketch_apply(dev(X), dev(Y), "srht", 4243, m, r)
+    ref = S.srht(X, Y, 4243, m, r)
+    bound = _srht_bound(X, Y, 12, U64)
+    assert np.all(np.abs(A.cpu().numpy() - ref["A"]) <= bound)
+    assert np.all(np.abs(Ah.cpu().numpy() - ref["Ahat"]) <= bound)
+
+
+def test_solve_trajectory_widest_rows(G):
+    # d = 1024: the Gram of the 6144-row Hessian sketch inverted by Gauss-Jordan
+    # (32 pivot blocks), stage-1 steps on 8192- and 16384-row prefixes
+    prob = make_problem("plain_small", n=1 << 15, d=1024)
+    m, r = [8192, 16384], 6144
+    params = G.Params(kind="srht", seed=808, m=m, a=[2, 2], r=r, s_max=6)
+    beta, info, traj, sur = G.solve(dev(prob.X), dev(prob.Y), params, record=True)
+    _, otraj, oinfo = OS.slse_frs(prob.X, prob.Y, 808, "srht", m, [2, 2], r, s=6)
+    tr = traj.cpu().numpy()
+    for t in range(1, 11):
+        assert OS.rel_err(tr[t], otraj[t]) < 1e-12, t
