@@ -90,6 +90,15 @@ slse_status slse_ctx_create(slse_ctx** out, int device);
 slse_status slse_ctx_destroy(slse_ctx* ctx);
 /* Release the context's scratch memory and cached graphs (they regrow on use). */
 slse_status slse_ctx_trim(slse_ctx* ctx);
+/* The launch shapes the context has tuned (residual-gradient pass and batched
+ * steps, per shape) saved to / loaded from a text file, so a later process skips
+ * the timing runs.  The file names the device architecture and compute-unit
+ * count; loading a file of another part loads nothing (*loaded = 0).  Shapes only
+ * set launch parameters, never what is computed.
+ *  loaded   host, may be NULL: the number of entries taken from the file.
+ * Errors: EINVAL for null pointers or an unreadable / unwritable / malformed file. */
+slse_status slse_ctx_save_tuning(slse_ctx* ctx, const char* path);
+slse_status slse_ctx_load_tuning(slse_ctx* ctx, const char* path, int32_t* loaded);
 
 /*
  * slse_sketch_apply — apply the nested sketches S_1..S_K and the Hessian

@@ -110,6 +110,8 @@ SIGNATURES = {
     "slse_ctx_create": (c_i32, [ctypes.POINTER(c_vp), c_i32]),
     "slse_ctx_destroy": (c_i32, [c_vp]),
     "slse_ctx_trim": (c_i32, [c_vp]),
+    "slse_ctx_save_tuning": (c_i32, [c_vp, ctypes.c_char_p]),
+    "slse_ctx_load_tuning": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(c_i32)]),
     "slse_sketch_apply": (c_i32, [c_vp, c_i32, c_u64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i32,
                                   ctypes.POINTER(c_i64), c_i32, c_i64, c_vp, c_i64, c_vp, c_i64,
                                   c_i32, ctypes.POINTER(slse_sketch_layout), c_vp]),

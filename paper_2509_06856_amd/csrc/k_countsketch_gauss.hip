@@ -233,6 +233,173 @@ __global__ __launch_bounds__(kThreads) void cs_gather_kernel(int64_t nb, int par
   }
 }
 
+// Level K straight from [X|Y] together with the L levels below it (levels
+// of m_K / 2, .., m_K / 2^L buckets, when the schedule has them).  One wave
+// per family of B = 2^L level-K buckets k_q = f + q mf (q < B, mf = m_K / B):
+// by h(j) mod m_i, the rows of the whole family land in bucket f of level
+// K - L.  The wave gathers the family's rows (about 2B of them, eight loads in
+// flight), keeps the B bucket sums of a chunk of 64 VEC columns in registers
+// and writes them with their halvings: level K - l receives the B / 2^l sums
+// A_{K-l}[f + q mf] = A_{K-l+1}[f + q mf] + A_{K-l+1}[f + (q + B / 2^l) mf],
+// the fold fold(A)[k] = A[k] + A[k + m/2] of the smaller levels.
+struct FamilyTargets {
+  int64_t off[4];  // off[l]: first row (in A) of level K - l, l = 0..L
+};
+
+template <typename T, int VEC, int L>
+__global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
+    int64_t mf, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y,
+    const int* __restrict__ off, const int* __restrict__ list, T* __restrict__ A, int64_t lda,
+    FamilyTargets tg, bool a_vec) {
+  constexpr int B = 1 << L;
+  const int lane = threadIdx.x & 63;
+  for (int64_t f = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); f < mf;
+       f += (int64_t)gridDim.x * kWaves) {
+    // lane q < B: the list range of bucket k_q, and its start in the family's entries
+    int o0 = 0, len = 0;
+    if (lane < B) {
+      const int64_t k = f + (int64_t)lane * mf;
+      o0 = off[k];
+      len = off[k + 1] - o0;
+    }
+    // every lane keeps each bucket's list offset and first entry index
+    int oo[B], st[B];
+    int E = 0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      oo[q] = __shfl(o0, q, 64);
+      st[q] = E;
+      E += __shfl(len, q, 64);
+    }
+    for (int c0 = 0; c0 < d; c0 += 64 * VEC) {
+      const int col = c0 + lane * VEC;
+      const bool whole = col + VEC <= d;
+      T acc[B][VEC];
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[q][v] = (T)0;
+      for (int r0 = 0; r0 < E; r0 += 64) {
+        // lane e of this round holds entry r0 + e and its bucket
+        const int e = r0 + lane;
+        int qe = 0, oq = oo[0], sq = st[0];
+#pragma unroll
+        for (int q = 1; q < B; ++q)
+          if (e >= st[q]) {
+            qe = q;
+            oq = oo[q];
+            sq = st[q];
+          }
+        const int ent = e < E ? list[oq + (e - sq)] : 0;
+        const int n = min(64, E - r0);
+        for (int u0 = 0; u0 < n; u0 += 8) {
+          T x[8][VEC];
+          int qu[8];
+          int neg = 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const bool ok = u0 + u < n;
+            const int eu = __shfl(ent, (u0 + u) & 63, 64);
+            qu[u] = ok ? __shfl(qe, (u0 + u) & 63, 64) : -1;
+            const int64_t j = eu < 0 ? (int64_t)~eu : (int64_t)eu;
+            neg |= (eu < 0 ? 1 : 0) << u;
+            const T* xr = X + j * ldx + col;
+            if (ok && whole) {
+              if constexpr (VEC > 1) {
+                typedef T V __attribute__((ext_vector_type(VEC)));
+                const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) x[u][v] = t[v];
+              } else {
+                x[u][0] = __builtin_nontemporal_load(xr);
+              }
+            } else {
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) x[u][v] = (ok && col + v < d) ? xr[v] : (T)0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+#pragma unroll
+              for (int v = 0; v < VEC; ++v)
+                if (qu[u] == q) acc[q][v] += ((neg >> u) & 1) ? -x[u][v] : x[u][v];
+        }
+      }
+      // level K, then the halvings down to level K - L
+#pragma unroll
+      for (int l = 0; l <= L; ++l) {
+        const int nq = B >> l;
+        if (l > 0) {
+#pragma unroll
+          for (int q = 0; q < (B >> 1); ++q)
+            if (q < nq)
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) acc[q][v] += acc[q + nq][v];
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          if (q >= nq) continue;
+          T* orow = A + (tg.off[l] + f + (int64_t)q * mf) * lda;
+          if constexpr (VEC > 1) {
+            if (a_vec && whole) {
+              typedef T V __attribute__((ext_vector_type(VEC)));
+              V t;
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) t[v] = acc[q][v];
+              *reinterpret_cast<V*>(orow + col) = t;
+              continue;
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            if (col + v < d) orow[col + v] = acc[q][v];
+        }
+      }
+    }
+    // the Y column: lanes split the entries, then one wave sum per bucket in lane order
+    T ys[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) ys[q] = (T)0;
+    for (int e = lane; e < E; e += 64) {
+      int qe = 0, oq = oo[0], sq = st[0];
+#pragma unroll
+      for (int q = 1; q < B; ++q)
+        if (e >= st[q]) {
+          qe = q;
+          oq = oo[q];
+          sq = st[q];
+        }
+      const int ent = list[oq + (e - sq)];
+      const int64_t j = ent < 0 ? (int64_t)~ent : (int64_t)ent;
+      const T y = Y[j];
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (qe == q) ys[q] += ent < 0 ? -y : y;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      for (int m = 32; m > 0; m >>= 1) ys[q] += __shfl_xor(ys[q], m, 64);
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+      const int nq = B >> l;
+      if (l > 0) {
+#pragma unroll
+        for (int q = 0; q < (B >> 1); ++q)
+          if (q < nq) ys[q] += ys[q + nq];
+      }
+      if (lane < nq) {
+        T yv = ys[0];
+#pragma unroll
+        for (int q = 1; q < B; ++q)
+          if (lane == q) yv = ys[q];
+        A[(tg.off[l] + f + (int64_t)lane * mf) * lda + d] = yv;
+      }
+    }
+  }
+}
+
 // dst[b] = sum over the parts of bucket b in part order
 template <typename T>
 __global__ void cs_parts_kernel(const T* __restrict__ part, int parts, int64_t nb, int cols,
@@ -802,12 +969,49 @@ void gather(int64_t nb, int parts, const CountSketchArgs& a, const int* off, con
   SLSE_LAUNCH_CHECK();
 }
 
-// Levels K-2 .. 0 from level K-1 (stored at row offK of A; level i sits just
-// before level i + 1).  Each pass folds a source level down as far as kFoldMax
-// rows per group allow and writes every level on the way; a step between two
-// levels wider than that falls back to the one-level fold.
+// Level K (at row offK of A) and the L levels below it, one wave per family.
 template <typename T>
-void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, hipStream_t s) {
+void gather_family(int L, const CountSketchArgs& a, const int* off, const int* list, T* A,
+                   int64_t offK, hipStream_t s) {
+  const int64_t mK = a.m[a.K - 1];
+  const int64_t mf = mK >> L;
+  FamilyTargets tg;
+  int64_t o = offK;
+  for (int l = 0; l < 4; ++l) tg.off[l] = -1;
+  for (int l = 0; l <= L; ++l) {
+    tg.off[l] = o;
+    if (l < L) o -= a.m[a.K - 2 - l];
+  }
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(mf, kWaves), 65536));
+  const T* X = static_cast<const T*>(a.X);
+  const T* Y = static_cast<const T*>(a.Y);
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((a.ldx * (int64_t)sizeof(T)) % 16 == 0);
+  const bool a_vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((a.lda * (int64_t)sizeof(T)) % 16 == 0);
+#define SLSE_FAMILY(VV, LL)                                                                   \
+  cs_gather_family_kernel<T, VV, LL><<<blocks, kThreads, 0, s>>>(mf, a.d, X, a.ldx, Y, off, list, \
+                                                                 A, a.lda, tg, a_vec)
+  if (vec) {
+    if (L == 3) SLSE_FAMILY(V, 3);
+    else if (L == 2) SLSE_FAMILY(V, 2);
+    else if (L == 1) SLSE_FAMILY(V, 1);
+    else SLSE_FAMILY(V, 0);
+  } else {
+    if (L == 3) SLSE_FAMILY(1, 3);
+    else if (L == 2) SLSE_FAMILY(1, 2);
+    else if (L == 1) SLSE_FAMILY(1, 1);
+    else SLSE_FAMILY(1, 0);
+  }
+#undef SLSE_FAMILY
+  SLSE_LAUNCH_CHECK();
+}
+
+// Levels top-1 .. 0 from level `top` (level i sits just before level i + 1
+// in A, level K-1 at row offK).  Each pass folds a source level down as far as
+// kFoldMax rows per group allow and writes every level on the way; a step
+// between two levels wider than that falls back to the one-level fold.
+template <typename T>
+void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, int top, hipStream_t s) {
   std::vector<int64_t> off(a.K);
   off[a.K - 1] = offK;
   for (int i = a.K - 2; i >= 0; --i) off[i] = off[i + 1] - a.m[i];
@@ -815,7 +1019,7 @@ void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, hipStream_t s) {
   constexpr int CT = 128 / (int)sizeof(T);
   const int n_ct = (int)ceil_div(cols, CT);
   const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((a.lda * (int64_t)sizeof(T)) % 16 == 0);
-  int S = a.K - 1;
+  int S = top;
   while (S > 0) {
     int Tl = S;
     while (Tl > 0 && a.m[S] / a.m[Tl - 1] <= kFoldMax) --Tl;
@@ -873,9 +1077,13 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   cs_fill_kernel<<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.listK,
                                          sc.cntH, sc.listH);
   SLSE_LAUNCH_CHECK();
-  // 4. gathers: the largest level straight into A, S_hat through its parts
+  // 4. gathers: the largest level and up to three below it straight into A,
+  //    S_hat through its parts
   const int64_t offK = rows_A - mK;
-  gather<T>(mK, 1, a, sc.offK, sc.listK, A + offK * a.lda, a.lda, s);
+  // fuse the levels below K that halve it step by step (up to three)
+  int L = 0;
+  while (L < 3 && L < a.K - 1 && a.m[a.K - 2 - L] == (mK >> (L + 1))) ++L;
+  gather_family<T>(L, a, sc.offK, sc.listK, A, offK, s);
   const int parts = cs_hat_parts(a.N, a.r);
   if (parts == 1) {
     gather<T>(a.r, 1, a, sc.offH, sc.listH, Ah, a.ldah, s);
@@ -888,7 +1096,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
     SLSE_LAUNCH_CHECK();
   }
   // 5. smaller levels by folding, several levels per pass
-  fold_levels<T>(a, A, offK, s);
+  fold_levels<T>(a, A, offK, a.K - 1 - L, s);
 }
 
 // BF16 path scratch: the staged tiles (shared by the two sketches of one

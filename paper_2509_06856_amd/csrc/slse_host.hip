@@ -147,8 +147,10 @@ struct slse_ctx {
   hipEvent_t batch_done = nullptr;
   bool batch_busy = false;
   // autotuned (grid blocks, lanes per row) of the residual-gradient pass, keyed
-  // by storage / accumulation / d / vector width / log2(rows)
+  // by storage / accumulation / d / vector width / log2(rows), and (grid,
+  // tiles per block) of batched steps, keyed by the batch shape
   std::map<std::string, std::pair<int, int>> rg_tune;
+  std::string arch;  // gcnArchName of the device and its compute-unit count
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
@@ -2007,6 +2009,7 @@ slse_status slse_ctx_create(slse_ctx** out, int device) {
     hipDeviceProp_t prop;
     SLSE_HIP(hipGetDeviceProperties(&prop, device));
     ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->arch = std::string(prop.gcnArchName) + "/" + std::to_string(ctx->num_cus);
     SLSE_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     setup_noalloc_scratch(device);
     *out = ctx.release();
@@ -2318,6 +2321,51 @@ slse_status slse_solve_batched(slse_ctx* ctx, int32_t B, const slse_problem* ps,
     if (B == 0) return SLSE_OK;
     DeviceGuard g(ctx->device);
     return batched_impl(ctx, B, ps, qs, betas, reps, as_stream(stream));
+  });
+}
+
+slse_status slse_ctx_save_tuning(slse_ctx* ctx, const char* path) {
+  return guarded([&]() -> slse_status {
+    require(ctx && path, "null pointer");
+    FILE* f = std::fopen(path, "w");
+    if (!f) fail(SLSE_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "libslse-tuning 1 %s\n", ctx->arch.c_str());
+    for (const auto& kv : ctx->rg_tune)
+      std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) fail(SLSE_EINVAL, std::string("cannot write ") + path);
+    return SLSE_OK;
+  });
+}
+
+slse_status slse_ctx_load_tuning(slse_ctx* ctx, const char* path, int32_t* loaded) {
+  return guarded([&]() -> slse_status {
+    require(ctx && path, "null pointer");
+    if (loaded) *loaded = 0;
+    FILE* f = std::fopen(path, "r");
+    if (!f) fail(SLSE_EINVAL, std::string("cannot read ") + path);
+    char head[64] = {0}, arch[128] = {0};
+    int version = 0;
+    const bool header = std::fscanf(f, "%63s %d %127s", head, &version, arch) == 3 &&
+                        std::string(head) == "libslse-tuning" && version == 1;
+    if (!header) {
+      std::fclose(f);
+      fail(SLSE_EINVAL, std::string("not a tuning file: ") + path);
+    }
+    int n = 0;
+    if (ctx->arch == arch) {  // entries of another part or CU count are ignored
+      char key[256];
+      int a = 0, b = 0;
+      while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3) {
+        if (a > 0 && b > 0) {
+          ctx->rg_tune[key] = {a, b};
+          ++n;
+        }
+      }
+    }
+    std::fclose(f);
+    if (loaded) *loaded = n;
+    return SLSE_OK;
   });
 }
 

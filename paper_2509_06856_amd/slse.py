@@ -50,6 +50,17 @@ class Context:
     def trim(self):
         L.check(self.lib.slse_ctx_trim(self.h))
 
+    def save_tuning(self, path):
+        """slse_ctx_save_tuning: the tuned launch shapes to a text file."""
+        L.check(self.lib.slse_ctx_save_tuning(self.h, str(path).encode()))
+
+    def load_tuning(self, path):
+        """slse_ctx_load_tuning: returns the number of entries taken (0 for a file
+        written on another part)."""
+        n = L.c_i32()
+        L.check(self.lib.slse_ctx_load_tuning(self.h, str(path).encode(), ctypes.byref(n)))
+        return n.value
+
     def __del__(self):
         try:
             self.close()

@@ -207,3 +207,30 @@ def test_batched_calls_back_to_back_on_a_side_stream(G):
         singles = (A, B)[i % 2][3]
         for b, ref in zip(betas, singles):
             assert OS.rel_err(b.cpu().numpy(), ref) < 1e-13, i
+
+
+def test_tuned_launch_shapes_persist_across_contexts(G, tmp_path):
+    p = make_problem("plain_small", n=1 << 15, d=64)
+    X, Y = dev(p.X), dev(p.Y)
+    m = G.paper_schedule(1 << 15, 64)
+    prm = G.Params(kind="srht", seed=21, m=m, a=[2] * len(m), r=384, s_max=8)
+    c1 = G.Context(0)
+    b1, _ = G.solve(X, Y, prm, ctx=c1)
+    path = tmp_path / "tune.txt"
+    c1.save_tuning(path)
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("libslse-tuning 1 gfx") and len(lines) > 1
+    c2 = G.Context(0)
+    assert c2.load_tuning(path) == len(lines) - 1
+    b2, _ = G.solve(X, Y, prm, ctx=c2)
+    assert torch.equal(b1, b2)  # same shapes, same kernels: the same result
+    other = tmp_path / "other.txt"
+    other.write_text("libslse-tuning 1 gfx000/1\n" + "\n".join(lines[1:]) + "\n")
+    assert G.Context(0).load_tuning(other) == 0
+    from paper_2509_06856_amd import _lib as L
+    bad = tmp_path / "bad.txt"
+    bad.write_text("something else\n")
+    with pytest.raises(L.SlseError):
+        c2.load_tuning(bad)
+    c1.close()
+    c2.close()
