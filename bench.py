@@ -159,10 +159,18 @@ def measure_kernels(G, torch, X, Y, m, r, seed):
         mg = [r]
         t = time_calls(torch, lambda: G.sketch_apply(X, Y, "gaussian", seed, mg, r, bf16=True), reps=2)
         flops = 2.0 * (mg[-1] + r) * N * (d + 1)
+        # the floor the VALU work sets: the same entries of G generated alone
+        sink = torch.empty(256 * 1024, dtype=torch.int32, device=X.device)
+        t_gen = time_calls(torch, lambda: [G.debug_gaussian_generate(seed, st, rows, N, 1024, sink=sink)
+                                           for st, rows in ((7, mg[-1]), (8, r))], reps=2)
         out["gaussian_bf16"] = {"ms": t * 1e3, "TFLOPs": flops / t / 1e12,
                                 "frac_of_peak": flops / t / 1e12 / BF16_PEAK_TFLOPS,
                                 "flops": flops, "sketch_rows": mg[-1] + r,
-                                "note": "G generated on the fly (Philox + Box-Muller), BF16 MFMA, FP32 accumulation"}
+                                "valu_floor_ms": t_gen * 1e3,
+                                "time_over_valu_floor": t / t_gen,
+                                "note": "G generated on the fly (Philox + Box-Muller), BF16 MFMA, FP32 "
+                                        "accumulation; valu_floor_ms: the same entries of G generated "
+                                        "alone (slse_debug_gaussian_generate)"}
     return out
 
 

@@ -422,6 +422,13 @@ slse_status slse_debug_bandwidth(slse_ctx* ctx, int32_t mode, const void* src, v
 slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id, int32_t form,
                                 int64_t k0, int64_t nk, int64_t j0, int64_t nj, double* out,
                                 void* stream);
+/* Reference for measurement: the matrix-core Gaussian sketch's generation of the m x N
+ * entries of G alone (Philox block, Box-Muller, BF16 rounding), with no data read and no
+ * product formed; one checksum word per thread into sink (device, >= 256 * blocks words).
+ * Its time is the floor that generating G sets for a sketch of m rows of N data rows. */
+slse_status slse_debug_gaussian_generate(slse_ctx* ctx, uint64_t seed, int32_t stream_id,
+                                        int64_t m, int64_t N, int32_t blocks, uint32_t* sink,
+                                        void* stream);
 /* Data-row splits the Gaussian sketch of N x (d+1) data into m sketch rows uses (host only):
  * bf16 = 1 for the matrix-core form on F32 data, 0 for the FP32/FP64 form.  Each split sums
  * its own contiguous range of data rows; the ranges are added in split order. */

@@ -144,6 +144,7 @@ SIGNATURES = {
     "slse_debug_stream": (c_i32, [c_vp, c_i32, c_u64, c_i32, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "slse_debug_gaussian": (c_i32, [c_vp, c_u64, c_i32, c_i32, c_i64, c_i64, c_i64, c_i64, c_vp,
                                     c_vp]),
+    "slse_debug_gaussian_generate": (c_i32, [c_vp, c_u64, c_i32, c_i64, c_i64, c_i32, c_vp, c_vp]),
     "slse_debug_gaussian_plan": (c_i32, [c_i64, c_i64, c_i64, c_i32, ctypes.POINTER(c_i32)]),
     "slse_debug_batch_tiles": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
     "slse_debug_bandwidth": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i64, c_i32, c_vp]),

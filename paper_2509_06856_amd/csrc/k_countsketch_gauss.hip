@@ -874,6 +874,26 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
       }
 }
 
+// Reference for measurement: the matrix-core kernel's generation of G alone
+// (Philox block -> eight Box-Muller values -> BF16) for entries k < m, j < N,
+// folded into one checksum word per thread; no data is read and no product
+// formed.  Its time is the floor the VALU work of the Gaussian sketch sets.
+__global__ __launch_bounds__(256) void gauss_generate_kernel(uint64_t seed, uint64_t stream,
+                                                             int64_t kblocks, int64_t N,
+                                                             unsigned* __restrict__ sink) {
+  const int64_t total = kblocks * N;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned acc = 0;
+  for (int64_t e = tid; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t kb = e / N, j = e % N;
+    float z[8];
+    box_muller8_fast(seed, stream, (uint64_t)j, (uint64_t)kb, z);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += __builtin_bit_cast(uint16_t, to_bf16_rne(z[q]));
+  }
+  sink[tid] = acc;
+}
+
 // form 0: the entries of the VALU kernels; form 1: those of the matrix-core
 // kernel (hardware transcendentals, then rounded to BF16 as its operands are)
 __global__ void debug_gauss_kernel(uint64_t seed, uint64_t stream, int64_t k0, int64_t nk,
@@ -1192,6 +1212,12 @@ void launch_gaussian(const GaussianArgs& a, hipStream_t s) {
     gaussian_t<float, float>(a, s);
   else
     fail(SLSE_EUNSUPPORTED, "gaussian: dtype");
+}
+
+void launch_gauss_generate(uint64_t seed, uint64_t stream_id, int64_t m, int64_t N, int blocks,
+                           unsigned* sink, hipStream_t s) {
+  gauss_generate_kernel<<<blocks, 256, 0, s>>>(seed, stream_id, ceil_div(m, 8), N, sink);
+  SLSE_LAUNCH_CHECK();
 }
 
 void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_t nk, int64_t j0,

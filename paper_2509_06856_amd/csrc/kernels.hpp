@@ -218,6 +218,10 @@ void gaussian_plan(GaussianArgs& a);
 void launch_gaussian(const GaussianArgs& a, hipStream_t s);
 void launch_debug_gaussian(uint64_t seed, uint64_t stream_id, int64_t k0, int64_t nk, int64_t j0,
                            int64_t nj, int form, double* out, hipStream_t s);
+// the matrix-core form's generation of m x N entries of G alone (one checksum
+// word per thread of `blocks` x 256 into sink)
+void launch_gauss_generate(uint64_t seed, uint64_t stream_id, int64_t m, int64_t N, int blocks,
+                           unsigned* sink, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Dense FP64 helpers for the factorization.

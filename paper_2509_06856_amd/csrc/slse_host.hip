@@ -2454,6 +2454,18 @@ slse_status slse_debug_gaussian(slse_ctx* ctx, uint64_t seed, int32_t stream_id,
   });
 }
 
+slse_status slse_debug_gaussian_generate(slse_ctx* ctx, uint64_t seed, int32_t stream_id,
+                                        int64_t m, int64_t N, int32_t blocks, uint32_t* sink,
+                                        void* stream) {
+  return guarded([&]() -> slse_status {
+    require(ctx && sink, "null pointer");
+    require(m >= 1 && N >= 1 && blocks >= 1 && blocks <= 65536, "bad sizes");
+    DeviceGuard g(ctx->device);
+    launch_gauss_generate(seed, (uint64_t)stream_id, m, N, blocks, sink, as_stream(stream));
+    return SLSE_OK;
+  });
+}
+
 slse_status slse_debug_gaussian_plan(int64_t N, int64_t d, int64_t m, int32_t bf16,
                                      int32_t* splits) {
   return guarded([&]() -> slse_status {

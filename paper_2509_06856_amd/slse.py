@@ -400,6 +400,16 @@ def debug_bandwidth(mode, src, dst, nbytes=None, blocks=0, ctx=None):
                                          blocks, _stream(src.device)))
 
 
+def debug_gaussian_generate(seed, stream_id, m, N, blocks=1024, device=0, ctx=None, sink=None):
+    """slse_debug_gaussian_generate: generate the m x N entries of G alone."""
+    ctx = ctx or default_context(device)
+    sink = torch.empty(256 * blocks, dtype=torch.int32, device=torch.device("cuda", device)) \
+        if sink is None else sink
+    L.check(ctx.lib.slse_debug_gaussian_generate(ctx.h, seed, stream_id, int(m), int(N), blocks,
+                                                 _ptr(sink), _stream(device)))
+    return sink
+
+
 def debug_gaussian_plan(N, d, m, bf16):
     """Data-row splits of a Gaussian sketch (host only)."""
     s = L.c_i32()
