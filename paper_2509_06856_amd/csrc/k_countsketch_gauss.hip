@@ -881,15 +881,23 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
 __global__ __launch_bounds__(256) void gauss_generate_kernel(uint64_t seed, uint64_t stream,
                                                              int64_t kblocks, int64_t N,
                                                              unsigned* __restrict__ sink) {
-  const int64_t total = kblocks * N;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // entry e = kb N + j, walked with a carry instead of a division per entry
+  int64_t kb = tid / N, j = tid % N;
+  const int64_t skb = stride / N, sj = stride % N;
   unsigned acc = 0;
-  for (int64_t e = tid; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t kb = e / N, j = e % N;
+  while (kb < kblocks) {
     float z[8];
     box_muller8_fast(seed, stream, (uint64_t)j, (uint64_t)kb, z);
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc += __builtin_bit_cast(uint16_t, to_bf16_rne(z[q]));
+    kb += skb;
+    j += sj;
+    if (j >= N) {
+      j -= N;
+      ++kb;
+    }
   }
   sink[tid] = acc;
 }
