@@ -557,19 +557,22 @@ __device__ __forceinline__ void box_muller8(uint64_t seed, uint64_t stream, uint
 // Box-Muller with the hardware transcendentals (v_log_f32 is log2, v_sin_f32
 // and v_cos_f32 take revolutions): about 1e-6 relative, far below the BF16
 // rounding the matrix-core path applies to G afterwards.
-__device__ __forceinline__ void box_muller8_fast(uint64_t seed, uint64_t stream, uint64_t j,
-                                                 uint64_t kblk, float (&z)[8]) {
-  const rng::Words w = rng::philox(j, kblk, 0, 0, seed, stream);
+__device__ __forceinline__ void box_muller8_words(const uint64_t (&w)[4], float (&z)[8]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint32_t lo = (uint32_t)(w.w[q] & 0xffffffffu);
-    const uint32_t hi = (uint32_t)(w.w[q] >> 32);
+    const uint32_t lo = (uint32_t)(w[q] & 0xffffffffu);
+    const uint32_t hi = (uint32_t)(w[q] >> 32);
     const float u1 = fmaf((float)lo, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
     const float u2 = fmaf((float)hi, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
     const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
     z[2 * q] = rad * __builtin_amdgcn_cosf(u2);
     z[2 * q + 1] = rad * __builtin_amdgcn_sinf(u2);
   }
+}
+__device__ __forceinline__ void box_muller8_fast(uint64_t seed, uint64_t stream, uint64_t j,
+                                                 uint64_t kblk, float (&z)[8]) {
+  const rng::Words w = rng::philox(j, kblk, 0, 0, seed, stream);
+  box_muller8_words(w.w, z);
 }
 
 constexpr int kGT = 64;   // tile (sketch rows and columns)
@@ -663,51 +666,55 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 
 // ---------------------------------------------------------------------------
 // Gaussian sketch on the matrix cores: G and [X|Y] rounded to BF16 (nearest
-// even), products accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  Block
-// tile kMT sketch rows x kNT columns: waves in a kRG x kCG grid, each owning
-// 32 sketch rows and kNQ column tiles of 32 (kNQ accumulators of 32 x 32);
-// 16 kCG data rows per step.  G is generated into LDS by the block (one
-// Philox block per thread per step).  [X|Y] is converted to BF16 once, by a
-// stage pass, into tiles laid out as the kernel's LDS tile (transposed, so
-// that every lane reads its 8 consecutive k as one 16-byte load); each step
-// copies its tile into LDS while it generates G.  Every block of columns
-// generates G again (about 15 ms per 3072 x 2^22 entries), so one block
-// covers every column of [X|Y] when d < 640; the waves need four per SIMD
-// to hide their latencies.
-// Lane layout (checked by an in-bounds probe): lane l holds A[l%32][8(l/32)+j]
-// and B[8(l/32)+j][l%32], j < 8; accumulator r of lane l is
-// C[(r%4) + 8(r/4) + 4(l/32)][l%32].
+// even), products accumulated in FP32 by v_mfma_f32_16x16x32_bf16.  A block
+// computes kMT sketch rows x kNT columns over one split of the data rows, in
+// steps of kKT data rows.  [X|Y] is converted to BF16 once, by a stage pass,
+// into tiles laid out column by column (every lane reads its 8 consecutive k
+// as one 16-byte load).
+//
+// The generation of G (Philox4x64-10 and Box-Muller, about 350 VALU
+// instructions per 8 entries) is the largest cost, so the waves specialise:
+// on every SIMD two waves generate G and two run the MFMAs.  A wave issues
+// in order, so a wave that did both would leave the matrix core idle while it
+// generates and the VALU idle while it multiplies; with one job per wave the
+// SIMD issues the MFMAs of some waves between the VALU instructions of the
+// others.  During step s the generator waves write the G tile of step s + 1
+// into the second of two LDS buffers while the MFMA waves multiply the tiles
+// of step s and copy the [X|Y] tile of step s + 1 into the second [X|Y]
+// buffer (global_load_lds: straight into LDS, no registers); one barrier per
+// step swaps the buffers.  The LDS tiles are unpadded: the 16-byte chunk q of
+// row c sits at chunk q ^ (c % 8) of that row, so the lanes that read one
+// chunk of consecutive rows hit 8 distinct 16-byte slots of every 128-byte
+// line (no bank conflicts), and a wave-wide copy still fills 1 KB of LDS in
+// order (each lane picks the source chunk of its slot).  Every block of
+// columns generates G again, so one block covers every column of [X|Y] when
+// d < kNT.
+// Lane layout of v_mfma_f32_16x16x32_bf16 (pinned by the element-wise parity
+// tests): lane l holds A[l%16][8(l/16)+j] and B[8(l/16)+j][l%16], j < 8;
+// accumulator r of lane l is C[4(l/16)+r][l%16].
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// 4 x 4 waves (128 sketch rows x 640 columns: every column of a d <= 639
-// problem in one block, so G is generated once; 64 data rows per step)
-// measured best for two 3072-row sketches of 2^22 x 513 with staged tiles:
-// 77 ms, against 84 ms for 8 x 2 (256 x 320) and 119 ms for 16 x 1 (512 x 160)
-#ifndef SLSE_GAUSS_RG
-#define SLSE_GAUSS_RG 4
-#endif
-#ifndef SLSE_GAUSS_CG
-#define SLSE_GAUSS_CG 4
-#endif
-#ifndef SLSE_GAUSS_NQ
-#define SLSE_GAUSS_NQ 5
-#endif
-#ifndef SLSE_GAUSS_RW
-#define SLSE_GAUSS_RW 1
-#endif
-constexpr int kRG = SLSE_GAUSS_RG;  // waves along the sketch rows
-constexpr int kCG = SLSE_GAUSS_CG;  // waves along the columns
-constexpr int kNQ = SLSE_GAUSS_NQ;  // 32-column tiles per wave
-constexpr int kRW = SLSE_GAUSS_RW;  // 32-row tiles per wave
-constexpr int kMT = 32 * kRW * kRG; // sketch rows per block
-constexpr int kNT = 32 * kNQ * kCG; // columns per block
-constexpr int kGThreads = 64 * kRG * kCG;
-constexpr int kKT = 8 * kGThreads / kMT;  // data rows per step: one Philox block per thread
-constexpr int kKP = kKT + 8;        // padded LDS row (bf16 elements)
-static_assert(kKT % 16 == 0, "steps are whole MFMA k-blocks");
+// 64 sketch rows x 576 columns per block (every column of a d <= 575 problem
+// in one block, so G is generated once), 64 data rows per step.  Sixteen
+// waves, four per SIMD: 8 MFMA waves, each two 16-row tiles x nine 16-column
+// tiles of v_mfma_f32_16x16x32_bf16 (18 accumulators of four registers), and
+// 8 generator waves, one Philox block per thread per step.  Two generator
+// waves per SIMD: one wave issues at most one VALU instruction every few
+// cycles, and the VALU keeps up with two.
+constexpr int kMT = 64;             // sketch rows per block
+constexpr int kNT = 576;            // columns per block
+constexpr int kKT = 64;             // data rows per step: 8 chunks of 8 per LDS row
+constexpr int kMW = 8;              // MFMA waves: 2 row halves x 4 column quarters
+constexpr int kGW = 8;              // generator waves
+constexpr int kGThreads = 64 * (kMW + kGW);
+constexpr int kRT = 2;              // 16-row tiles per MFMA wave
+constexpr int kCT = kNT / 16 / 4;   // 16-column tiles per MFMA wave (9)
+constexpr int kGB = kMT / 8 * kKT / (64 * kGW);  // Philox blocks per generator thread per step
+static_assert(kRT * 16 * 2 == kMT && kCT * 16 * 4 == kNT, "MFMA waves tile the block");
+static_assert(kGB * 64 * kGW == kMT / 8 * kKT, "whole Philox blocks per generator thread");
+static_assert((2 * kNT + 2 * kMT) * kKT * 2 <= 163840, "two [X|Y] tiles and two G tiles fit in LDS");
 
 __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
   uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -715,11 +722,16 @@ __device__ __forceinline__ __bf16 to_bf16_rne(float f) {
   return __builtin_bit_cast(__bf16, (uint16_t)u);
 }
 
+// element offset of (row, k) in an unpadded swizzled LDS tile of kKT columns
+__device__ __forceinline__ int swz(int row, int k) {
+  return row * kKT + ((((k >> 3) ^ row) & 7) << 3) + (k & 7);
+}
+
 // [X|Y] in BF16 (nearest even), cut into tiles of kKT data rows x kNT
 // columns stored column by column (tile[c][k]), tiles ordered by column block
-// then data-row chunk: the layout of the kernel's LDS tile, so that every
-// block copies its tiles with 16-byte loads instead of converting and
-// transposing [X|Y] again.  Rows past N and columns past d are zeros.
+// then data-row chunk, so that every block copies its tiles with 16-byte
+// loads instead of converting and transposing [X|Y] again.  Rows past N and
+// columns past d are zeros.
 constexpr int kStageThreads = 256;
 // columns held by the tiles of column block cb: whole 32-column MFMA tiles up
 // to the last one with a column of [X|Y] (cols = d + 1)
@@ -778,100 +790,138 @@ __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
   }
 }
 
+// one step of the generator waves: kGB Philox blocks of 8 sketch rows at
+// data row j per thread, rounded to BF16 and written to the G tile (rows past
+// the split are zeros)
+__device__ __forceinline__ void gauss_gen_step(uint64_t seed, uint64_t stream, int64_t k0,
+                                               int64_t j, int64_t j_end, int gt, __bf16* Gb) {
+  const int kb = gt / kKT, jj = gt % kKT;
+  // the blocks' rounds side by side: independent chains for the one
+  // generator wave of a SIMD to issue back to back
+  rng::PhiloxState st[kGB];
+#pragma unroll
+  for (int b = 0; b < kGB; ++b)
+    st[b] = rng::PhiloxState{{(uint64_t)j, (uint64_t)((k0 >> 3) + kb + b * (64 * kGW / kKT)), 0, 0},
+                             seed,
+                             stream};
+#pragma unroll
+  for (int r = 0; r < 10; ++r)
+#pragma unroll
+    for (int b = 0; b < kGB; ++b) rng::philox_round(st[b], r);
+  const bool live = j < j_end;
+#pragma unroll
+  for (int b = 0; b < kGB; ++b) {
+    const int rb = kb + b * (64 * kGW / kKT);  // group of 8 sketch rows
+    float z[8];
+    box_muller8_words(st[b].c, z);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Gb[swz(rb * 8 + q, jj)] = to_bf16_rne(live ? z[q] : 0.0f);
+  }
+}
+
+// the staged [X|Y] tile of one step copied straight into LDS by the MFMA
+// waves (16 bytes per lane, placed in order from the wave's LDS base; no
+// registers): slot p of row c receives the tile's chunk p ^ (c % 8)
+__device__ __forceinline__ void gauss_copy_step(const __bf16* tb, int wc, __bf16* Wb, int wave,
+                                                int lane) {
+  const int copies = wc / 8;  // 8 rows of 128 bytes per wave-wide copy
+  const int c_in = lane >> 3, p = lane & 7;
+  for (int g = wave; g < copies; g += kMW) {
+    const int c = 8 * g + c_in;
+    const __bf16* src = tb + (int64_t)c * kKT + 8 * (p ^ c_in);
+    __builtin_amdgcn_global_load_lds(
+        (const SLSE_GLOBAL void*)src,
+        (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(Wb) + 1024 * g), 16, 0,
+        0);
+  }
+}
+
 __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
                                                          const __bf16* __restrict__ tiles,
                                                          int64_t nchunks, uint64_t seed,
                                                          uint64_t stream, int64_t m, int splits,
                                                          float* __restrict__ part, int64_t ldp) {
-  __shared__ __attribute__((aligned(16))) __bf16 Gs[kMT][kKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Ws[kNT][kKP];
+  __shared__ __attribute__((aligned(1024))) __bf16 Ws[2][kNT * kKT];
+  __shared__ __attribute__((aligned(1024))) __bf16 Gs[2][kMT * kKT];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t k0 = (int64_t)blockIdx.x * kMT;
   const int c0 = blockIdx.y * kNT;
   const int split = blockIdx.z;
   const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
   const int64_t j_begin = (int64_t)split * per;
   const int64_t j_end = min(N, j_begin + per);
-  constexpr int NQ = kNQ;
-  const int rg = wave % kRG;  // row group (kRW tiles of 32 rows)
-  const int cg = wave / kRG;  // column group
   const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
   const int wc = gauss_tile_cols(d + 1, blockIdx.y);  // columns of this block's tiles
-  f32x16_t acc[kRW][NQ];
-#pragma unroll
-  for (int w = 0; w < kRW; ++w)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[w][q][r] = 0.0f;
-  for (int64_t j0 = j_begin; j0 < j_end; j0 += kKT) {
-    {  // [X|Y] tile: the staged BF16 tile copied straight into LDS (16 bytes
-       // per lane, placed linearly from the wave's LDS base; no registers),
-       // issued first so that the copy overlaps the generation of G.  An LDS
-       // row of Ws is kKP / 8 slots; its padding slot gets any valid bytes.
-      constexpr int kRowSlots = kKP / 8;
-      static_assert(kKT % 8 == 0 && (kNT * kRowSlots) % 64 == 0, "whole wave-wide copies");
-      const int copies = (wc * kRowSlots + 63) / 64;  // wave-wide copies of this tile
-      const __bf16* tb = tcol + (j0 / kKT) * (wc * kKT);
-      for (int g = wave; g < copies; g += kGThreads / 64) {
-        const int sl = 64 * g + lane;
-        const int cc = sl / kRowSlots, pc = sl % kRowSlots;
-        // rows past the tile (the last copy's tail) and padding slots read
-        // the tile's first bytes; those LDS slots are never used
-        const __bf16* src = cc < wc ? tb + (int64_t)cc * kKT + 8 * (pc < kKT / 8 ? pc : 0) : tb;
-        __builtin_amdgcn_global_load_lds(
-            (const SLSE_GLOBAL void*)src,
-            (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(&Ws[0][0]) + 1024 * g),
-            16, 0, 0);
-      }
-    }
-    {  // G tile: thread -> (row block of 8, data row)
-      static_assert(kMT / 8 * kKT == kGThreads, "one Philox block per thread per step");
-      const int kb = threadIdx.x / kKT;  // group of 8 sketch rows
-      const int jj = threadIdx.x % kKT;
-      const int64_t j = j0 + jj;
-      float z[8];
-      if (j < j_end) {
-        box_muller8_fast(seed, stream, (uint64_t)j, (uint64_t)((k0 >> 3) + kb), z);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) z[q] = 0.0f;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Gs[kb * 8 + q][jj] = to_bf16_rne(z[q]);
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's copies are in LDS
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kKT / 16; ++ks) {
-      const int kk = 16 * ks + 8 * (lane >> 5);
-      bf16x8_t a[kRW];
-#pragma unroll
-      for (int w = 0; w < kRW; ++w)
-        a[w] = *reinterpret_cast<const bf16x8_t*>(&Gs[(rg * kRW + w) * 32 + (lane & 31)][kk]);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if ((cg * NQ + q) * 32 >= wc) continue;  // a column tile past [X|Y]
-        const bf16x8_t b =
-            *reinterpret_cast<const bf16x8_t*>(&Ws[(cg * NQ + q) * 32 + (lane & 31)][kk]);
-#pragma unroll
-        for (int w = 0; w < kRW; ++w)
-          acc[w][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[w], b, acc[w][q], 0, 0, 0);
-      }
-    }
-    __syncthreads();
+  const int64_t steps = j_end > j_begin ? ceil_div(j_end - j_begin, kKT) : 0;
+  if (steps == 0) return;  // the whole block: no barrier is left waiting
+  const bool mfma_wave = wave < kMW;
+  const int gt = threadIdx.x - 64 * kMW;  // generator thread index
+  // step 0's tiles
+  if (mfma_wave) {
+    gauss_copy_step(tcol + (j_begin / kKT) * (wc * kKT), wc, Ws[0], wave, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    gauss_gen_step(seed, stream, k0, j_begin + gt % kKT, j_end, gt, Gs[0]);
   }
+  __syncthreads();
+  if (mfma_wave) {
+    const int rh = wave & 1;   // 32-row half: two 16-row tiles
+    const int cq = wave >> 1;  // quarter of the 36 16-column tiles
+    f32x4_t acc[kRT][kCT];
 #pragma unroll
-  for (int w = 0; w < kRW; ++w)
+    for (int i = 0; i < kRT; ++i)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
+      for (int q = 0; q < kCT; ++q)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t k = k0 + (rg * kRW + w) * 32 + (r % 4) + 8 * (r / 4) + 4 * (lane >> 5);
-        const int col = c0 + (cg * NQ + q) * 32 + (lane & 31);
-        if (k < m && col <= d) part[((int64_t)split * m + k) * ldp + col] = acc[w][q][r];
+        for (int r = 0; r < 4; ++r) acc[i][q][r] = 0.0f;
+    for (int64_t s = 0; s < steps; ++s) {
+      const int b = (int)(s & 1);
+      if (s + 1 < steps)
+        gauss_copy_step(tcol + ((j_begin + (s + 1) * kKT) / kKT) * (wc * kKT), wc, Ws[b ^ 1],
+                        wave, lane);
+      const __bf16* Gb = Gs[b];
+      const __bf16* Wb = Ws[b];
+#pragma unroll
+      for (int ks = 0; ks < kKT / 32; ++ks) {
+        const int kk = 32 * ks + 8 * (lane >> 4);
+        bf16x8_t a[kRT];
+#pragma unroll
+        for (int i = 0; i < kRT; ++i)
+          a[i] = *reinterpret_cast<const bf16x8_t*>(&Gb[swz(rh * 32 + i * 16 + (lane & 15), kk)]);
+#pragma unroll
+        for (int q = 0; q < kCT; ++q) {
+          // tiles past [X|Y] multiply stale LDS and are never stored
+          const int col = (cq * kCT + q) * 16 + (lane & 15);
+          const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&Wb[swz(col, kk)]);
+#pragma unroll
+          for (int i = 0; i < kRT; ++i)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[i][q], 0, 0, 0);
+        }
       }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // next [X|Y] tile is in LDS
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kRT; ++i)
+#pragma unroll
+      for (int q = 0; q < kCT; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t k = k0 + rh * 32 + i * 16 + 4 * (lane >> 4) + r;
+          const int t = cq * kCT + q;
+          const int col = c0 + t * 16 + (lane & 15);
+          if (k < m && col <= d && t * 16 < wc)
+            part[((int64_t)split * m + k) * ldp + col] = acc[i][q][r];
+        }
+  } else {
+    for (int64_t s = 0; s < steps; ++s) {
+      // G of step s + 1 (zeros after the last step: never read)
+      const int64_t j = j_begin + (s + 1) * kKT + gt % kKT;
+      gauss_gen_step(seed, stream, k0, j, j_end, gt, Gs[(s + 1) & 1]);
+      __syncthreads();
+    }
+  }
 }
 
 // Reference for measurement: the matrix-core kernel's generation of G alone

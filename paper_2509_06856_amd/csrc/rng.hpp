@@ -45,26 +45,37 @@ __host__ __device__ __forceinline__ void mulhilo(uint64_t a, uint64_t b, uint64_
   hi = (uint64_t)(p >> 64);
 }
 
+// Philox4x64-10 state between rounds: counter words and key.
+struct PhiloxState {
+  uint64_t c[4];
+  uint64_t k0, k1;
+};
+
+// round r (0..9) of Philox4x64-10: the key is bumped by the Weyl constants
+// before every round but the first
+__host__ __device__ __forceinline__ void philox_round(PhiloxState& s, int r) {
+  if (r) {
+    s.k0 += kW0;
+    s.k1 += kW1;
+  }
+  uint64_t hi0, lo0, hi1, lo1;
+  mulhilo(kM0, s.c[0], hi0, lo0);
+  mulhilo(kM1, s.c[2], hi1, lo1);
+  const uint64_t n0 = hi1 ^ s.c[1] ^ s.k0;
+  const uint64_t n2 = hi0 ^ s.c[3] ^ s.k1;
+  s.c[0] = n0;
+  s.c[1] = lo1;
+  s.c[2] = n2;
+  s.c[3] = lo0;
+}
+
 // Philox4x64-10 block: 10 rounds, key bumped by the Weyl constants between them.
 __host__ __device__ __forceinline__ Words philox(uint64_t c0, uint64_t c1, uint64_t c2,
                                                  uint64_t c3, uint64_t k0, uint64_t k1) {
+  PhiloxState s{{c0, c1, c2, c3}, k0, k1};
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += kW0;
-      k1 += kW1;
-    }
-    uint64_t hi0, lo0, hi1, lo1;
-    mulhilo(kM0, c0, hi0, lo0);
-    mulhilo(kM1, c2, hi1, lo1);
-    uint64_t n0 = hi1 ^ c1 ^ k0;
-    uint64_t n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return Words{{c0, c1, c2, c3}};
+  for (int r = 0; r < 10; ++r) philox_round(s, r);
+  return Words{{s.c[0], s.c[1], s.c[2], s.c[3]}};
 }
 
 __host__ __device__ __forceinline__ uint64_t feistel_round(uint64_t x, int i, uint64_t seed,
