@@ -227,12 +227,28 @@ typedef struct {
   double* pred_err;           /* device, T+1: ||X (beta_t - beta_ref)||^2, the prediction error
                                  Delta_t of the experiments (Sec. 5) when beta_ref is the true
                                  beta; or NULL.  Costs one extra read of X per iterate. */
+  /* Checkpoint and resume.  The sketch is a function of the seed, so the whole
+   * state of the iteration after step t - 1 is (beta_t, beta_{t-1}).  Steps are
+   * numbered t = 0..T-1 over the whole solve (stage 1 subproblem by subproblem,
+   * then stage 2; T = sum a_i + s_max).  The call sketches and factors, then
+   * runs steps start_step .. stop_step - 1 from beta_{start_step} = beta0 and
+   * beta_{start_step - 1} = beta_prev.  A momentum reset (momentum_reset) at the
+   * start of a subproblem or of stage 2 happens when its first step is run.
+   * trajectory rows and the surrogate and error entries keep their indices t;
+   * those of steps not run are not written.  A stopped run resumed from its
+   * state_out retraces the uninterrupted run (Alg. 2 keeps one global t). */
+  int32_t start_step;         /* first step to run, 0 <= start_step <= stop */
+  int32_t stop_step;          /* run the steps t < stop_step; 0 = T */
+  const double* beta_prev;    /* device, d: beta_{start_step - 1}; NULL = beta0 */
+  double* state_out;          /* device, 2 x d: (beta_{t-1}, beta_t) for the last iterate t
+                                 computed, the checkpoint to resume from; or NULL.  After a
+                                 stop on tol the pair is unspecified. */
 } slse_params;
 
 typedef struct {
   slse_status status;
-  int32_t stage1_steps;
-  int32_t stage2_steps; /* steps actually taken */
+  int32_t stage1_steps; /* stage-1 steps run by this call */
+  int32_t stage2_steps; /* stage-2 steps run by this call (up to the tol stop) */
   double surrogate0;    /* error estimate at the first stage-2 step */
   double surrogate_final; /* error estimate at the last step taken */
   double ms_total;      /* device time of the call (hipEvents) */
@@ -252,7 +268,8 @@ typedef struct {
  *  beta_out   device FP64, length d: beta_T.
  *  rep        host report or NULL.  When non-NULL the call synchronizes the
  *             stream to fill it.
- * Errors: EINVAL (see slse_sketch_apply for the sizes), ESINGULAR from the
+ * Errors: EINVAL (see slse_sketch_apply for the sizes; also start_step or
+ * stop_step outside 0..T, or start_step > stop), ESINGULAR from the
  * factorization, ENOTCONV when tol > 0 was not met (beta_out still holds
  * the last iterate), ENONFINITE when the surrogate is not finite.
  */
@@ -295,7 +312,7 @@ slse_status slse_solve_ws(slse_ctx* ctx, const slse_problem* p, const slse_param
  * nested level of the power of 2 >= r rows, which IHS does not use).  It is
  * eq. (99) with mu = 1 and eta = 0 and a fresh H_hat per step.  Read from q: kind,
  * seed, r, s_max, precision, factor, beta0, trajectory, use_graph; m, a, mu, eta,
- * tol and the error-accounting fields are ignored.
+ * tol, the error-accounting and the checkpoint fields are ignored.
  *  beta_out   device FP64, length d: beta_{s_max}.
  * Errors: as slse_solve.
  */
@@ -345,7 +362,8 @@ slse_status slse_stage1_counts(const int64_t* m, int32_t K, int64_t d, double om
  *     dY = X lambda,   dX = r lambda^T - (X lambda) beta_hat^T,  r = Y - X beta_hat
  * (from differentiating the normal equations of the problem statement).
  * The preconditioner of the last slse_solve on the same data, seed and sizes
- * is reused when the context still holds it; otherwise it is rebuilt.
+ * is reused when the context still holds it; otherwise it is rebuilt.  The
+ * error-accounting and checkpoint fields of q are ignored.
  *  beta_hat      device FP64, length d.
  *  w, incw       device FP64, entry k at w[k * incw] (incw >= 0; 0 repeats w[0]).
  *  dX, lddx      device output N x d in grad_t (F32 or F64), or NULL.
@@ -364,7 +382,8 @@ slse_status slse_backward(slse_ctx* ctx, const slse_problem* p, const slse_param
  * whole sequence captured once as a hipGraph and replayed.  Problems whose
  * schedule is shorter idle through the extra steps.
  *  ps, qs      host arrays of B problems and parameters (trajectory,
- *              surrogate and use_graph fields are ignored).
+ *              surrogate and use_graph fields are ignored; the checkpoint
+ *              fields must be zero / NULL: EINVAL otherwise).
  *  betas       host array of B device pointers (FP64, length d_b each).
  *  reps        host array of B reports, or NULL.
  * Every problem of a batch shares one storage dtype and has d_b <= 512

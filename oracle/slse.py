@@ -92,13 +92,23 @@ def prediction_error(X, beta, beta_ref, row_block=ROW_BLOCK):
 
 
 def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
-             momentum_reset=False, sk=None, **sketch_kw):
+             momentum_reset=False, sk=None, start=0, stop=None, beta_prev0=None, **sketch_kw):
     """Run Alg. 2 and return (beta_T, trajectory, info).
 
     trajectory[t] is beta_t for t = 0..T (T = sum(a) + s).  info["surrogate"][t]
     is stop_estimate of step t (the step from beta_t to beta_{t+1}, with the
     scaled sketched gradient in stage 1).  `sk` may pass a precomputed oracle
     sketch (same seed and sizes) to avoid recomputing it.
+
+    Checkpoint and resume: the steps are numbered t = 0..T-1 over the whole
+    algorithm (stage 1 level by level, then stage 2), and the sketch is a
+    function of the seed, so the iteration's whole state after step t - 1 is
+    (beta_t, beta_{t-1}).  With start > 0 the call runs steps start..stop-1
+    from beta_start = beta0 and beta_{start-1} = beta_prev0 (beta0 when None);
+    trajectory and surrogate entries before `start` are None.  A momentum
+    reset at the start of a subproblem (or of stage 2) happens when the first
+    step of that subproblem is run.  info["state"] = (beta_{t-1}, beta_t) at
+    the last iterate t computed, the checkpoint to resume from.
     """
     d = X.shape[1]
     if mu is None or eta is None:
@@ -108,27 +118,33 @@ def slse_frs(X, Y, seed, kind, m, a, r, s, mu=None, eta=None, beta0=None,
     if sk is None:
         sk = make_sketch(kind, X, Y, seed, m, r, **sketch_kw)
     R = precond_factor(sk["Ahat"], d, sk["hat_scale"])
+    T = sum(a[: len(sk["m"])]) + s
+    stop = T if stop is None else stop
+    assert 0 <= start <= stop <= T
     beta = np.zeros(d) if beta0 is None else np.asarray(beta0, np.float64).copy()
-    beta_prev = beta.copy()
-    traj = [beta.copy()]
-    sur = []
-    for i, (mi, ai) in enumerate(zip(sk["m"], a)):
-        Ai = sk["A"][sk["offset"][i]: sk["offset"][i] + mi]
-        if momentum_reset:
+    beta_prev = beta.copy() if beta_prev0 is None else np.asarray(beta_prev0, np.float64).copy()
+    traj = [None] * start + [beta.copy()]
+    sur = [None] * start
+    # the step sequence of Alg. 2: (subproblem or None for stage 2, its first step?)
+    steps = []
+    for i, ai in enumerate(a[: len(sk["m"])]):
+        steps += [(i, j == 0) for j in range(ai)]
+    steps += [(None, j == 0) for j in range(s)]
+    # a reset at a subproblem with no steps is repeated by the next one's: no effect
+    for t in range(start, stop):
+        i, first = steps[t]
+        if momentum_reset and first:
             beta_prev = beta.copy()
-        for _ in range(ai):
+        if i is not None:
+            Ai = sk["A"][sk["offset"][i]: sk["offset"][i] + sk["m"][i]]
             g = sketched_grad(Ai, d, sk["scale"][i], beta)
-            beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
-            sur.append(stop_estimate(R, g, beta))
-            traj.append(beta.copy())
-    if momentum_reset:
-        beta_prev = beta.copy()
-    for _ in range(s):
-        g = full_grad(X, Y, beta)
+        else:
+            g = full_grad(X, Y, beta)
         beta, beta_prev = mihs_step(beta, beta_prev, g, R, mu, eta), beta
         sur.append(stop_estimate(R, g, beta))
         traj.append(beta.copy())
-    return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta, surrogate=sur)
+    return beta, traj, dict(R=R, sketch=sk, mu=mu, eta=eta, surrogate=sur,
+                            state=(beta_prev.copy(), beta.copy()))
 
 
 def ihs(X, Y, seed, kind, r, steps, beta0=None, **sketch_kw):

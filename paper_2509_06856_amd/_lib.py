@@ -86,6 +86,10 @@ class slse_params(ctypes.Structure):
         ("beta_ref", c_vp),
         ("rel_err", c_vp),
         ("pred_err", c_vp),
+        ("start_step", c_i32),
+        ("stop_step", c_i32),
+        ("beta_prev", c_vp),
+        ("state_out", c_vp),
     ]
 
 

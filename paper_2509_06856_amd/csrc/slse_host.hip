@@ -598,16 +598,26 @@ struct Stepper {
     launch_finalize_grad(b.gpart, pl.groups, pl.ldp, d, 1.0, b.err_g, err.pred + t, st);
   }
 
-  void start(const double* beta0, double* traj) {
+  // beta_{t0} = beta0 (zeros if NULL), beta_{t0-1} = beta_prev (beta0 if NULL)
+  void start(const double* beta0, double* traj, const double* beta_prev = nullptr, int t0 = 0) {
     if (beta0)
       launch_copy_f64(beta0, b.beta[0], d, st);
     else
       launch_fill_f64(b.beta[0], 0.0, d, st);
-    if (traj) launch_copy_f64(b.beta[0], traj, d, st);
-    launch_fill_i32(b.flags, 0, 4, st);
     cur = prev = 0;
-    t = 0;
+    if (beta_prev) {
+      launch_copy_f64(beta_prev, b.beta[1], d, st);
+      prev = 1;
+    }
+    t = t0;
+    if (traj) launch_copy_f64(b.beta[0], traj + (int64_t)t0 * d, d, st);
+    launch_fill_i32(b.flags, 0, 4, st);
     record_errors();
+  }
+  // (beta_{t-1}, beta_t) of the current iterate
+  void save_state(double* out) const {
+    launch_copy_f64(b.beta[prev], out, d, st);
+    launch_copy_f64(b.beta[cur], out + d, d, st);
   }
   void reset_momentum() { prev = cur; }
 
@@ -700,12 +710,23 @@ void check_params(const slse_problem* p, const slse_params* q) {
   require(std::isfinite(q->mu) && std::isfinite(q->eta), "mu, eta must be finite");
   require(q->factor == SLSE_FACTOR_CHOL || q->factor == SLSE_FACTOR_QR, "unknown factor method");
   require(!(q->rel_err || q->pred_err) || q->beta_ref, "rel_err / pred_err need beta_ref");
+  int T = q->s_max;
+  for (int i = 0; i < q->K; ++i) T += q->a[i];
+  require(q->stop_step >= 0 && q->stop_step <= T, "need 0 <= stop_step <= T");
+  require(q->start_step >= 0 && q->start_step <= (q->stop_step ? q->stop_step : T),
+          "need 0 <= start_step <= stop_step (or T)");
 }
 
 int total_steps(const slse_params* q) {
   int T = q->s_max;
   for (int i = 0; i < q->K; ++i) T += q->a[i];
   return T;
+}
+
+// the steps [t0, t1) that a call runs (checkpoint and resume)
+void step_range(const slse_params* q, int& t0, int& t1) {
+  t0 = q->start_step;
+  t1 = q->stop_step ? q->stop_step : total_steps(q);
 }
 
 // Row stride of the internal sketch buffers: rows of at least one 128-byte
@@ -766,28 +787,35 @@ void enqueue_solve(const slse_ctx* ctx, const SolvePlan& pl, const slse_problem*
   mark(0);
   enqueue_factor(pl.f, sk.r, d, pl.Ahat, pl.ldah, pl.st_t, sk.hat_scale, q->factor, st);
   mark(1);
+  // steps t0 .. t1-1 of the global step sequence (all of them unless resuming)
+  int t0, t1;
+  step_range(q, t0, t1);
   Stepper S{pl.it, d, pl.f.M, 0, 0, 0, st, ctx, error_sink(p, q)};
-  S.start(q->beta0, q->trajectory);
+  S.start(q->beta0, q->trajectory, q->beta_prev, t0);
   launch_copy_f64(S.b.beta[0], beta_out, d, st);
   const size_t es = dtype_size(pl.st_t);
+  int g = 0;  // global index of the next step
   // stage 1: a_i steps on the prefix of m_i sketched rows (eq. (98))
   for (int i = 0; i < sk.K; ++i) {
-    if (q->momentum_reset) S.reset_momentum();
     const char* base = static_cast<const char*>(pl.A) + (size_t)sk.offset[i] * pl.lda * es;
-    for (int j = 0; j < q->a[i]; ++j) {
+    for (int j = 0; j < q->a[i]; ++j, ++g) {
+      if (g < t0 || g >= t1) continue;
+      if (j == 0 && q->momentum_reset) S.reset_momentum();
       S.step(sk.m[i], base, pl.lda, base + (size_t)d * es, pl.lda, pl.st_t, pl.acc1, sk.scale[i],
              nullptr, q->mu, q->eta, beta_out, q->trajectory, pl.sur, 0.0);
     }
   }
   mark(2);
   // stage 2: full-data steps (eq. (99))
-  if (q->momentum_reset) S.reset_momentum();
-  for (int j = 0; j < q->s_max; ++j) {
+  for (int j = 0; j < q->s_max; ++j, ++g) {
+    if (g < t0 || g >= t1) continue;
+    if (j == 0 && q->momentum_reset) S.reset_momentum();
     slse_dtype acc = SLSE_F64;
     if (q->precision == SLSE_PREC_MIXED && j < q->fp32_sweeps) acc = SLSE_F32;
     S.step(p->N, p->X, p->ldx, p->Y, 1, pl.st_t, acc, 1.0, nullptr, q->mu, q->eta, beta_out,
            q->trajectory, pl.sur, q->tol);
   }
+  if (q->state_out) S.save_state(q->state_out);
   mark(3);
 }
 
@@ -874,20 +902,23 @@ slse_status finish_report(const SolvePlan& pl, const slse_params* q, slse_report
     rep->status = status;
     int s1 = 0;
     for (int i = 0; i < q->K; ++i) s1 += q->a[i];
-    rep->stage1_steps = s1;
-    rep->stage2_steps = q->s_max;
     const int T = s1 + q->s_max;
-    if (T > 0 && pl.sur) {
+    int t0, t1;
+    step_range(q, t0, t1);
+    const int u2 = std::max(t0, s1);  // first stage-2 step run
+    rep->stage1_steps = std::max(0, std::min(t1, s1) - t0);
+    rep->stage2_steps = std::max(0, t1 - u2);
+    if (t1 > t0 && pl.sur) {
       std::vector<double> sur(T, 0.0);
       SLSE_HIP(hipMemcpy(sur.data(), pl.sur, sizeof(double) * T, hipMemcpyDeviceToHost));
       int taken = 0;
-      for (int t = s1; t < T; ++t) {
+      for (int t = u2; t < t1; ++t) {
         ++taken;
         if (q->tol > 0 && sur[t] <= q->tol) break;
       }
-      rep->stage2_steps = q->tol > 0 ? taken : q->s_max;
-      rep->surrogate0 = s1 < T ? sur[s1] : sur[0];
-      const int last = std::min(T - 1, std::max(0, s1 + rep->stage2_steps - 1));
+      if (q->tol > 0) rep->stage2_steps = taken;
+      rep->surrogate0 = u2 < t1 ? sur[u2] : sur[t0];
+      const int last = rep->stage2_steps > 0 ? u2 + rep->stage2_steps - 1 : t1 - 1;
       rep->surrogate_final = sur[last];
     }
     if (tm.n == 5) {
@@ -1004,6 +1035,9 @@ slse_status ihs_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
   qq.surrogate = nullptr;
   qq.beta_ref = nullptr;
   qq.rel_err = qq.pred_err = nullptr;
+  qq.start_step = qq.stop_step = 0;
+  qq.beta_prev = nullptr;
+  qq.state_out = nullptr;
   check_params(p, &qq);
   ctx->arena.grew = false;
   SolvePlan pl = reserve_solve(ctx, p, &qq);
@@ -1447,6 +1481,8 @@ std::pair<std::string, bool> plan_batched(slse_ctx* ctx, int B, const slse_probl
   bp.t = ps[0].dtype;
   for (int b = 0; b < B; ++b) {
     check_params(&ps[b], &qs[b]);
+    require(qs[b].start_step == 0 && qs[b].stop_step == 0 && !qs[b].beta_prev && !qs[b].state_out,
+            "batched solves do not checkpoint or resume");
     require(betas[b] != nullptr, "null beta pointer in the batch");
     require(ps[b].dtype == bp.t, "every problem of a batch must share one storage dtype");
     require(ps[b].d <= 512, "batched problems need d <= 512");

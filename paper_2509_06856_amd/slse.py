@@ -128,7 +128,7 @@ class Params:
     use_graph: bool = False
 
     def to_c(self, d, beta0=None, trajectory=None, surrogate=None, beta_ref=None, rel_err=None,
-             pred_err=None):
+             pred_err=None, start_step=0, stop_step=0, beta_prev=None, state_out=None):
         q = L.slse_params()
         q.kind = _KIND[self.kind]
         q.seed = self.seed
@@ -155,6 +155,10 @@ class Params:
         q.beta_ref = _ptr(beta_ref).value
         q.rel_err = _ptr(rel_err).value
         q.pred_err = _ptr(pred_err).value
+        q.start_step = int(start_step)
+        q.stop_step = int(stop_step)
+        q.beta_prev = _ptr(beta_prev).value
+        q.state_out = _ptr(state_out).value
         return q
 
 
@@ -184,13 +188,16 @@ def _info(st, rep):
 
 
 def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True, beta_ref=None,
-          pred_err=False, ws=None):
+          pred_err=False, ws=None, start_step=0, stop_step=0, beta_prev=None, state_out=None):
     """slse_solve (slse_solve_ws when `ws`, a uint8 device tensor, is given).
 
     Returns (beta, report dict), plus (trajectory, surrogate) when `record`,
     plus the per-iterate errors against `beta_ref` as a dict with "rel_err"
     (and "pred_err" = ||X (beta_t - beta_ref)||^2 when `pred_err`) when
-    `beta_ref` is given.
+    `beta_ref` is given.  Checkpoint and resume: steps start_step ..
+    stop_step - 1 (0 = to the end) are run from beta0 (beta_t) and beta_prev
+    (beta_{t-1}); `state_out`, a (2, d) float64 device tensor, receives the
+    state (beta_{t-1}, beta_t) after the last step run.
     """
     ctx = ctx or default_context(X.device.index)
     p = _problem(X, Y)
@@ -204,8 +211,14 @@ def solve(X, Y, params: Params, ctx=None, beta0=None, record=False, report=True,
         errs = {"rel_err": torch.empty(T + 1, dtype=torch.float64, device=X.device)}
         if pred_err:
             errs["pred_err"] = torch.empty(T + 1, dtype=torch.float64, device=X.device)
+    for v in (beta_prev, state_out):
+        if v is not None:
+            _need_cuda(v)
+    if state_out is not None and (state_out.dtype != torch.float64 or state_out.numel() < 2 * d
+                                  or not state_out.is_contiguous()):
+        raise ValueError("state_out must be a contiguous float64 tensor of 2 x d")
     q = params.to_c(d, beta0, traj, sur, beta_ref, errs and errs["rel_err"],
-                    errs and errs.get("pred_err"))
+                    errs and errs.get("pred_err"), start_step, stop_step, beta_prev, state_out)
     beta = torch.empty(d, dtype=torch.float64, device=X.device)
     rep = L.slse_report()
     rp = ctypes.byref(rep) if report else None

@@ -2,7 +2,8 @@
 the per-step stop estimate, per-iterate error accounting (relative error and
 the prediction error Delta_t of Sec. 5), phase times, the caller-workspace
 solve, the IHS baseline, FP32-accumulated stage-2 sweeps, the adjoint's
-strided right-hand side and back-to-back batched calls on a side stream.
+strided right-hand side, back-to-back batched calls on a side stream, the
+persistent tuning cache and checkpoint / resume of a solve.
 """
 import numpy as np
 import pytest
@@ -234,3 +235,50 @@ def test_tuned_launch_shapes_persist_across_contexts(G, tmp_path):
         c2.load_tuning(bad)
     c1.close()
     c2.close()
+
+
+@pytest.mark.parametrize("kind", ["srht", "gaussian"])
+@pytest.mark.parametrize("reset", [False, True])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_checkpoint_resume_retraces_the_solve(G, kind, reset, use_graph):
+    # a solve stopped after k steps and resumed from its (beta_{k-1}, beta_k)
+    # retraces the uninterrupted solve bit for bit (the sketch is recomputed
+    # from the seed; the launch shapes and reduction orders are the same):
+    # mid-subproblem, at a subproblem boundary, at the start of stage 2,
+    # inside stage 2 and at the end
+    p = make_problem("plain_small", n=1 << 14, d=32)
+    X, Y = dev(p.X), dev(p.Y)
+    prm = G.Params(kind=kind, seed=77, m=[256, 512, 1024], a=[2, 3, 2], r=192, s_max=12,
+                   momentum_reset=reset, use_graph=use_graph)
+    T = sum(prm.a) + prm.s_max
+    beta, info, traj, sur = G.solve(X, Y, prm, record=True)
+    assert info["stage1_steps"] == 7 and info["stage2_steps"] == 12
+    for k in [3, 5, 7, 11, T]:  # stop_step = 0 means T
+        st = torch.empty((2, 32), dtype=torch.float64, device="cuda:0")
+        _, ip = G.solve(X, Y, prm, stop_step=k, state_out=st)
+        assert ip["stage1_steps"] == min(k, 7) and ip["stage2_steps"] == max(0, k - 7)
+        assert torch.equal(st[1], traj[k]), k
+        assert torch.equal(st[0], traj[k - 1]), k
+        b2, ir, traj2, sur2 = G.solve(X, Y, prm, record=True, start_step=k, beta0=st[1],
+                                      beta_prev=st[0])
+        assert ir["stage1_steps"] == max(0, 7 - k) and ir["stage2_steps"] == min(12, T - k)
+        assert torch.equal(b2, beta), k
+        assert torch.equal(traj2[k:], traj[k:]), k
+        if k < T:
+            assert torch.equal(sur2[k:T], sur[k:T]), k
+    # the oracle's state at a checkpoint is the same iterate (Gaussian sketch
+    # entries agree to FP32 Box-Muller accuracy only)
+    _, otraj, _ = OS.slse_frs(p.X, p.Y, 77, kind, prm.m, prm.a, 192, 12, momentum_reset=reset)
+    assert OS.rel_err(traj[5].cpu().numpy(), otraj[5]) < (1e-12 if kind == "srht" else 1e-5)
+
+
+def test_checkpoint_fields_are_checked(G):
+    p = make_problem("plain_small", n=4096, d=16)
+    X, Y = dev(p.X), dev(p.Y)
+    prm = G.Params(kind="srht", seed=3, m=[128, 256], a=[2, 2], r=96, s_max=4)
+    for kw in (dict(start_step=9), dict(stop_step=9), dict(start_step=5, stop_step=3),
+               dict(start_step=-1)):
+        with pytest.raises(Exception):
+            G.solve(X, Y, prm, **kw)
+    beta, _ = G.solve(X, Y, prm, start_step=8)  # nothing left to run: beta_8 = beta0 = 0
+    assert not beta.cpu().numpy().any()

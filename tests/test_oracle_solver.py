@@ -142,6 +142,34 @@ def test_momentum_reset_changes_only_the_path():
     assert L.rel_err(b1, bstar) < 1e-13 and L.rel_err(b2, bstar) < 1e-13
 
 
+@pytest.mark.parametrize("reset", [False, True])
+def test_checkpoint_resume_is_bit_identical(reset):
+    # the state after step t - 1 is (beta_t, beta_{t-1}) (the sketch is a
+    # function of the seed): a run stopped at k and resumed from its state
+    # retraces the uninterrupted run exactly, mid-subproblem, at a subproblem
+    # boundary, at the start of stage 2, inside stage 2 and at the end
+    p = make_problem("plain_small", n=2048, d=12)
+    m, a, r, s = [128, 256, 512], [2, 3, 2], 72, 9
+    sk = S.sketch("srht", p.X, p.Y, 33, m, r)
+    b_full, t_full, _ = L.slse_frs(p.X, p.Y, 33, "srht", m, a, r, s, sk=sk, momentum_reset=reset)
+    T = sum(a) + s
+    for k in [0, 1, 2, 3, 5, 7, 8, 12, T - 1, T]:
+        _, t_part, info = L.slse_frs(p.X, p.Y, 33, "srht", m, a, r, s, sk=sk, stop=k,
+                                     momentum_reset=reset)
+        prev, cur = info["state"]
+        assert np.array_equal(cur, t_full[k])
+        if k > 0:
+            assert np.array_equal(prev, t_full[k - 1])
+        b_res, t_res, _ = L.slse_frs(p.X, p.Y, 33, "srht", m, a, r, s, sk=sk, start=k, beta0=cur,
+                                     beta_prev0=prev, momentum_reset=reset)
+        assert np.array_equal(b_res, b_full), k
+        for t in range(k, T + 1):
+            assert np.array_equal(t_res[t], t_full[t]), (k, t)
+    # a resume that forgets beta_{t-1} loses the momentum term: another path
+    _, t_bad, _ = L.slse_frs(p.X, p.Y, 33, "srht", m, a, r, s, sk=sk, start=3, beta0=t_full[3])
+    assert not np.allclose(t_bad[4], t_full[4])
+
+
 def test_paper_ls_error_level():
     """Delta_T reaches the LS error sigma^2 d (Sec. 5.2 and its Fig. 2 left)."""
     with open(os.path.join(GOLDEN, "paper_ls_error.json")) as f:
