@@ -619,8 +619,14 @@ def main():
             raise SystemExit("--gaussian-only needs the FP32 (mixed) workload")
         for _ in range(3):
             G.sketch_apply(X, Y, "gaussian", params.seed, [6 * d], 6 * d, bf16=True)
+        # the VALU floor: the same entries of G generated alone, three times
+        sink = torch.empty(256 * 1024, dtype=torch.int32, device=X.device)
+        for _ in range(3):
+            for st in (7, 8):
+                G.debug_gaussian_generate(params.seed, st, 6 * d, N, 1024, sink=sink)
         torch.cuda.synchronize()
-        log(f"gaussian_bf16: 3 sketch pairs of N={N}, {6 * d} + {6 * d} rows")
+        log(f"gaussian_bf16: 3 sketch pairs of N={N}, {6 * d} + {6 * d} rows, then 3 generation-only "
+            f"pairs")
         return
     if args.kernel_only:
         beta0 = torch.from_numpy(beta_star).to(dev)
