@@ -716,11 +716,10 @@ static_assert(kRT * 16 * 2 == kMT && kCT * 16 * 4 == kNT, "MFMA waves tile the b
 static_assert(kGB * 64 * kGW == kMT / 8 * kKT, "whole Philox blocks per generator thread");
 static_assert((2 * kNT + 2 * kMT) * kKT * 2 <= 163840, "two [X|Y] tiles and two G tiles fit in LDS");
 
-__device__ __forceinline__ __bf16 to_bf16_rne(float f) {
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-  return __builtin_bit_cast(__bf16, (uint16_t)u);
-}
+// FP32 -> BF16, round to nearest even: gfx950 converts two values per
+// instruction (v_cvt_pk_bf16_f32), which the compiler forms from adjacent
+// conversions
+__device__ __forceinline__ __bf16 to_bf16_rne(float f) { return (__bf16)f; }
 
 // element offset of (row, k) in an unpadded swizzled LDS tile of kKT columns
 __device__ __forceinline__ int swz(int row, int k) {

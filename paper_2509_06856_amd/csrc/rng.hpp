@@ -38,11 +38,32 @@ struct Words {
   uint64_t w[4];
 };
 
+// The 128-bit product a * b.  On the device it is built from 32 x 32 -> 64-bit
+// multiply-adds (v_mad_u64_u32, whose scalar destination is the carry out of
+// the 64-bit add): with a = a1 2^32 + a0 and b = b1 2^32 + b0,
+//   t1 = a0 b1 + hi32(a0 b0)      (cannot overflow),
+//   s  = a1 b0 + t1               (its carry c is kept),
+//   lo = lo32(s) 2^32 + lo32(a0 b0),  hi = a1 b1 + (c 2^32 + hi32(s)).
+// The compiler's own lowering splits s into 32-bit halves and spends register
+// moves and a 64-bit add on them.
 __host__ __device__ __forceinline__ void mulhilo(uint64_t a, uint64_t b, uint64_t& hi,
                                                  uint64_t& lo) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p0 = (uint64_t)a0 * b0;
+  const uint64_t t1 = (uint64_t)a0 * b1 + (p0 >> 32);
+  uint64_t s, c;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(s), "=s"(c) : "v"(a1), "v"(b0), "v"(t1));
+  uint32_t cbit;
+  asm("v_cndmask_b32_e64 %0, 0, 1, %1" : "=v"(cbit) : "s"(c));
+  lo = (s << 32) | (p0 & 0xffffffffu);
+  hi = (uint64_t)a1 * b1 + ((s >> 32) | ((uint64_t)cbit << 32));
+#else
   unsigned __int128 p = (unsigned __int128)a * b;
   lo = (uint64_t)p;
   hi = (uint64_t)(p >> 64);
+#endif
 }
 
 // Philox4x64-10 state between rounds: counter words and key.
