@@ -853,17 +853,21 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
   const int wc = gauss_tile_cols(d + 1, blockIdx.y);  // columns of this block's tiles
   const int64_t steps = j_end > j_begin ? ceil_div(j_end - j_begin, kKT) : 0;
-  if (steps == 0) return;  // the whole block: no barrier is left waiting
   const bool mfma_wave = wave < kMW;
   const int gt = threadIdx.x - 64 * kMW;  // generator thread index
-  // step 0's tiles
-  if (mfma_wave) {
-    gauss_copy_step(tcol + (j_begin / kKT) * (wc * kKT), wc, Ws[0], wave, lane);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
-    gauss_gen_step(seed, stream, k0, j_begin + gt % kKT, j_end, gt, Gs[0]);
+  // step 0's tiles.  A split past the last data row (the rounding of the
+  // split length can leave the last ones empty) runs no step but still
+  // writes its zero partials; steps is the same for the whole block, so
+  // every wave meets the same barriers.
+  if (steps > 0) {
+    if (mfma_wave) {
+      gauss_copy_step(tcol + (j_begin / kKT) * (wc * kKT), wc, Ws[0], wave, lane);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else {
+      gauss_gen_step(seed, stream, k0, j_begin + gt % kKT, j_end, gt, Gs[0]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (mfma_wave) {
     const int rh = wave & 1;   // 32-row half: two 16-row tiles
     const int cq = wave >> 1;  // quarter of the 36 16-column tiles

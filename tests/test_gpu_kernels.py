@@ -278,13 +278,13 @@ def test_gaussian_sketch_parity(G, dtype):
 
 
 @pytest.mark.parametrize("N,d", [(3000, 37), (2500, 200), (1500, 520), (1200, 575), (1200, 576),
-                                 (1500, 700)])
+                                 (1500, 700), (1100, 1024)])
 def test_gaussian_sketch_bf16_mfma_parity(G, N, d):
     # BF16 operands (G and [X|Y] rounded to nearest even), FP32 accumulation on
     # the matrix cores; compared with the oracle on the same rounded operands.
     # Staged tiles hold the 32-column tiles with data: 64 columns at d = 37,
     # every column in one block up to d = 575, two column blocks from d = 576
-    # (576 + 32 columns) and at d = 700 (576 + 128 columns)
+    # (576 + 32 columns), at d = 700 (576 + 128) and at d = 1024 (576 + 480)
     g = np.random.default_rng(6 + d)
     X = g.standard_normal((N, d)).astype(np.float32)
     Y = g.standard_normal(N).astype(np.float32)
