@@ -134,10 +134,12 @@ def measure_kernels(G, torch, X, Y, m, r, seed):
     out = {}
     xbytes = X.numel() * X.element_size()
     sink = torch.empty(1 << 16, dtype=torch.int32, device=X.device)
-    t = time_calls(torch, lambda: G.debug_bandwidth(0, X, sink), reps=5)
+    # the ceilings are what a bare stream reaches at best: the fastest of
+    # three rounds of 20 launches each
+    t = min(time_calls(torch, lambda: G.debug_bandwidth(0, X, sink), reps=20) for _ in range(3))
     out["stream_read_GBs"] = xbytes / t / 1e9
     Z = torch.empty_like(X)
-    t = time_calls(torch, lambda: G.debug_bandwidth(1, X, Z), reps=5)
+    t = min(time_calls(torch, lambda: G.debug_bandwidth(1, X, Z), reps=20) for _ in range(3))
     out["stream_copy_GBs"] = 2 * xbytes / t / 1e9
     del Z
     torch.cuda.empty_cache()
