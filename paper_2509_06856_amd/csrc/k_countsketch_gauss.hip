@@ -41,33 +41,133 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64
 
 constexpr int kHistLds = 8192;  // Hessian buckets counted in LDS up to this many
 
-// bucket sizes of the largest level and of S_hat
-template <bool LDS_H>
+// bucket sizes of the largest level and (HAT) of S_hat
+template <bool LDS_H, bool HAT>
 __global__ __launch_bounds__(kThreads) void cs_count_kernel(int64_t n, uint64_t seed,
                                                             uint64_t mK_mask, int64_t r,
                                                             int* __restrict__ cntK,
                                                             int* __restrict__ cntH) {
-  __shared__ int hist[LDS_H ? kHistLds : 1];
-  if constexpr (LDS_H) {
+  __shared__ int hist[LDS_H && HAT ? kHistLds : 1];
+  if constexpr (LDS_H && HAT) {
     for (int k = threadIdx.x; k < r; k += kThreads) hist[k] = 0;
     __syncthreads();
   }
   for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kThreads) {
-    uint64_t h, hh;
-    int sg, sh;
+    uint64_t h;
+    int sg;
     rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
-    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
     atomicAdd(cntK + h, 1);
-    if constexpr (LDS_H)
-      atomicAdd(hist + hh, 1);
-    else
-      atomicAdd(cntH + hh, 1);
+    if constexpr (HAT) {
+      uint64_t hh;
+      int sh;
+      rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+      if constexpr (LDS_H)
+        atomicAdd(hist + hh, 1);
+      else
+        atomicAdd(cntH + hh, 1);
+    }
   }
-  if constexpr (LDS_H) {
+  if constexpr (LDS_H && HAT) {
     __syncthreads();
     for (int k = threadIdx.x; k < r; k += kThreads)
       if (hist[k]) atomicAdd(cntH + k, hist[k]);
+  }
+}
+
+// The Hessian buckets' lists in row order, without atomics on their (hot)
+// cursors: wave w owns the contiguous rows [w C, (w + 1) C).  It counts its
+// rows per bucket; a scan over the waves of every bucket gives each wave the
+// first slot of its rows in every bucket; the wave then lists its rows in
+// order, 64 at a time (a row's place among the batch's rows of its bucket
+// comes from comparing buckets across the lanes).  Up to kHistLds buckets.
+constexpr int kHatWaves = 1024;
+
+// per wave: its rows' counts per bucket (cntW row w), and the bucket sizes
+// (integer sums: the order of the additions does not matter)
+__global__ __launch_bounds__(64) void cs_hat_count_kernel(int64_t n, int64_t chunk, uint64_t seed,
+                                                          int64_t r, int* __restrict__ cntW,
+                                                          int* __restrict__ cntH) {
+  __shared__ int hist[kHistLds];
+  for (int k = threadIdx.x; k < r; k += 64) hist[k] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 64) {
+    uint64_t hh;
+    int sh;
+    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+    atomicAdd(hist + hh, 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < r; k += 64) {
+    const int c = hist[k];
+    cntW[(int64_t)blockIdx.x * r + k] = c;
+    if (c) atomicAdd(cntH + k, c);
+  }
+}
+
+// per bucket: the first slot of every wave's rows (in place over the counts).
+// A block takes 64 buckets; its 16 waves each sum a sixteenth of the waves'
+// rows (lanes on consecutive buckets: coalesced), the sixteen partial sums
+// are scanned in LDS, then every wave writes its rows' running starts.
+constexpr int kColTile = 64;
+__global__ __launch_bounds__(1024) void cs_hat_colscan_kernel(int64_t r, int waves,
+                                                              int* __restrict__ cntW,
+                                                              const int* __restrict__ offH) {
+  __shared__ int part[16][kColTile];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * kColTile + lane;
+  const int per = (waves + 15) / 16;
+  const int w0 = g * per, w1 = min(waves, w0 + per);
+  int t = 0;
+  if (k < r)
+    for (int w = w0; w < w1; ++w) t += cntW[(int64_t)w * r + k];
+  part[g][lane] = t;
+  __syncthreads();
+  if (k < r) {
+    int run = offH[k];
+    for (int h = 0; h < g; ++h) run += part[h][lane];
+    for (int w = w0; w < w1; ++w) {
+      const int c = cntW[(int64_t)w * r + k];
+      cntW[(int64_t)w * r + k] = run;
+      run += c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void cs_hat_fill_kernel(int64_t n, int64_t chunk, uint64_t seed,
+                                                         int64_t r, int bits,
+                                                         const int* __restrict__ offW,
+                                                         int* __restrict__ listH) {
+  __shared__ int cur[kHistLds];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < r; k += 64) cur[k] = offW[(int64_t)blockIdx.x * r + k];
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t jb = j0; jb < j1; jb += 64) {
+    const int64_t j = jb + lane;
+    int hh = -1, sh = 1;
+    if (j < j1) {
+      uint64_t b;
+      rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, b, sh);
+      hh = (int)b;
+    }
+    // lanes with the same bucket: one ballot per bucket bit, and the valid lanes
+    uint64_t same = __ballot(hh >= 0);
+    for (int b = 0; b < bits; ++b) {
+      const uint64_t ones = __ballot((hh >> b) & 1);
+      same &= ((hh >> b) & 1) ? ones : ~ones;
+    }
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    const int before = __popcll(same & below);
+    const int after = __popcll(same & ~below & ~(uint64_t(1) << lane));
+    if (hh >= 0) {
+      // every lane reads its cursor before any lane writes one (one wave:
+      // its LDS accesses take effect in program order)
+      const int slot = cur[hh] + before;
+      listH[slot] = sh > 0 ? (int)j : ~(int)j;
+      if (after == 0) cur[hh] = slot + 1;  // the batch's last row in this bucket
+    }
   }
 }
 
@@ -143,7 +243,9 @@ __global__ void scan_carry_kernel(int* __restrict__ out, int64_t n, const int* _
   if (i < n) out[i] += totals[i / kScanTile];
 }
 
-// list every row in its two buckets: entry = j, or ~j when the sign is -1
+// list every row in its bucket of the largest level (and, HAT, of S_hat):
+// entry = j, or ~j when the sign is -1
+template <bool HAT>
 __global__ __launch_bounds__(kThreads) void cs_fill_kernel(int64_t n, uint64_t seed, uint64_t mK_mask,
                                                            int64_t r, int* __restrict__ curK,
                                                            int* __restrict__ listK,
@@ -151,12 +253,100 @@ __global__ __launch_bounds__(kThreads) void cs_fill_kernel(int64_t n, uint64_t s
                                                            int* __restrict__ listH) {
   for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kThreads) {
-    uint64_t h, hh;
-    int sg, sh;
+    uint64_t h;
+    int sg;
     rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
-    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
     listK[atomicAdd(curK + h, 1)] = sg > 0 ? (int)j : ~(int)j;
-    listH[atomicAdd(curH + hh, 1)] = sh > 0 ? (int)j : ~(int)j;
+    if constexpr (HAT) {
+      uint64_t hh;
+      int sh;
+      rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+      listH[atomicAdd(curH + hh, 1)] = sh > 0 ? (int)j : ~(int)j;
+    }
+  }
+}
+
+// The fill claims slots with atomics, so the order of a bucket's rows varies
+// from run to run, and with it the rounding of the bucket's sum.  Sorting
+// every bucket's entries by row index afterwards makes the lists, and every
+// sum over them, the same on every run.  An entry is j or ~j (negative sign).
+__device__ __forceinline__ int cs_row(int e) { return e < 0 ? ~e : e; }
+
+// one thread per bucket: insertion sort in place (the largest level's buckets
+// hold about N / m_K rows, two on average)
+__global__ void cs_sort_small_kernel(int64_t nb, const int* __restrict__ off, int* __restrict__ list) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nb;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int a = off[k], b = off[k + 1];
+    for (int i = a + 1; i < b; ++i) {
+      const int e = list[i];
+      const int key = cs_row(e);
+      int p = i - 1;
+      while (p >= a && cs_row(list[p]) > key) {
+        list[p + 1] = list[p];
+        --p;
+      }
+      list[p + 1] = e;
+    }
+  }
+}
+
+// One block per bucket: a sorting network whose compare-exchanges all put the
+// smaller key at the lower index (each merge first compares mirrored
+// positions, then halves), so the length need not be a power of 2: missing
+// positions act as +infinity and never move.  Segments up to kSortLds entries
+// are sorted in LDS, longer ones in place in global memory.
+constexpr int kSortLds = 16384;
+constexpr int kSortThreads = 1024;
+
+// LOCAL: v is in LDS, where a wave's accesses take effect in program order,
+// so the sub-steps that stay inside one wave's 128 positions (t <= 128: the
+// wave's 64 consecutive pairs) need no block barrier.
+template <bool LOCAL, typename P>
+__device__ __forceinline__ void cs_block_sort(P v, int len) {
+  int span = 1;
+  while (span < len) span <<= 1;
+  for (int s = 2; s <= span; s <<= 1) {
+    for (int t = s, lh = __builtin_ctz((unsigned)s) - 1; t >= 2; t >>= 1, --lh) {
+      const bool sync = !LOCAL || t > 128;
+      if (sync) __syncthreads();
+      // first sub-step of a merge of size s: mirrored pairs; then half-cleaners
+      // (pair q: block q >> lh of t positions, offset q mod t / 2 in it)
+      const int half = t >> 1;
+      for (int q = threadIdx.x; q < span / 2; q += kSortThreads) {
+        const int r = q & (half - 1);
+        const int i = ((q >> lh) << (lh + 1)) + r;
+        const int l = (t == s) ? i - r + t - 1 - r : i + half;
+        if (l < len) {
+          const int x = v[i], y = v[l];
+          if (cs_row(x) > cs_row(y)) {
+            v[i] = y;
+            v[l] = x;
+          }
+        }
+      }
+      if (sync) __syncthreads();
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSortThreads) void cs_sort_large_kernel(int64_t nb,
+                                                                     const int* __restrict__ off,
+                                                                     int* __restrict__ list) {
+  __shared__ int tile[kSortLds];
+  for (int64_t k = blockIdx.x; k < nb; k += gridDim.x) {
+    const int a = off[k], len = off[k + 1] - a;
+    if (len <= 1) continue;
+    if (len <= kSortLds) {
+      for (int i = threadIdx.x; i < len; i += kSortThreads) tile[i] = list[a + i];
+      __syncthreads();
+      cs_block_sort<true>(tile, len);
+      for (int i = threadIdx.x; i < len; i += kSortThreads) list[a + i] = tile[i];
+      __syncthreads();
+    } else {
+      cs_block_sort<false>(list + a, len);
+    }
   }
 }
 
@@ -997,6 +1187,9 @@ void copy_i32(const int* src, int* dst, int64_t n, hipStream_t s) {
 // Scratch of the bucket lists, carved from CountSketchArgs::scratch.
 struct CsScratch {
   int *cntK, *offK, *listK, *cntH, *offH, *listH, *totals;
+  int* cntW;  // per (wave, Hessian bucket) counts, then first slots (row-order fill)
+  int waves;
+  int64_t chunk;
   void* partH;
   size_t bytes;
 };
@@ -1022,6 +1215,16 @@ CsScratch cs_scratch(const CountSketchArgs& a) {
   c.listH = reinterpret_cast<int*>(take(sizeof(int) * a.N));
   c.totals = reinterpret_cast<int*>(take(sizeof(int) * ntiles));
   c.partH = parts > 1 ? take(es * (size_t)a.r * parts * (a.d + 1)) : nullptr;
+  // the Hessian lists in row order when their counts fit in a wave's LDS
+  c.waves = 0;
+  c.chunk = 0;
+  c.cntW = nullptr;
+  if (a.r <= kHistLds) {
+    const int64_t w = std::min<int64_t>(kHatWaves, ceil_div(std::max<int64_t>(a.N, 1), 64));
+    c.chunk = round_up(ceil_div(std::max<int64_t>(a.N, 1), w), 64);
+    c.waves = (int)ceil_div(std::max<int64_t>(a.N, 1), c.chunk);
+    c.cntW = reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * a.r));
+  }
   c.bytes = o;
   return c;
 }
@@ -1144,19 +1347,39 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
   fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
   const unsigned rb = (unsigned)grid1(a.N);
-  if (a.r <= kHistLds)
-    cs_count_kernel<true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.cntH);
-  else
-    cs_count_kernel<false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.cntH);
+  const bool rows_in_order = sc.cntW != nullptr;  // the Hessian lists filled per wave
+  if (rows_in_order) {
+    cs_count_kernel<false, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r,
+                                                          sc.cntK, sc.cntH);
+    cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
+                                                          sc.cntH);
+  } else {
+    cs_count_kernel<false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r,
+                                                         sc.cntK, sc.cntH);
+  }
   SLSE_LAUNCH_CHECK();
   // 2. offsets; the counts become the fill cursors
   scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
   scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
   copy_i32(sc.offK, sc.cntK, mK, s);
-  copy_i32(sc.offH, sc.cntH, a.r, s);
-  // 3. lists
-  cs_fill_kernel<<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK, sc.listK,
-                                         sc.cntH, sc.listH);
+  // 3. lists; then every bucket's rows in increasing order, so that the lists
+  //    and every sum over them are the same on every run
+  if (rows_in_order) {
+    cs_hat_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves,
+                                                                            sc.cntW, sc.offH);
+    cs_fill_kernel<false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK,
+                                                  sc.listK, nullptr, nullptr);
+    cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
+                                                         ilog2_exact(a.r), sc.cntW, sc.listH);
+  } else {
+    copy_i32(sc.offH, sc.cntH, a.r, s);
+    cs_fill_kernel<true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK,
+                                                 sc.listK, sc.cntH, sc.listH);
+    cs_sort_large_kernel<<<(unsigned)std::min<int64_t>(a.r, 65535), kSortThreads, 0, s>>>(
+        a.r, sc.offH, sc.listH);
+  }
+  SLSE_LAUNCH_CHECK();
+  cs_sort_small_kernel<<<grid1(mK), 256, 0, s>>>(mK, sc.offK, sc.listK);
   SLSE_LAUNCH_CHECK();
   // 4. gathers: the largest level and up to three below it straight into A,
   //    S_hat through its parts
