@@ -279,16 +279,19 @@ def test_checkpoint_fields_are_checked(G):
     assert not beta.cpu().numpy().any()
 
 
-@pytest.mark.parametrize("kind", ["srht", "countsketch", "gaussian"])
+@pytest.mark.parametrize("kind,N,r", [("srht", 20000, 300), ("gaussian", 20000, 300),
+                                      ("countsketch", 20000, 300),
+                                      ("countsketch", 300000, 24),    # ~12500 rows a bucket, in parts
+                                      ("countsketch", 60000, 9000)])  # the fallback past 8192 buckets
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_sketches_are_bit_reproducible(G, kind, dtype):
+def test_sketches_are_bit_reproducible(G, kind, N, r, dtype):
     # the same call twice gives the same bits: every reduction runs in a fixed
-    # order (the CountSketch bucket lists are sorted by row after their atomic fill)
+    # order (the CountSketch bucket lists are in row order)
     g = np.random.default_rng(5)
-    N, d = 20000, 40
+    d = 16
     X = dev(g.standard_normal((N, d)).astype(dtype))
     Y = dev(g.standard_normal(N).astype(dtype))
-    m, r = [256, 512, 1024, 4096], 300
+    m = [256, 512, 1024, 4096]
     bf16 = kind == "gaussian" and dtype == np.float32
     A1, H1, _ = G.sketch_apply(X, Y, kind, 21, m, r, bf16=bf16)
     A2, H2, _ = G.sketch_apply(X, Y, kind, 21, m, r, bf16=bf16)
