@@ -19,6 +19,7 @@
 // summed in split order by a second kernel.  FP64 data accumulates in FP64,
 // FP32 data in FP32.
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.hpp"
 #include "rng.hpp"
@@ -41,8 +42,8 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64
 
 constexpr int kHistLds = 8192;  // Hessian buckets counted in LDS up to this many
 
-// bucket sizes of the largest level and (HAT) of S_hat
-template <bool LDS_H, bool HAT>
+// bucket sizes of the largest level (DO_K) and of S_hat (HAT)
+template <bool LDS_H, bool HAT, bool DO_K = true>
 __global__ __launch_bounds__(kThreads) void cs_count_kernel(int64_t n, uint64_t seed,
                                                             uint64_t mK_mask, int64_t r,
                                                             int* __restrict__ cntK,
@@ -54,10 +55,12 @@ __global__ __launch_bounds__(kThreads) void cs_count_kernel(int64_t n, uint64_t 
   }
   for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kThreads) {
-    uint64_t h;
-    int sg;
-    rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
-    atomicAdd(cntK + h, 1);
+    if constexpr (DO_K) {
+      uint64_t h;
+      int sg;
+      rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+      atomicAdd(cntK + h, 1);
+    }
     if constexpr (HAT) {
       uint64_t hh;
       int sh;
@@ -132,6 +135,122 @@ __global__ __launch_bounds__(1024) void cs_hat_colscan_kernel(int64_t r, int wav
       cntW[(int64_t)w * r + k] = run;
       run += c;
     }
+  }
+}
+
+// The largest level's lists by a stable two-pass counting sort of the rows
+// on their bucket h(j) (low digit, then high digit of at most kDigitBits
+// bits each), each pass in the per-wave scheme above: every wave owns a
+// contiguous range of positions, counts it per digit, a scan over the waves
+// of every digit gives it its first slots, and it writes its positions in
+// order.  The result lists every bucket's rows in increasing row order with
+// no atomic slot claims.
+constexpr int kDigitBits = 11;
+constexpr int kDigits = 1 << kDigitBits;
+
+// the rank of this lane among the batch's lanes with the same digit, and
+// whether it is the last of them (one ballot per digit bit)
+__device__ __forceinline__ void digit_rank(int dg, bool valid, int bits, int& before, bool& last) {
+  const int lane = threadIdx.x & 63;
+  uint64_t same = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const uint64_t ones = __ballot((dg >> b) & 1);
+    same &= ((dg >> b) & 1) ? ones : ~ones;
+  }
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  before = __popcll(same & below);
+  last = (same & ~below & ~(uint64_t(1) << lane)) == 0;
+}
+
+// PASS 0 draws the rows' buckets (digit = low bits); PASS 1 reads the first
+// pass's keys (digit = the bits above shift)
+template <int PASS>
+__global__ __launch_bounds__(64) void cs_digit_count_kernel(int64_t n, int64_t chunk, uint64_t seed,
+                                                            uint64_t mK_mask, int shift, int bits,
+                                                            const int* __restrict__ keys,
+                                                            int* __restrict__ cntW,
+                                                            int* __restrict__ tot) {
+  __shared__ int hist[kDigits];
+  const int nd = 1 << bits;
+  for (int k = threadIdx.x; k < nd; k += 64) hist[k] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 64) {
+    int key;
+    if constexpr (PASS == 0) {
+      uint64_t h;
+      int sg;
+      rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+      key = (int)h;
+    } else {
+      key = keys[j];
+    }
+    atomicAdd(hist + ((key >> shift) & (nd - 1)), 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nd; k += 64) {
+    const int c = hist[k];
+    cntW[(int64_t)blockIdx.x * nd + k] = c;
+    if (c) atomicAdd(tot + k, c);
+  }
+}
+
+// PASS 0: writes (bucket, entry) of every row in low-digit order; PASS 1:
+// moves them into high-digit order, writing the entries (the lists) and the
+// buckets in the final order
+template <int PASS>
+__global__ __launch_bounds__(64) void cs_digit_fill_kernel(int64_t n, int64_t chunk, uint64_t seed,
+                                                           uint64_t mK_mask, int shift, int bits,
+                                                           const int* __restrict__ offW,
+                                                           const int* __restrict__ keys_in,
+                                                           const int* __restrict__ vals_in,
+                                                           int* __restrict__ keys_out,
+                                                           int* __restrict__ vals_out) {
+  __shared__ int cur[kDigits];
+  const int lane = threadIdx.x;
+  const int nd = 1 << bits;
+  for (int k = lane; k < nd; k += 64) cur[k] = offW[(int64_t)blockIdx.x * nd + k];
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t jb = j0; jb < j1; jb += 64) {
+    const int64_t j = jb + lane;
+    const bool valid = j < j1;
+    int key = 0, val = 0;
+    if (valid) {
+      if constexpr (PASS == 0) {
+        uint64_t h;
+        int sg;
+        rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+        key = (int)h;
+        val = sg > 0 ? (int)j : ~(int)j;
+      } else {
+        key = keys_in[j];
+        val = vals_in[j];
+      }
+    }
+    const int dg = (key >> shift) & (nd - 1);
+    int before;
+    bool last;
+    digit_rank(dg, valid, bits, before, last);
+    if (valid) {
+      // every lane reads its cursor before any lane writes one (one wave)
+      const int slot = cur[dg] + before;
+      keys_out[slot] = key;
+      vals_out[slot] = val;
+      if (last) cur[dg] = slot + 1;
+    }
+  }
+}
+
+// bucket starts from the bucket-sorted keys: position i starts every bucket
+// in (key[i-1], key[i]], and the buckets past the last key start at n
+__global__ void cs_starts_kernel(int64_t n, int64_t nb, const int* __restrict__ keys,
+                                 int* __restrict__ off) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+    const int64_t hi = i == n ? nb : (int64_t)keys[i];
+    for (int64_t k = lo; k <= hi; ++k) off[k] = (int)i;
   }
 }
 
@@ -243,9 +362,9 @@ __global__ void scan_carry_kernel(int* __restrict__ out, int64_t n, const int* _
   if (i < n) out[i] += totals[i / kScanTile];
 }
 
-// list every row in its bucket of the largest level (and, HAT, of S_hat):
-// entry = j, or ~j when the sign is -1
-template <bool HAT>
+// list every row in its bucket of the largest level (DO_K) and of S_hat
+// (HAT): entry = j, or ~j when the sign is -1
+template <bool HAT, bool DO_K = true>
 __global__ __launch_bounds__(kThreads) void cs_fill_kernel(int64_t n, uint64_t seed, uint64_t mK_mask,
                                                            int64_t r, int* __restrict__ curK,
                                                            int* __restrict__ listK,
@@ -253,10 +372,12 @@ __global__ __launch_bounds__(kThreads) void cs_fill_kernel(int64_t n, uint64_t s
                                                            int* __restrict__ listH) {
   for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kThreads) {
-    uint64_t h;
-    int sg;
-    rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
-    listK[atomicAdd(curK + h, 1)] = sg > 0 ? (int)j : ~(int)j;
+    if constexpr (DO_K) {
+      uint64_t h;
+      int sg;
+      rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+      listK[atomicAdd(curK + h, 1)] = sg > 0 ? (int)j : ~(int)j;
+    }
     if constexpr (HAT) {
       uint64_t hh;
       int sh;
@@ -1187,9 +1308,12 @@ void copy_i32(const int* src, int* dst, int64_t n, hipStream_t s) {
 // Scratch of the bucket lists, carved from CountSketchArgs::scratch.
 struct CsScratch {
   int *cntK, *offK, *listK, *cntH, *offH, *listH, *totals;
-  int* cntW;  // per (wave, Hessian bucket) counts, then first slots (row-order fill)
+  int* cntW;  // per (wave, bucket or digit) counts, then first slots (row-order fills)
   int waves;
   int64_t chunk;
+  bool radix;                    // the largest level's lists by the counting sort
+  int *keysA, *valsA, *keysB;    // its passes' buckets and entries
+  int *dtot, *doff;              // per-digit totals and their scan
   void* partH;
   size_t bytes;
 };
@@ -1215,15 +1339,23 @@ CsScratch cs_scratch(const CountSketchArgs& a) {
   c.listH = reinterpret_cast<int*>(take(sizeof(int) * a.N));
   c.totals = reinterpret_cast<int*>(take(sizeof(int) * ntiles));
   c.partH = parts > 1 ? take(es * (size_t)a.r * parts * (a.d + 1)) : nullptr;
-  // the Hessian lists in row order when their counts fit in a wave's LDS
-  c.waves = 0;
-  c.chunk = 0;
-  c.cntW = nullptr;
-  if (a.r <= kHistLds) {
-    const int64_t w = std::min<int64_t>(kHatWaves, ceil_div(std::max<int64_t>(a.N, 1), 64));
-    c.chunk = round_up(ceil_div(std::max<int64_t>(a.N, 1), w), 64);
-    c.waves = (int)ceil_div(std::max<int64_t>(a.N, 1), c.chunk);
-    c.cntW = reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * a.r));
+  // per-wave row ranges: the Hessian lists in row order when their counts fit
+  // in a wave's LDS; the largest level's by the counting sort when its
+  // buckets take at most two digits
+  const int64_t w = std::min<int64_t>(kHatWaves, ceil_div(std::max<int64_t>(a.N, 1), 64));
+  c.chunk = round_up(ceil_div(std::max<int64_t>(a.N, 1), w), 64);
+  c.waves = (int)ceil_div(std::max<int64_t>(a.N, 1), c.chunk);
+  const bool hat_rows = a.r <= kHistLds;
+  c.radix = ilog2_exact(mK) <= 2 * kDigitBits;
+  const int64_t cols = std::max<int64_t>(hat_rows ? a.r : 0, c.radix ? kDigits : 0);
+  c.cntW = cols ? reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * cols)) : nullptr;
+  c.keysA = c.valsA = c.keysB = c.dtot = c.doff = nullptr;
+  if (c.radix) {
+    c.keysA = reinterpret_cast<int*>(take(sizeof(int) * a.N));
+    c.valsA = reinterpret_cast<int*>(take(sizeof(int) * a.N));
+    c.keysB = reinterpret_cast<int*>(take(sizeof(int) * a.N));
+    c.dtot = reinterpret_cast<int*>(take(sizeof(int) * (kDigits + 1)));
+    c.doff = reinterpret_cast<int*>(take(sizeof(int) * (kDigits + 1)));
   }
   c.bytes = o;
   return c;
@@ -1343,43 +1475,69 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   for (int i = 0; i < a.K; ++i) rows_A += a.m[i];
   const int64_t mK = a.m[a.K - 1];
   const CsScratch sc = cs_scratch(a);
-  // 1. bucket sizes
-  fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
-  fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
   const unsigned rb = (unsigned)grid1(a.N);
-  const bool rows_in_order = sc.cntW != nullptr;  // the Hessian lists filled per wave
-  if (rows_in_order) {
-    cs_count_kernel<false, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r,
-                                                          sc.cntK, sc.cntH);
-    cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
-                                                          sc.cntH);
+  const uint64_t mK_mask = (uint64_t)mK - 1;
+  // 1. the largest level's lists, every bucket's rows in increasing row order
+  // (SLSE_CS_SORT=0 takes the atomic fill and per-list sort for measurement)
+  bool radix = sc.radix;
+  if (const char* e = std::getenv("SLSE_CS_SORT")) radix = radix && std::atoi(e) != 0;
+  if (radix) {
+    const int p = ilog2_exact(mK);
+    const int b0 = std::min(p, kDigitBits), b1 = p - b0;
+    const unsigned cs = (unsigned)ceil_div(kDigits, kColTile);
+    auto digits = [&](int shift, int bits) {  // counts, their scan, every wave's first slots
+      fill_kernel<int><<<grid1(kDigits), 256, 0, s>>>(sc.dtot, 1, kDigits, kDigits);
+      if (shift == 0)
+        cs_digit_count_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(
+            a.N, sc.chunk, a.seed, mK_mask, 0, bits, nullptr, sc.cntW, sc.dtot);
+      else
+        cs_digit_count_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
+            a.N, sc.chunk, a.seed, mK_mask, shift, bits, sc.keysA, sc.cntW, sc.dtot);
+      scan_exclusive(sc.dtot, sc.doff, int64_t(1) << bits, sc.totals, s);
+      cs_hat_colscan_kernel<<<cs, 1024, 0, s>>>(int64_t(1) << bits, sc.waves, sc.cntW, sc.doff);
+    };
+    digits(0, b0);
+    int* k0 = b1 ? sc.keysA : sc.keysB;
+    int* v0 = b1 ? sc.valsA : sc.listK;
+    cs_digit_fill_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, mK_mask, 0, b0,
+                                                              sc.cntW, nullptr, nullptr, k0, v0);
+    if (b1) {
+      digits(b0, b1);
+      cs_digit_fill_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
+          a.N, sc.chunk, a.seed, mK_mask, b0, b1, sc.cntW, sc.keysA, sc.valsA, sc.keysB, sc.listK);
+    }
+    cs_starts_kernel<<<grid1(a.N + 1), 256, 0, s>>>(a.N, mK, sc.keysB, sc.offK);
   } else {
-    cs_count_kernel<false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r,
-                                                         sc.cntK, sc.cntH);
+    fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
+    cs_count_kernel<false, false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
+                                                                nullptr);
+    scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
+    copy_i32(sc.offK, sc.cntK, mK, s);
+    cs_fill_kernel<false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
+                                                        sc.listK, nullptr, nullptr);
+    cs_sort_small_kernel<<<grid1(mK), 256, 0, s>>>(mK, sc.offK, sc.listK);
   }
   SLSE_LAUNCH_CHECK();
-  // 2. offsets; the counts become the fill cursors
-  scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
-  scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
-  copy_i32(sc.offK, sc.cntK, mK, s);
-  // 3. lists; then every bucket's rows in increasing order, so that the lists
-  //    and every sum over them are the same on every run
-  if (rows_in_order) {
+  // 2. the Hessian buckets' lists, in row order too
+  fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
+  if (a.r <= kHistLds) {
+    cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
+                                                          sc.cntH);
+    scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
     cs_hat_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves,
                                                                             sc.cntW, sc.offH);
-    cs_fill_kernel<false><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK,
-                                                  sc.listK, nullptr, nullptr);
     cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
                                                          ilog2_exact(a.r), sc.cntW, sc.listH);
   } else {
+    cs_count_kernel<false, true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
+                                                                sc.cntH);
+    scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
     copy_i32(sc.offH, sc.cntH, a.r, s);
-    cs_fill_kernel<true><<<rb, kThreads, 0, s>>>(a.N, a.seed, (uint64_t)mK - 1, a.r, sc.cntK,
-                                                 sc.listK, sc.cntH, sc.listH);
+    cs_fill_kernel<true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
+                                                        nullptr, sc.cntH, sc.listH);
     cs_sort_large_kernel<<<(unsigned)std::min<int64_t>(a.r, 65535), kSortThreads, 0, s>>>(
         a.r, sc.offH, sc.listH);
   }
-  SLSE_LAUNCH_CHECK();
-  cs_sort_small_kernel<<<grid1(mK), 256, 0, s>>>(mK, sc.offK, sc.listK);
   SLSE_LAUNCH_CHECK();
   // 4. gathers: the largest level and up to three below it straight into A,
   //    S_hat through its parts

@@ -296,3 +296,21 @@ def test_sketches_are_bit_reproducible(G, kind, N, r, dtype):
     A1, H1, _ = G.sketch_apply(X, Y, kind, 21, m, r, bf16=bf16)
     A2, H2, _ = G.sketch_apply(X, Y, kind, 21, m, r, bf16=bf16)
     assert torch.equal(A1, A2) and torch.equal(H1, H2)
+
+
+@pytest.mark.parametrize("N,m", [(20000, [256, 512, 1024, 2048]),       # one digit
+                                 (70001, [1024, 4096, 16384, 32768]),   # two digits, ragged N
+                                 (1 << 20, [4096, 1 << 17, 1 << 18, 1 << 19])])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_countsketch_sorted_lists_match_sorted_atomic_lists(G, N, m, dtype, monkeypatch):
+    # the largest level's lists by the counting sort and by atomic slot claims
+    # sorted afterwards hold the same rows in the same (row) order, so both
+    # routes give the same sketch bit for bit
+    g = np.random.default_rng(11)
+    d = 24
+    X = dev(g.standard_normal((N, d)).astype(dtype))
+    Y = dev(g.standard_normal(N).astype(dtype))
+    A1, H1, _ = G.sketch_apply(X, Y, "countsketch", 8, m, 200)
+    monkeypatch.setenv("SLSE_CS_SORT", "0")
+    A2, H2, _ = G.sketch_apply(X, Y, "countsketch", 8, m, 200)
+    assert torch.equal(A1, A2) and torch.equal(H1, H2)
