@@ -985,7 +985,7 @@ __global__ void gauss_reduce_kernel(const Acc* __restrict__ part, int splits, in
 //
 // The generation of G (Philox4x64-10 and Box-Muller, about 350 VALU
 // instructions per 8 entries) is the largest cost, so the waves specialise:
-// on every SIMD two waves generate G and two run the MFMAs.  A wave issues
+// on every SIMD one wave generates G and one runs the MFMAs.  A wave issues
 // in order, so a wave that did both would leave the matrix core idle while it
 // generates and the VALU idle while it multiplies; with one job per wave the
 // SIMD issues the MFMAs of some waves between the VALU instructions of the
@@ -1008,22 +1008,24 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // 64 sketch rows x 576 columns per block (every column of a d <= 575 problem
-// in one block, so G is generated once), 64 data rows per step.  Sixteen
-// waves, four per SIMD: 8 MFMA waves, each two 16-row tiles x nine 16-column
-// tiles of v_mfma_f32_16x16x32_bf16 (18 accumulators of four registers), and
-// 8 generator waves, one Philox block per thread per step.  Two generator
-// waves per SIMD: one wave issues at most one VALU instruction every few
-// cycles, and the VALU keeps up with two.
+// in one block, so G is generated once), 64 data rows per step.  Eight
+// waves, two per SIMD: 4 MFMA waves, each all four 16-row tiles x nine
+// 16-column tiles of v_mfma_f32_16x16x32_bf16 (36 accumulators of four
+// registers; every [X|Y] element is read from LDS by one wave only), and 4
+// generator waves, two Philox blocks per thread per step with their rounds
+// interleaved (two independent chains keep one wave's VALU issue busy).
 constexpr int kMT = 64;             // sketch rows per block
 constexpr int kNT = 576;            // columns per block
 constexpr int kKT = 64;             // data rows per step: 8 chunks of 8 per LDS row
-constexpr int kMW = 8;              // MFMA waves: 2 row halves x 4 column quarters
-constexpr int kGW = 8;              // generator waves
+constexpr int kMW = 4;              // MFMA waves: 4 column quarters of all 64 rows
+constexpr int kGW = 4;              // generator waves
+constexpr int kRT = 4;              // 16-row tiles per MFMA wave
 constexpr int kGThreads = 64 * (kMW + kGW);
-constexpr int kRT = 2;              // 16-row tiles per MFMA wave
-constexpr int kCT = kNT / 16 / 4;   // 16-column tiles per MFMA wave (9)
+constexpr int kRH = kMT / (16 * kRT);  // row groups of MFMA waves
+constexpr int kCQ = kMW / kRH;         // column groups of MFMA waves
+constexpr int kCT = kNT / 16 / kCQ;    // 16-column tiles per MFMA wave (9)
 constexpr int kGB = kMT / 8 * kKT / (64 * kGW);  // Philox blocks per generator thread per step
-static_assert(kRT * 16 * 2 == kMT && kCT * 16 * 4 == kNT, "MFMA waves tile the block");
+static_assert(kRH * kCQ == kMW && kCT * 16 * kCQ == kNT, "MFMA waves tile the block");
 static_assert(kGB * 64 * kGW == kMT / 8 * kKT, "whole Philox blocks per generator thread");
 static_assert((2 * kNT + 2 * kMT) * kKT * 2 <= 163840, "two [X|Y] tiles and two G tiles fit in LDS");
 
@@ -1156,13 +1158,14 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t k0 = (int64_t)blockIdx.x * kMT;
-  const int c0 = blockIdx.y * kNT;
   const int split = blockIdx.z;
+  const int cblk = blockIdx.y;
+  const int c0 = cblk * kNT;
   const int64_t per = round_up(ceil_div(N, (int64_t)splits), kKT);
   const int64_t j_begin = (int64_t)split * per;
   const int64_t j_end = min(N, j_begin + per);
-  const __bf16* tcol = tiles + (int64_t)blockIdx.y * nchunks * (kNT * kKT);
-  const int wc = gauss_tile_cols(d + 1, blockIdx.y);  // columns of this block's tiles
+  const __bf16* tcol = tiles + (int64_t)cblk * nchunks * (kNT * kKT);
+  const int wc = gauss_tile_cols(d + 1, cblk);  // columns of this block's tiles
   const int64_t steps = j_end > j_begin ? ceil_div(j_end - j_begin, kKT) : 0;
   const bool mfma_wave = wave < kMW;
   const int gt = threadIdx.x - 64 * kMW;  // generator thread index
@@ -1180,8 +1183,8 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
     __syncthreads();
   }
   if (mfma_wave) {
-    const int rh = wave & 1;   // 32-row half: two 16-row tiles
-    const int cq = wave >> 1;  // quarter of the 36 16-column tiles
+    const int rh = wave % kRH;  // row group: kRT 16-row tiles
+    const int cq = wave / kRH;  // column group: kCT 16-column tiles
     f32x4_t acc[kRT][kCT];
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
@@ -1202,10 +1205,11 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
         bf16x8_t a[kRT];
 #pragma unroll
         for (int i = 0; i < kRT; ++i)
-          a[i] = *reinterpret_cast<const bf16x8_t*>(&Gb[swz(rh * 32 + i * 16 + (lane & 15), kk)]);
+          a[i] = *reinterpret_cast<const bf16x8_t*>(&Gb[swz(rh * 16 * kRT + i * 16 + (lane & 15), kk)]);
 #pragma unroll
         for (int q = 0; q < kCT; ++q) {
-          // tiles past [X|Y] multiply stale LDS and are never stored
+          // tiles past [X|Y] multiply stale LDS and are never stored (a
+          // wave-uniform skip measured slower: it splits the unrolled loop)
           const int col = (cq * kCT + q) * 16 + (lane & 15);
           const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&Wb[swz(col, kk)]);
 #pragma unroll
@@ -1222,7 +1226,7 @@ __global__ __launch_bounds__(kGThreads) void gauss_mfma_kernel(int64_t N, int d,
       for (int q = 0; q < kCT; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t k = k0 + rh * 32 + i * 16 + 4 * (lane >> 4) + r;
+          const int64_t k = k0 + rh * 16 * kRT + i * 16 + 4 * (lane >> 4) + r;
           const int t = cq * kCT + q;
           const int col = c0 + t * 16 + (lane & 15);
           if (k < m && col <= d && t * 16 < wc)
@@ -1589,7 +1593,8 @@ void gaussian_mfma(const GaussianArgs& a, hipStream_t s) {
   }
   // blockIdx.x is the sketch-row block: the blocks that read the same data
   // rows and columns run side by side and share them through the caches
-  dim3 grid((unsigned)ceil_div(a.m, kMT), (unsigned)ceil_div(cols, kNT), (unsigned)a.splits);
+  const int ncb = (int)ceil_div(cols, kNT);
+  dim3 grid((unsigned)ceil_div(a.m, kMT), (unsigned)ncb, (unsigned)a.splits);
   gauss_mfma_kernel<<<grid, kGThreads, 0, s>>>(a.N, a.d, tiles, nchunks, a.seed, a.stream_id, a.m,
                                                a.splits, part, ldp);
   SLSE_LAUNCH_CHECK();
