@@ -52,7 +52,8 @@ inline size_t dtype_size(slse_dtype t) {
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-inline int ilog2_exact(int64_t v) {
+// smallest p with 2^p >= v (the exact log for a power of 2)
+inline int ilog2_ceil(int64_t v) {
   int p = 0;
   while ((int64_t(1) << p) < v) ++p;
   return p;

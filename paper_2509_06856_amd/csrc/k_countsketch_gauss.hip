@@ -1350,7 +1350,7 @@ CsScratch cs_scratch(const CountSketchArgs& a) {
   c.chunk = round_up(ceil_div(std::max<int64_t>(a.N, 1), w), 64);
   c.waves = (int)ceil_div(std::max<int64_t>(a.N, 1), c.chunk);
   const bool hat_rows = a.r <= kHistLds;
-  c.radix = ilog2_exact(mK) <= 2 * kDigitBits;
+  c.radix = ilog2_ceil(mK) <= 2 * kDigitBits;
   const int64_t cols = std::max<int64_t>(hat_rows ? a.r : 0, c.radix ? kDigits : 0);
   c.cntW = cols ? reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * cols)) : nullptr;
   c.keysA = c.valsA = c.keysB = c.dtot = c.doff = nullptr;
@@ -1452,10 +1452,10 @@ void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, int top, hipStrea
       continue;
     }
     const int64_t mT = a.m[Tl];
-    const int lgR = ilog2_exact(a.m[S] / mT);
+    const int lgR = ilog2_ceil(a.m[S] / mT);
     FoldTargets tg;
     for (int k = 0; k < 10; ++k) tg.off[k] = -1;
-    for (int i = Tl; i < S; ++i) tg.off[ilog2_exact(a.m[i] / mT)] = off[i];
+    for (int i = Tl; i < S; ++i) tg.off[ilog2_ceil(a.m[i] / mT)] = off[i];
     const int64_t blocks = mT * n_ct;
     if (blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "countsketch: too many fold work items");
     const int64_t xq = blocks / 8;
@@ -1486,7 +1486,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   bool radix = sc.radix;
   if (const char* e = std::getenv("SLSE_CS_SORT")) radix = radix && std::atoi(e) != 0;
   if (radix) {
-    const int p = ilog2_exact(mK);
+    const int p = ilog2_ceil(mK);
     const int b0 = std::min(p, kDigitBits), b1 = p - b0;
     const unsigned cs = (unsigned)ceil_div(kDigits, kColTile);
     auto digits = [&](int shift, int bits) {  // counts, their scan, every wave's first slots
@@ -1531,7 +1531,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
     cs_hat_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves,
                                                                             sc.cntW, sc.offH);
     cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
-                                                         ilog2_exact(a.r), sc.cntW, sc.listH);
+                                                         ilog2_ceil(a.r), sc.cntW, sc.listH);
   } else {
     cs_count_kernel<false, true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
                                                                 sc.cntH);

@@ -207,7 +207,7 @@ SketchShape make_sketch_shape(slse_sketch_kind kind, int64_t N, int64_t d, const
   s.offset.resize(K);
   s.scale.resize(K);
   if (kind == SLSE_SRHT) {
-    s.p = std::max(1, ilog2_exact(N));
+    s.p = std::max(1, ilog2_ceil(N));
     require(s.p <= 30, "N too large for this build (N' <= 2^30)");
     s.n_pad = int64_t(1) << s.p;
     require(s.m[K - 1] <= s.n_pad && r <= s.n_pad, "SRHT: m_K and r must be <= N'");
@@ -1025,7 +1025,7 @@ slse_status ihs_impl(slse_ctx* ctx, const slse_problem* p, const slse_params* q,
   // the fields IHS reads, with one unused nested level of the power of 2 >= r
   slse_params qq = *q;
   qq.K = 1;
-  qq.m[0] = int64_t(1) << ilog2_exact(std::max<int64_t>(q->r, 1));
+  qq.m[0] = int64_t(1) << ilog2_ceil(std::max<int64_t>(q->r, 1));
   qq.a[0] = 0;
   qq.mu = 1.0;
   qq.eta = 0.0;
@@ -2287,7 +2287,7 @@ slse_status slse_paper_schedule(int64_t N, int64_t d, int64_t m1_factor, int64_t
     require(d >= 1 && N > d && m1_factor >= 1, "need N > d >= 1 and m1_factor >= 1");
     require(d <= (int64_t(1) << 40) / m1_factor, "m1_factor * d too large");
     // m_1: the power of 2 at or above m1_factor * d; m_K: the power of 2 at or below N / 2
-    const int64_t m1 = int64_t(1) << ilog2_exact(m1_factor * d);
+    const int64_t m1 = int64_t(1) << ilog2_ceil(m1_factor * d);
     int64_t mk = 1;
     while (mk * 2 <= N / 2) mk *= 2;
     require(N / 2 >= 1 && m1 <= mk, "empty schedule: m_1 > N/2");
