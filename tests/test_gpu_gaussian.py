@@ -24,6 +24,8 @@ import torch
 from oracle import rng as R
 from oracle import sketch as S
 
+from bounds import bf16_uncertain
+
 pytestmark = pytest.mark.gpu
 
 U64 = 2.0 ** -53
@@ -41,18 +43,6 @@ def G():
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-
-
-def _bf16_uncertain(g64, delta):
-    """Entries whose FP64 value lies within delta of a BF16 rounding midpoint,
-    and the BF16 ulp at each entry."""
-    f = g64.astype(np.float32)
-    u = f.view(np.uint32)
-    lo = (u & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
-    mid = (u & np.uint32(0xFFFF0000) | np.uint32(0x8000)).view(np.float32).astype(np.float64)
-    hi_bits = (u & np.uint32(0xFFFF0000)) + np.uint32(0x10000)
-    ulp = np.abs(hi_bits.view(np.float32).astype(np.float64) - lo)
-    return np.abs(np.abs(g64) - np.abs(mid)) <= delta, ulp
 
 
 def _ranges(N, splits, bf16):
@@ -94,7 +84,7 @@ def _case(G, N, d, m, r, form, seed=88, drop_rows=64, check_drop=True):
             delta = 2.0 ** -16 * (1.0 + np.abs(g64))
             if bf16:
                 gq = S.round_to(g64, "bf16")
-                unc, ulp = _bf16_uncertain(g64, delta)
+                unc, ulp = bf16_uncertain(g64, delta)
                 extra += (np.where(unc, ulp, 0.0)) @ Wabs[j]
             else:
                 gq = g64
