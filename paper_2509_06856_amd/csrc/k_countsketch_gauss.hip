@@ -557,12 +557,13 @@ struct FamilyTargets {
   int64_t off[4];  // off[l]: first row (in A) of level K - l, l = 0..L
 };
 
-template <typename T, int VEC, int L>
+template <typename T, int VEC, int L, int CH>
 __global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
     int64_t mf, int d, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y,
     const int* __restrict__ off, const int* __restrict__ list, T* __restrict__ A, int64_t lda,
     FamilyTargets tg, bool a_vec) {
   constexpr int B = 1 << L;
+  constexpr int U = 8 / CH;  // rows per batch: eight loads in flight
   const int lane = threadIdx.x & 63;
   for (int64_t f = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); f < mf;
        f += (int64_t)gridDim.x * kWaves) {
@@ -582,14 +583,15 @@ __global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
       st[q] = E;
       E += __shfl(len, q, 64);
     }
-    for (int c0 = 0; c0 < d; c0 += 64 * VEC) {
-      const int col = c0 + lane * VEC;
-      const bool whole = col + VEC <= d;
-      T acc[B][VEC];
+    // CH chunks of 64 VEC columns per pass: a row's chunks are loaded together
+    for (int c0 = 0; c0 < d; c0 += 64 * VEC * CH) {
+      T acc[CH][B][VEC];
 #pragma unroll
-      for (int q = 0; q < B; ++q)
+      for (int h = 0; h < CH; ++h)
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[q][v] = (T)0;
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[h][q][v] = (T)0;
       for (int r0 = 0; r0 < E; r0 += 64) {
         // lane e of this round holds entry r0 + e and its bucket
         const int e = r0 + lane;
@@ -603,39 +605,45 @@ __global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
           }
         const int ent = e < E ? list[oq + (e - sq)] : 0;
         const int n = min(64, E - r0);
-        for (int u0 = 0; u0 < n; u0 += 8) {
-          T x[8][VEC];
-          int qu[8];
+        for (int u0 = 0; u0 < n; u0 += U) {
+          T x[U][CH][VEC];
+          int qu[U];
           int neg = 0;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < U; ++u) {
             const bool ok = u0 + u < n;
             const int eu = __shfl(ent, (u0 + u) & 63, 64);
             qu[u] = ok ? __shfl(qe, (u0 + u) & 63, 64) : -1;
             const int64_t j = eu < 0 ? (int64_t)~eu : (int64_t)eu;
             neg |= (eu < 0 ? 1 : 0) << u;
-            const T* xr = X + j * ldx + col;
-            if (ok && whole) {
-              if constexpr (VEC > 1) {
-                typedef T V __attribute__((ext_vector_type(VEC)));
-                const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) x[u][v] = t[v];
+            for (int h = 0; h < CH; ++h) {
+              const int col = c0 + h * 64 * VEC + lane * VEC;
+              const T* xr = X + j * ldx + col;
+              if (ok && col + VEC <= d) {
+                if constexpr (VEC > 1) {
+                  typedef T V __attribute__((ext_vector_type(VEC)));
+                  const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
+#pragma unroll
+                  for (int v = 0; v < VEC; ++v) x[u][h][v] = t[v];
+                } else {
+                  x[u][h][0] = __builtin_nontemporal_load(xr);
+                }
               } else {
-                x[u][0] = __builtin_nontemporal_load(xr);
-              }
-            } else {
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) x[u][v] = (ok && col + v < d) ? xr[v] : (T)0;
+                for (int v = 0; v < VEC; ++v) x[u][h][v] = (ok && col + v < d) ? xr[v] : (T)0;
+              }
             }
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+          for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int q = 0; q < B; ++q)
 #pragma unroll
-              for (int v = 0; v < VEC; ++v)
-                if (qu[u] == q) acc[q][v] += ((neg >> u) & 1) ? -x[u][v] : x[u][v];
+              for (int h = 0; h < CH; ++h)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v)
+                  if (qu[u] == q) acc[h][q][v] += ((neg >> u) & 1) ? -x[u][h][v] : x[u][h][v];
         }
       }
       // level K, then the halvings down to level K - L
@@ -647,25 +655,31 @@ __global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
           for (int q = 0; q < (B >> 1); ++q)
             if (q < nq)
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) acc[q][v] += acc[q + nq][v];
+              for (int h = 0; h < CH; ++h)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[h][q][v] += acc[h][q + nq][v];
         }
 #pragma unroll
         for (int q = 0; q < B; ++q) {
           if (q >= nq) continue;
           T* orow = A + (tg.off[l] + f + (int64_t)q * mf) * lda;
-          if constexpr (VEC > 1) {
-            if (a_vec && whole) {
-              typedef T V __attribute__((ext_vector_type(VEC)));
-              V t;
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) t[v] = acc[q][v];
-              *reinterpret_cast<V*>(orow + col) = t;
-              continue;
+          for (int h = 0; h < CH; ++h) {
+            const int col = c0 + h * 64 * VEC + lane * VEC;
+            if constexpr (VEC > 1) {
+              if (a_vec && col + VEC <= d) {
+                typedef T V __attribute__((ext_vector_type(VEC)));
+                V t;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) t[v] = acc[h][q][v];
+                *reinterpret_cast<V*>(orow + col) = t;
+                continue;
+              }
             }
-          }
 #pragma unroll
-          for (int v = 0; v < VEC; ++v)
-            if (col + v < d) orow[col + v] = acc[q][v];
+            for (int v = 0; v < VEC; ++v)
+              if (col + v < d) orow[col + v] = acc[h][q][v];
+          }
         }
       }
     }
@@ -1408,19 +1422,26 @@ void gather_family(int L, const CountSketchArgs& a, const int* off, const int* l
   constexpr int V = 16 / sizeof(T);
   const bool vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((a.ldx * (int64_t)sizeof(T)) % 16 == 0);
   const bool a_vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((a.lda * (int64_t)sizeof(T)) % 16 == 0);
-#define SLSE_FAMILY(VV, LL)                                                                   \
-  cs_gather_family_kernel<T, VV, LL><<<blocks, kThreads, 0, s>>>(mf, a.d, X, a.ldx, Y, off, list, \
-                                                                 A, a.lda, tg, a_vec)
-  if (vec) {
-    if (L == 3) SLSE_FAMILY(V, 3);
-    else if (L == 2) SLSE_FAMILY(V, 2);
-    else if (L == 1) SLSE_FAMILY(V, 1);
-    else SLSE_FAMILY(V, 0);
+#define SLSE_FAMILY(VV, LL, CC)                                                                 \
+  cs_gather_family_kernel<T, VV, LL, CC><<<blocks, kThreads, 0, s>>>(mf, a.d, X, a.ldx, Y, off,   \
+                                                                     list, A, a.lda, tg, a_vec)
+  // rows wider than one chunk of 64 V columns: two chunks of a row per pass
+  const bool two = a.d > 64 * V;
+  if (vec && two) {
+    if (L == 3) SLSE_FAMILY(V, 3, 2);
+    else if (L == 2) SLSE_FAMILY(V, 2, 2);
+    else if (L == 1) SLSE_FAMILY(V, 1, 2);
+    else SLSE_FAMILY(V, 0, 2);
+  } else if (vec) {
+    if (L == 3) SLSE_FAMILY(V, 3, 1);
+    else if (L == 2) SLSE_FAMILY(V, 2, 1);
+    else if (L == 1) SLSE_FAMILY(V, 1, 1);
+    else SLSE_FAMILY(V, 0, 1);
   } else {
-    if (L == 3) SLSE_FAMILY(1, 3);
-    else if (L == 2) SLSE_FAMILY(1, 2);
-    else if (L == 1) SLSE_FAMILY(1, 1);
-    else SLSE_FAMILY(1, 0);
+    if (L == 3) SLSE_FAMILY(1, 3, 1);
+    else if (L == 2) SLSE_FAMILY(1, 2, 1);
+    else if (L == 1) SLSE_FAMILY(1, 1, 1);
+    else SLSE_FAMILY(1, 0, 1);
   }
 #undef SLSE_FAMILY
   SLSE_LAUNCH_CHECK();
