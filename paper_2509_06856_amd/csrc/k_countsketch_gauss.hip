@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kSortThreads) void cs_sort_large_kernel(int64_t nb,
 // [off[b] + p len / P, off[b] + (p + 1) len / P), len = off[b+1] - off[b].
 // One wave per (bucket, part); a lane holds VEC columns of a 64 VEC-column
 // chunk, eight list entries in flight.
-template <typename T, int VEC>
+template <typename T, int VEC, int CH>
 __global__ __launch_bounds__(kThreads) void cs_gather_kernel(int64_t nb, int parts, int d,
                                                              const T* __restrict__ X, int64_t ldx,
                                                              const T* __restrict__ Y,
@@ -492,44 +492,56 @@ __global__ __launch_bounds__(kThreads) void cs_gather_kernel(int64_t nb, int par
     const int e0 = o0 + (int)((int64_t)len * p / parts);
     const int e1 = o0 + (int)((int64_t)len * (p + 1) / parts);
     T* orow = out + w * ldo;
-    for (int c0 = 0; c0 < d; c0 += 64 * VEC) {
-      const int col = c0 + lane * VEC;
-      T acc[VEC];
+    // CH chunks of 64 VEC columns per pass: a row's chunks are loaded together
+    constexpr int U = 8 / CH;  // list entries per batch: eight loads in flight
+    for (int c0 = 0; c0 < d; c0 += 64 * VEC * CH) {
+      T acc[CH][VEC];
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) acc[v] = 0;
-      const bool whole = col + VEC <= d;
-      for (int e = e0; e < e1; e += 8) {
-        T x[8][VEC];
+      for (int h = 0; h < CH; ++h)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[h][v] = 0;
+      for (int e = e0; e < e1; e += U) {
+        T x[U][CH][VEC];
         int neg = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
           const int ent = e + u < e1 ? list[e + u] : 0;
           const bool ok = e + u < e1;
           const int64_t j = ent < 0 ? (int64_t)~ent : (int64_t)ent;
           neg |= (ent < 0 ? 1 : 0) << u;
-          const T* xr = X + j * ldx + col;
-          if (ok && whole) {
-            if constexpr (VEC > 1) {
-              typedef T V __attribute__((ext_vector_type(VEC)));
-              const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) x[u][v] = t[v];
+          for (int h = 0; h < CH; ++h) {
+            const int col = c0 + h * 64 * VEC + lane * VEC;
+            const T* xr = X + j * ldx + col;
+            if (ok && col + VEC <= d) {
+              if constexpr (VEC > 1) {
+                typedef T V __attribute__((ext_vector_type(VEC)));
+                const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(xr));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) x[u][h][v] = t[v];
+              } else {
+                x[u][h][0] = __builtin_nontemporal_load(xr);
+              }
             } else {
-              x[u][0] = __builtin_nontemporal_load(xr);
-            }
-          } else {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) x[u][v] = (ok && col + v < d) ? xr[v] : (T)0;
+              for (int v = 0; v < VEC; ++v) x[u][h][v] = (ok && col + v < d) ? xr[v] : (T)0;
+            }
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v] += ((neg >> u) & 1) ? -x[u][v] : x[u][v];
+          for (int h = 0; h < CH; ++h)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[h][v] += ((neg >> u) & 1) ? -x[u][h][v] : x[u][h][v];
       }
 #pragma unroll
-      for (int v = 0; v < VEC; ++v)
-        if (col + v < d) orow[col + v] = acc[v];
+      for (int h = 0; h < CH; ++h) {
+        const int col = c0 + h * 64 * VEC + lane * VEC;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if (col + v < d) orow[col + v] = acc[h][v];
+      }
     }
     // the Y column: lanes split the list, then a wave sum in lane order
     T yacc = 0;
@@ -1396,10 +1408,12 @@ void gather(int64_t nb, int parts, const CountSketchArgs& a, const int* off, con
   const T* Y = static_cast<const T*>(a.Y);
   constexpr int V = 16 / sizeof(T);
   const bool vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((a.ldx * (int64_t)sizeof(T)) % 16 == 0);
-  if (vec)
-    cs_gather_kernel<T, V><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
+  if (vec && a.d > 64 * V)  // rows wider than one chunk: two chunks of a row per pass
+    cs_gather_kernel<T, V, 2><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
+  else if (vec)
+    cs_gather_kernel<T, V, 1><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
   else
-    cs_gather_kernel<T, 1><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
+    cs_gather_kernel<T, 1, 1><<<blocks, kThreads, 0, s>>>(nb, parts, a.d, X, a.ldx, Y, off, list, out, ldo);
   SLSE_LAUNCH_CHECK();
 }
 
