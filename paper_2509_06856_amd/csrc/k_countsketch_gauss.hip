@@ -772,7 +772,9 @@ __global__ void cs_fold_kernel(const T* __restrict__ src, T* __restrict__ dst, i
 // halves them down to one row; after the halving to s rows, the level of
 // s mT rows (when the schedule has it) gets rows g + q mT, q < s.  Work
 // items are dealt to the XCDs in contiguous runs, so the column tiles of one
-// group (the same rows) run back to back on one XCD.
+// group (the same rows) run back to back on one XCD.  The LDS tile is sized
+// for the R rows at launch: a small R leaves room for many blocks per CU,
+// whose loads are then in flight together.
 constexpr int kFoldMax = 512;  // source rows per group
 template <typename T, int VEC>
 struct FoldVec {
@@ -793,7 +795,8 @@ __global__ __launch_bounds__(256) void cs_fold_tree_kernel(const T* __restrict__
                                                            int64_t xcd_q, FoldTargets tg) {
   constexpr int CT = 128 / (int)sizeof(T);  // columns per tile (128 bytes)
   constexpr int NV = CT / VEC;              // vectors per row segment
-  __shared__ __attribute__((aligned(16))) T tile[kFoldMax * CT];
+  extern __shared__ __attribute__((aligned(16))) char fold_lds[];  // R x CT values
+  T* tile = reinterpret_cast<T*>(fold_lds);
   int64_t bid = blockIdx.x;
   if (xcd_q > 0 && bid < 8 * xcd_q) bid = (bid & 7) * xcd_q + (bid >> 3);
   const int ct = (int)(bid % n_ct);
@@ -1494,12 +1497,13 @@ void fold_levels(const CountSketchArgs& a, T* A, int64_t offK, int top, hipStrea
     const int64_t blocks = mT * n_ct;
     if (blocks > 0x7fffffffLL) fail(SLSE_EUNSUPPORTED, "countsketch: too many fold work items");
     const int64_t xq = blocks / 8;
+    const size_t lds = (size_t)(int64_t(1) << lgR) * CT * sizeof(T);  // at most 64 KiB
     if (vec)
-      cs_fold_tree_kernel<T, 16 / sizeof(T)><<<(unsigned)blocks, 256, 0, s>>>(
+      cs_fold_tree_kernel<T, 16 / sizeof(T)><<<(unsigned)blocks, 256, lds, s>>>(
           A + off[S] * a.lda, A, a.lda, mT, lgR, cols, n_ct, xq, tg);
     else
-      cs_fold_tree_kernel<T, 1><<<(unsigned)blocks, 256, 0, s>>>(A + off[S] * a.lda, A, a.lda, mT,
-                                                                 lgR, cols, n_ct, xq, tg);
+      cs_fold_tree_kernel<T, 1><<<(unsigned)blocks, 256, lds, s>>>(A + off[S] * a.lda, A, a.lda, mT,
+                                                                   lgR, cols, n_ct, xq, tg);
     SLSE_LAUNCH_CHECK();
     S = Tl;
   }
