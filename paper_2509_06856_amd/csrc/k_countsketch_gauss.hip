@@ -175,17 +175,23 @@ __global__ __launch_bounds__(64) void cs_digit_count_kernel(int64_t n, int64_t c
   for (int k = threadIdx.x; k < nd; k += 64) hist[k] = 0;
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += 64) {
-    int key;
-    if constexpr (PASS == 0) {
+  if constexpr (PASS == 0) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 64) {
       uint64_t h;
       int sg;
       rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
-      key = (int)h;
-    } else {
-      key = keys[j];
+      atomicAdd(hist + (((int)h >> shift) & (nd - 1)), 1);
     }
-    atomicAdd(hist + ((key >> shift) & (nd - 1)), 1);
+  } else {
+    // four rows per thread per round, their loads in flight together
+    for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256) {
+      int key[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) key[u] = jb + 64 * u < j1 ? keys[jb + 64 * u] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (key[u] >= 0) atomicAdd(hist + ((key[u] >> shift) & (nd - 1)), 1);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nd; k += 64) {
