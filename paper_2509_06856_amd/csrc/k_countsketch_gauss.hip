@@ -147,6 +147,7 @@ __global__ __launch_bounds__(1024) void cs_hat_colscan_kernel(int64_t r, int wav
 // no atomic slot claims.
 constexpr int kDigitBits = 11;
 constexpr int kDigits = 1 << kDigitBits;
+constexpr int64_t kRadixRows = int64_t(1) << 21;  // the sort pays off from here (measured)
 
 // the rank of this lane among the batch's lanes with the same digit, and
 // whether it is the last of them (one ballot per digit bit)
@@ -1526,10 +1527,12 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   const CsScratch sc = cs_scratch(a);
   const unsigned rb = (unsigned)grid1(a.N);
   const uint64_t mK_mask = (uint64_t)mK - 1;
-  // 1. the largest level's lists, every bucket's rows in increasing row order
-  // (SLSE_CS_SORT=0 takes the atomic fill and per-list sort for measurement)
-  bool radix = sc.radix;
-  if (const char* e = std::getenv("SLSE_CS_SORT")) radix = radix && std::atoi(e) != 0;
+  // 1. the largest level's lists, every bucket's rows in increasing row order:
+  // by the counting sort from 2^21 rows, below that by atomic slot claims and
+  // a sort of each list (fewer launches; the two give the same lists).
+  // SLSE_CS_SORT=1 / 0 forces one of them, for measurement and tests.
+  bool radix = sc.radix && a.N >= kRadixRows;
+  if (const char* e = std::getenv("SLSE_CS_SORT")) radix = sc.radix && std::atoi(e) != 0;
   if (radix) {
     const int p = ilog2_ceil(mK);
     const int b0 = std::min(p, kDigitBits), b1 = p - b0;

@@ -310,6 +310,7 @@ def test_countsketch_sorted_lists_match_sorted_atomic_lists(G, N, m, dtype, monk
     d = 24
     X = dev(g.standard_normal((N, d)).astype(dtype))
     Y = dev(g.standard_normal(N).astype(dtype))
+    monkeypatch.setenv("SLSE_CS_SORT", "1")
     A1, H1, _ = G.sketch_apply(X, Y, "countsketch", 8, m, 200)
     monkeypatch.setenv("SLSE_CS_SORT", "0")
     A2, H2, _ = G.sketch_apply(X, Y, "countsketch", 8, m, 200)
