@@ -1591,7 +1591,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
         a.r, sc.offH, sc.listH);
   }
   SLSE_LAUNCH_CHECK();
-  // 4. gathers: the largest level and up to three below it straight into A,
+  // 3. gathers: the largest level and up to three below it straight into A,
   //    S_hat through its parts
   const int64_t offK = rows_A - mK;
   // fuse the levels below K that halve it step by step (up to three)
@@ -1609,7 +1609,7 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
                                                              a.ldah);
     SLSE_LAUNCH_CHECK();
   }
-  // 5. smaller levels by folding, several levels per pass
+  // 4. smaller levels by folding, several levels per pass
   fold_levels<T>(a, A, offK, a.K - 1 - L, s);
 }
 
