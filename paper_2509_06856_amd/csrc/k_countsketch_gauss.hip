@@ -691,7 +691,9 @@ __global__ __launch_bounds__(kThreads) void cs_gather_family_kernel(
                 V t;
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) t[v] = acc[h][q][v];
-                *reinterpret_cast<V*>(orow + col) = t;
+                // streaming stores: the levels are not read again by this
+                // pass, and keeping them out of L2 leaves it to the gathers
+                __builtin_nontemporal_store(t, reinterpret_cast<V*>(orow + col));
                 continue;
               }
             }
@@ -1133,7 +1135,7 @@ __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
       bf16x8_t w;
 #pragma unroll
       for (int r = 0; r < 8; ++r) w[r] = to_bf16_rne(v[r][i]);
-      *reinterpret_cast<bf16x8_t*>(t + (int64_t)(4 * c4 + i) * kKT + 8 * q) = w;
+      __builtin_nontemporal_store(w, reinterpret_cast<bf16x8_t*>(t + (int64_t)(4 * c4 + i) * kKT + 8 * q));
     }
   }
 }
