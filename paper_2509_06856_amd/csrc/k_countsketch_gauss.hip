@@ -1114,7 +1114,8 @@ __global__ __launch_bounds__(kStageThreads) void gauss_stage_kernel(
       // the common case: eight whole 16-byte loads, all in flight at once
       f32x4_t x[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) x[r] = *reinterpret_cast<const f32x4_t*>(X + (jq + r) * ldx + col);
+      for (int r = 0; r < 8; ++r)
+        x[r] = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(X + (jq + r) * ldx + col));
 #pragma unroll
       for (int r = 0; r < 8; ++r)
 #pragma unroll
