@@ -109,17 +109,42 @@ __global__ __launch_bounds__(64) void cs_hat_count_kernel(int64_t n, int64_t chu
   }
 }
 
-// per bucket: the first slot of every wave's rows (in place over the counts).
-// A block takes 64 buckets; its 16 waves each sum a sixteenth of the waves'
-// rows (lanes on consecutive buckets: coalesced), the sixteen partial sums
-// are scanned in LDS, then every wave writes its rows' running starts.
+// per bucket: the exclusive scan of the bucket totals (written to off, with
+// off[r] = their sum) and the first slot of every wave's rows (in place over
+// the counts).  A block takes 64 buckets: its threads first sum the totals
+// before them and one wave scans its 64; then its 16 waves each sum a
+// sixteenth of the waves' rows (lanes on consecutive buckets: coalesced), the
+// sixteen partial sums are scanned in LDS, and every wave writes its rows'
+// running starts.  Integer sums: exact in any order.
 constexpr int kColTile = 64;
-__global__ __launch_bounds__(1024) void cs_hat_colscan_kernel(int64_t r, int waves,
-                                                              int* __restrict__ cntW,
-                                                              const int* __restrict__ offH) {
+__global__ __launch_bounds__(1024) void cs_colscan_kernel(int64_t r, int waves,
+                                                          int* __restrict__ cntW,
+                                                          const int* __restrict__ tot,
+                                                          int* __restrict__ off) {
   __shared__ int part[16][kColTile];
+  __shared__ int red[16];
+  __shared__ int base[kColTile];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int64_t k = (int64_t)blockIdx.x * kColTile + lane;
+  const int64_t c0 = (int64_t)blockIdx.x * kColTile;
+  const int64_t k = c0 + lane;
+  int pre = 0;
+  for (int64_t e = threadIdx.x; e < c0; e += 1024) pre += tot[e];
+  for (int m = 32; m > 0; m >>= 1) pre += __shfl_xor(pre, m, 64);
+  if (lane == 0) red[g] = pre;
+  __syncthreads();
+  if (g == 0) {
+    int p0 = 0;
+    for (int h = 0; h < 16; ++h) p0 += red[h];
+    const int t = k < r ? tot[k] : 0;
+    int incl = t;
+    for (int m = 1; m < 64; m <<= 1) {
+      const int v = __shfl_up(incl, m, 64);
+      if (lane >= m) incl += v;
+    }
+    base[lane] = p0 + incl - t;
+    if (k < r) off[k] = p0 + incl - t;
+    if (k == r - 1) off[r] = p0 + incl;
+  }
   const int per = (waves + 15) / 16;
   const int w0 = g * per, w1 = min(waves, w0 + per);
   int t = 0;
@@ -128,7 +153,7 @@ __global__ __launch_bounds__(1024) void cs_hat_colscan_kernel(int64_t r, int wav
   part[g][lane] = t;
   __syncthreads();
   if (k < r) {
-    int run = offH[k];
+    int run = base[lane];
     for (int h = 0; h < g; ++h) run += part[h][lane];
     for (int w = w0; w < w1; ++w) {
       const int c = cntW[(int64_t)w * r + k];
@@ -1548,8 +1573,8 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
       else
         cs_digit_count_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
             a.N, sc.chunk, a.seed, mK_mask, shift, bits, sc.keysA, sc.cntW, sc.dtot);
-      scan_exclusive(sc.dtot, sc.doff, int64_t(1) << bits, sc.totals, s);
-      cs_hat_colscan_kernel<<<cs, 1024, 0, s>>>(int64_t(1) << bits, sc.waves, sc.cntW, sc.doff);
+      cs_colscan_kernel<<<cs, 1024, 0, s>>>(int64_t(1) << bits, sc.waves, sc.cntW, sc.dtot,
+                                            sc.doff);
     };
     digits(0, b0);
     int* k0 = b1 ? sc.keysA : sc.keysB;
@@ -1578,9 +1603,8 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   if (a.r <= kHistLds) {
     cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
                                                           sc.cntH);
-    scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
-    cs_hat_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves,
-                                                                            sc.cntW, sc.offH);
+    cs_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves, sc.cntW,
+                                                                        sc.cntH, sc.offH);
     cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
                                                          ilog2_ceil(a.r), sc.cntW, sc.listH);
   } else {
