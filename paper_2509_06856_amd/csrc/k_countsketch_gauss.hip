@@ -322,6 +322,88 @@ __global__ __launch_bounds__(64) void cs_hat_fill_kernel(int64_t n, int64_t chun
   }
 }
 
+// The Hessian lists and the first (low-digit) pass of the largest level's
+// counting sort in one pass over the rows: both walk the same per-wave row
+// ranges, so one kernel hashes each row once for the count and once for the
+// fill.  Count: per wave, its rows per Hessian bucket (cntW) and per low
+// digit (cntWd), and the totals of both.
+__global__ __launch_bounds__(64) void cs_lists_count_kernel(int64_t n, int64_t chunk, uint64_t seed,
+                                                            int64_t r, uint64_t mK_mask, int bits,
+                                                            int* __restrict__ cntW,
+                                                            int* __restrict__ cntH,
+                                                            int* __restrict__ cntWd,
+                                                            int* __restrict__ dtot) {
+  __shared__ int hist[kHistLds];
+  __shared__ int histd[kDigits];
+  const int nd = 1 << bits;
+  for (int k = threadIdx.x; k < r; k += 64) hist[k] = 0;
+  for (int k = threadIdx.x; k < nd; k += 64) histd[k] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 64) {
+    uint64_t hh, h;
+    int sh, sg;
+    rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, hh, sh);
+    rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+    atomicAdd(hist + hh, 1);
+    atomicAdd(histd + ((int)h & (nd - 1)), 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < r; k += 64) {
+    const int c = hist[k];
+    cntW[(int64_t)blockIdx.x * r + k] = c;
+    if (c) atomicAdd(cntH + k, c);
+  }
+  for (int k = threadIdx.x; k < nd; k += 64) {
+    const int c = histd[k];
+    cntWd[(int64_t)blockIdx.x * nd + k] = c;
+    if (c) atomicAdd(dtot + k, c);
+  }
+}
+
+// Fill: every row into its Hessian bucket's list (listH) and, by its low
+// digit, its (bucket, entry) into the first pass's order (keys_out, vals_out)
+__global__ __launch_bounds__(64) void cs_lists_fill_kernel(
+    int64_t n, int64_t chunk, uint64_t seed, int64_t r, int hbits, const int* __restrict__ offW,
+    int* __restrict__ listH, uint64_t mK_mask, int bits, const int* __restrict__ offWd,
+    int* __restrict__ keys_out, int* __restrict__ vals_out) {
+  __shared__ int cur[kHistLds];
+  __shared__ int curd[kDigits];
+  const int lane = threadIdx.x;
+  const int nd = 1 << bits;
+  for (int k = lane; k < r; k += 64) cur[k] = offW[(int64_t)blockIdx.x * r + k];
+  for (int k = lane; k < nd; k += 64) curd[k] = offWd[(int64_t)blockIdx.x * nd + k];
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t jb = j0; jb < j1; jb += 64) {
+    const int64_t j = jb + lane;
+    const bool valid = j < j1;
+    int hh = 0, sh = 1, key = 0, sg = 1;
+    if (valid) {
+      uint64_t b, h;
+      rng::cs_hash_hat(seed, (uint64_t)j, (uint64_t)r, b, sh);
+      rng::cs_hash(seed, (uint64_t)j, mK_mask, h, sg);
+      hh = (int)b;
+      key = (int)h;
+    }
+    int before, beforeD;
+    bool last, lastD;
+    digit_rank(hh, valid, hbits, before, last);
+    const int dg = key & (nd - 1);
+    digit_rank(dg, valid, bits, beforeD, lastD);
+    if (valid) {
+      // every lane reads its cursors before any lane writes one (one wave)
+      const int slot = cur[hh] + before;
+      const int slotD = curd[dg] + beforeD;
+      listH[slot] = sh > 0 ? (int)j : ~(int)j;
+      keys_out[slotD] = key;
+      vals_out[slotD] = sg > 0 ? (int)j : ~(int)j;
+      if (last) cur[hh] = slot + 1;
+      if (lastD) curd[dg] = slotD + 1;
+    }
+  }
+}
+
 // exclusive scan of n ints in three steps: per-block scans of kScanTile
 // elements with block totals, one block scanning the totals, then the carry
 constexpr int kScanTile = kThreads * 8;
@@ -1376,7 +1458,8 @@ void copy_i32(const int* src, int* dst, int64_t n, hipStream_t s) {
 // Scratch of the bucket lists, carved from CountSketchArgs::scratch.
 struct CsScratch {
   int *cntK, *offK, *listK, *cntH, *offH, *listH, *totals;
-  int* cntW;  // per (wave, bucket or digit) counts, then first slots (row-order fills)
+  int* cntW;   // per (wave, Hessian bucket) counts, then first slots (row-order fills)
+  int* cntWd;  // the same per (wave, digit) for the counting sort
   int waves;
   int64_t chunk;
   bool radix;                    // the largest level's lists by the counting sort
@@ -1415,8 +1498,8 @@ CsScratch cs_scratch(const CountSketchArgs& a) {
   c.waves = (int)ceil_div(std::max<int64_t>(a.N, 1), c.chunk);
   const bool hat_rows = a.r <= kHistLds;
   c.radix = ilog2_ceil(mK) <= 2 * kDigitBits;
-  const int64_t cols = std::max<int64_t>(hat_rows ? a.r : 0, c.radix ? kDigits : 0);
-  c.cntW = cols ? reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * cols)) : nullptr;
+  c.cntW = hat_rows ? reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * a.r)) : nullptr;
+  c.cntWd = c.radix ? reinterpret_cast<int*>(take(sizeof(int) * (size_t)c.waves * kDigits)) : nullptr;
   c.keysA = c.valsA = c.keysB = c.dtot = c.doff = nullptr;
   if (c.radix) {
     c.keysA = reinterpret_cast<int*>(take(sizeof(int) * a.N));
@@ -1561,63 +1644,78 @@ void countsketch_t(const CountSketchArgs& a, hipStream_t s) {
   // SLSE_CS_SORT=1 / 0 forces one of them, for measurement and tests.
   bool radix = sc.radix && a.N >= kRadixRows;
   if (const char* e = std::getenv("SLSE_CS_SORT")) radix = sc.radix && std::atoi(e) != 0;
-  if (radix) {
+  const bool hat_rows = a.r <= kHistLds;
+  const unsigned ncs = (unsigned)ceil_div(kDigits, kColTile);
+  auto digit_pass1 = [&](int shift, int bits) {  // high digit: counts, first slots, fill
+    fill_kernel<int><<<grid1(kDigits), 256, 0, s>>>(sc.dtot, 1, kDigits, kDigits);
+    cs_digit_count_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, mK_mask, shift,
+                                                              bits, sc.keysA, sc.cntWd, sc.dtot);
+    cs_colscan_kernel<<<ncs, 1024, 0, s>>>(int64_t(1) << bits, sc.waves, sc.cntWd, sc.dtot, sc.doff);
+    cs_digit_fill_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
+        a.N, sc.chunk, a.seed, mK_mask, shift, bits, sc.cntWd, sc.keysA, sc.valsA, sc.keysB, sc.listK);
+  };
+  if (radix && hat_rows) {
+    // the Hessian lists and the low-digit pass together, then the high digit
     const int p = ilog2_ceil(mK);
     const int b0 = std::min(p, kDigitBits), b1 = p - b0;
-    const unsigned cs = (unsigned)ceil_div(kDigits, kColTile);
-    auto digits = [&](int shift, int bits) {  // counts, their scan, every wave's first slots
-      fill_kernel<int><<<grid1(kDigits), 256, 0, s>>>(sc.dtot, 1, kDigits, kDigits);
-      if (shift == 0)
-        cs_digit_count_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(
-            a.N, sc.chunk, a.seed, mK_mask, 0, bits, nullptr, sc.cntW, sc.dtot);
-      else
-        cs_digit_count_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
-            a.N, sc.chunk, a.seed, mK_mask, shift, bits, sc.keysA, sc.cntW, sc.dtot);
-      cs_colscan_kernel<<<cs, 1024, 0, s>>>(int64_t(1) << bits, sc.waves, sc.cntW, sc.dtot,
-                                            sc.doff);
-    };
-    digits(0, b0);
-    int* k0 = b1 ? sc.keysA : sc.keysB;
-    int* v0 = b1 ? sc.valsA : sc.listK;
-    cs_digit_fill_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, mK_mask, 0, b0,
-                                                              sc.cntW, nullptr, nullptr, k0, v0);
-    if (b1) {
-      digits(b0, b1);
-      cs_digit_fill_kernel<1><<<(unsigned)sc.waves, 64, 0, s>>>(
-          a.N, sc.chunk, a.seed, mK_mask, b0, b1, sc.cntW, sc.keysA, sc.valsA, sc.keysB, sc.listK);
-    }
-    cs_starts_kernel<<<grid1(a.N + 1), 256, 0, s>>>(a.N, mK, sc.keysB, sc.offK);
-  } else {
-    fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
-    cs_count_kernel<false, false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
-                                                                nullptr);
-    scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
-    copy_i32(sc.offK, sc.cntK, mK, s);
-    cs_fill_kernel<false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
-                                                        sc.listK, nullptr, nullptr);
-    cs_sort_small_kernel<<<grid1(mK), 256, 0, s>>>(mK, sc.offK, sc.listK);
-  }
-  SLSE_LAUNCH_CHECK();
-  // 2. the Hessian buckets' lists, in row order too
-  fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
-  if (a.r <= kHistLds) {
-    cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
-                                                          sc.cntH);
+    fill_kernel<int><<<grid1(kDigits), 256, 0, s>>>(sc.dtot, 1, kDigits, kDigits);
+    fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
+    cs_lists_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, mK_mask, b0,
+                                                            sc.cntW, sc.cntH, sc.cntWd, sc.dtot);
+    cs_colscan_kernel<<<ncs, 1024, 0, s>>>(int64_t(1) << b0, sc.waves, sc.cntWd, sc.dtot, sc.doff);
     cs_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves, sc.cntW,
                                                                         sc.cntH, sc.offH);
-    cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
-                                                         ilog2_ceil(a.r), sc.cntW, sc.listH);
+    cs_lists_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(
+        a.N, sc.chunk, a.seed, a.r, ilog2_ceil(a.r), sc.cntW, sc.listH, mK_mask, b0, sc.cntWd,
+        b1 ? sc.keysA : sc.keysB, b1 ? sc.valsA : sc.listK);
+    if (b1) digit_pass1(b0, b1);
+    cs_starts_kernel<<<grid1(a.N + 1), 256, 0, s>>>(a.N, mK, sc.keysB, sc.offK);
+    SLSE_LAUNCH_CHECK();
   } else {
-    cs_count_kernel<false, true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
-                                                                sc.cntH);
-    scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
-    copy_i32(sc.offH, sc.cntH, a.r, s);
-    cs_fill_kernel<true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
-                                                        nullptr, sc.cntH, sc.listH);
-    cs_sort_large_kernel<<<(unsigned)std::min<int64_t>(a.r, 65535), kSortThreads, 0, s>>>(
-        a.r, sc.offH, sc.listH);
+    if (radix) {
+      const int p = ilog2_ceil(mK);
+      const int b0 = std::min(p, kDigitBits), b1 = p - b0;
+      fill_kernel<int><<<grid1(kDigits), 256, 0, s>>>(sc.dtot, 1, kDigits, kDigits);
+      cs_digit_count_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, mK_mask, 0,
+                                                                b0, nullptr, sc.cntWd, sc.dtot);
+      cs_colscan_kernel<<<ncs, 1024, 0, s>>>(int64_t(1) << b0, sc.waves, sc.cntWd, sc.dtot, sc.doff);
+      cs_digit_fill_kernel<0><<<(unsigned)sc.waves, 64, 0, s>>>(
+          a.N, sc.chunk, a.seed, mK_mask, 0, b0, sc.cntWd, nullptr, nullptr,
+          b1 ? sc.keysA : sc.keysB, b1 ? sc.valsA : sc.listK);
+      if (b1) digit_pass1(b0, b1);
+      cs_starts_kernel<<<grid1(a.N + 1), 256, 0, s>>>(a.N, mK, sc.keysB, sc.offK);
+    } else {
+      fill_kernel<int><<<grid1(mK), 256, 0, s>>>(sc.cntK, 1, mK, mK);
+      cs_count_kernel<false, false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
+                                                                  nullptr);
+      scan_exclusive(sc.cntK, sc.offK, mK, sc.totals, s);
+      copy_i32(sc.offK, sc.cntK, mK, s);
+      cs_fill_kernel<false, true><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, sc.cntK,
+                                                          sc.listK, nullptr, nullptr);
+      cs_sort_small_kernel<<<grid1(mK), 256, 0, s>>>(mK, sc.offK, sc.listK);
+    }
+    SLSE_LAUNCH_CHECK();
+    // 2. the Hessian buckets' lists, in row order too
+    fill_kernel<int><<<grid1(a.r), 256, 0, s>>>(sc.cntH, 1, a.r, a.r);
+    if (hat_rows) {
+      cs_hat_count_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r, sc.cntW,
+                                                            sc.cntH);
+      cs_colscan_kernel<<<(unsigned)ceil_div(a.r, kColTile), 1024, 0, s>>>(a.r, sc.waves, sc.cntW,
+                                                                          sc.cntH, sc.offH);
+      cs_hat_fill_kernel<<<(unsigned)sc.waves, 64, 0, s>>>(a.N, sc.chunk, a.seed, a.r,
+                                                           ilog2_ceil(a.r), sc.cntW, sc.listH);
+    } else {
+      cs_count_kernel<false, true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
+                                                                  sc.cntH);
+      scan_exclusive(sc.cntH, sc.offH, a.r, sc.totals, s);
+      copy_i32(sc.offH, sc.cntH, a.r, s);
+      cs_fill_kernel<true, false><<<rb, kThreads, 0, s>>>(a.N, a.seed, mK_mask, a.r, nullptr,
+                                                          nullptr, sc.cntH, sc.listH);
+      cs_sort_large_kernel<<<(unsigned)std::min<int64_t>(a.r, 65535), kSortThreads, 0, s>>>(
+          a.r, sc.offH, sc.listH);
+    }
+    SLSE_LAUNCH_CHECK();
   }
-  SLSE_LAUNCH_CHECK();
   // 3. gathers: the largest level and up to three below it straight into A,
   //    S_hat through its parts
   const int64_t offK = rows_A - mK;
