@@ -329,11 +329,10 @@ constexpr int ct_of() {
 
 // Passes of up to 10 stages exchange the whole 2^B x CT tile through LDS at
 // once (128 KB at B = 10); an 11-stage pass does it in two rounds.
-template <typename T, int B, int MODE>
+template <typename T, int B, int MODE, int CT = ct_of<T>()>
 void launch_pass(PassParams<T> P, int64_t npad, hipStream_t s) {
   constexpr int BA = (B + 1) / 2;
   constexpr int BB = B / 2;
-  constexpr int CT = ct_of<T>();
   constexpr int ROUNDS = B > 10 ? 2 : 1;
   const int64_t groups = npad >> B;
   P.n_ct = (int)(P.ldz / CT);
@@ -364,6 +363,23 @@ void dispatch_b(int b, PassParams<T> P, int64_t npad, hipStream_t s) {
     SLSE_CASE(11)
 #undef SLSE_CASE
     default: fail(SLSE_EUNSUPPORTED, "srht: bad pass size");
+  }
+}
+
+// the one-column passes of Y (two-pass transforms in group order only)
+template <typename T, int MODE>
+void dispatch_b_y(int b, PassParams<T> P, int64_t npad, hipStream_t s) {
+  switch (b) {
+#define SLSE_CASE(BV) \
+  case BV: launch_pass<T, BV, MODE, 1>(P, npad, s); break;
+    SLSE_CASE(6)
+    SLSE_CASE(7)
+    SLSE_CASE(8)
+    SLSE_CASE(9)
+    SLSE_CASE(10)
+    SLSE_CASE(11)
+#undef SLSE_CASE
+    default: fail(SLSE_EUNSUPPORTED, "srht: bad pass size for the Y passes");
   }
 }
 
@@ -474,6 +490,23 @@ void run_passes(const SrhtArgs& a, hipStream_t s) {
     dispatch_mode<T>(mode, bs[i], P, npad, s);
     s0 += bs[i];
   }
+  if (a.split_y) {
+    // Y on its own: a one-column transform with the same index maps, its
+    // workspace after X's, its sampled values into column d of A and A_hat
+    PassParams<T> Q = P;
+    Q.X = static_cast<const T*>(a.Y);  // not read: every column is past d = 0
+    Q.ldx = 1;
+    Q.d = 0;
+    Q.Z = static_cast<T*>(a.Z) + npad * a.ldz;
+    Q.ldz = 1;
+    Q.A = static_cast<T*>(a.A) + a.d;
+    Q.Ahat = static_cast<T*>(a.Ahat) + a.d;
+    Q.zb = bs.back();
+    Q.s0 = 0;
+    dispatch_b_y<T, kFirst | kGroupOrder>(bs[0], Q, npad, s);
+    Q.s0 = bs[0];
+    dispatch_b_y<T, kLast | kGroupOrder>(bs[1], Q, npad, s);
+  }
 }
 
 // Parameter records of every pass of every transform, ordered by pass round
@@ -582,9 +615,19 @@ void srht_plan(SrhtArgs& a, int prefer_bmax) {
   if (const char* e = std::getenv("SLSE_SRHT_XCD")) a.xcd_swizzle = std::atoi(e) != 0;
 }
 
+void srht_split_y(SrhtArgs& a) {
+  a.split_y = false;
+  if (const char* e = std::getenv("SLSE_SRHT_SPLIT_Y"))
+    if (std::atoi(e) == 0) return;
+  if (a.d <= 0 || a.d % a.ct != 0 || pass_sizes(a.p, a.bmax).size() != 2 || !srht_group_order())
+    return;
+  a.split_y = true;
+  a.ldz = a.d;
+}
+
 size_t srht_z_bytes(const SrhtArgs& a) {
   if (a.p <= a.bmax) return 0;  // a single pass needs no workspace
-  return (size_t)(int64_t(1) << a.p) * (size_t)a.ldz * dtype_size(a.t);
+  return (size_t)(int64_t(1) << a.p) * (size_t)(a.ldz + (a.split_y ? 1 : 0)) * dtype_size(a.t);
 }
 
 namespace {

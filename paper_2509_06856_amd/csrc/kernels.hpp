@@ -128,9 +128,14 @@ struct SrhtArgs {
   bool narrow = false;        // half-width column tiles (two blocks per CU)
   bool xcd_swizzle = true;    // contiguous work runs per XCD
   bool indices_ready = false; // pi_sgn / slotA / slotH already built (batched)
+  bool split_y = false;       // Y transformed on its own: Z = X's d columns, then N' values of Y
 };
 
 void srht_plan(SrhtArgs& a, int prefer_ct);
+// Single transforms whose X columns fill whole column tiles (d a multiple of
+// the tile) take Y through its own one-column passes instead of a tile that
+// would hold Y and padding (no-op otherwise; SLSE_SRHT_SPLIT_Y=0 disables).
+void srht_split_y(SrhtArgs& a);
 
 // Index maps of many SRHTs in two launches (rows of every job, then the r
 // Hessian samples of every job).  base/hbase: first global index of the job.

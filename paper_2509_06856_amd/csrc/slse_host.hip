@@ -269,6 +269,7 @@ void reserve_sketch(slse_ctx* ctx, const SketchShape& s, slse_dtype t, SrhtArgs*
     srht->mK = s.m[s.K - 1];
     srht->r = s.r;
     srht_plan(*srht, 0);
+    srht_split_y(*srht);
     srht->pi_sgn = ctx->arena.get_t<int32_t>("srht_pi", s.n_pad);
     srht->slotA = ctx->arena.get_t<int32_t>("srht_slotA", s.n_pad);
     srht->slotH = ctx->arena.get_t<int32_t>("srht_slotH", s.n_pad);
