@@ -315,3 +315,20 @@ def test_countsketch_sorted_lists_match_sorted_atomic_lists(G, N, m, dtype, monk
     monkeypatch.setenv("SLSE_CS_SORT", "0")
     A2, H2, _ = G.sketch_apply(X, Y, "countsketch", 8, m, 200)
     assert torch.equal(A1, A2) and torch.equal(H1, H2)
+
+
+@pytest.mark.parametrize("N,d,dtype", [(1 << 13, 64, np.float32), (9000, 32, np.float32),
+                                       (1 << 13, 48, np.float64), (1 << 12, 16, np.float64)])
+def test_srht_own_y_passes_match_the_shared_tile(G, N, d, dtype, monkeypatch):
+    # when d fills whole column tiles, Y is transformed on its own (one-column
+    # passes); every column's butterflies are the same either way, so the
+    # sketch must not change by a bit
+    g = np.random.default_rng(13)
+    X = dev(g.standard_normal((N, d)).astype(dtype))
+    Y = dev(g.standard_normal(N).astype(dtype))
+    m = [128, 256, 1024]
+    monkeypatch.setenv("SLSE_SRHT_SPLIT_Y", "1")
+    A1, H1, _ = G.sketch_apply(X, Y, "srht", 4, m, 3 * d)
+    monkeypatch.setenv("SLSE_SRHT_SPLIT_Y", "0")
+    A2, H2, _ = G.sketch_apply(X, Y, "srht", 4, m, 3 * d)
+    assert torch.equal(A1, A2) and torch.equal(H1, H2)
