@@ -125,7 +125,6 @@ struct SrhtArgs {
   int64_t ldz = 0;
   int ct = 0;                 // column tile (chosen by srht_plan)
   int bmax = 0;               // stages per pass cap
-  bool narrow = false;        // half-width column tiles (two blocks per CU)
   bool xcd_swizzle = true;    // contiguous work runs per XCD
   bool indices_ready = false; // pi_sgn / slotA / slotH already built (batched)
   bool split_y = false;       // Y transformed on its own: Z = X's d columns, then N' values of Y
