@@ -244,19 +244,18 @@ PAPER_CASES = {
 }
 
 
-def bench_paper(args, G, torch, dev):
+def paper_rows(G, torch, dev, keys):
     """The paper's own problems (Sec. 5 recipe: X = G D, D log-spaced 1..1/kappa,
     sigma^2 = 1e-8, FP64) with the schedule variants and baselines that run on
     the same kernels.  The library records the prediction error
     Delta_t = ||X (beta_t - beta)||^2 of every iterate (beta the true
     coefficients); each method is then timed, with its graph replayed, to the
     first iterate within 1% of the LS error (the smallest final Delta of the
-    methods, which all reach OLS)."""
+    methods, which all reach OLS).  Returns one record per (problem, method)."""
     from slse_inputs import paper_problem
 
     sigma2 = 1e-8
     rows = []
-    keys = args.paper_cases.split(",") if args.paper_cases else list(PAPER_CASES)
 
     def first_within(ds, target):
         return next((t for t, v in enumerate(ds) if v <= target), None)
@@ -332,6 +331,13 @@ def bench_paper(args, G, torch, dev):
             del XB
         del X, Y
         torch.cuda.empty_cache()
+    return rows
+
+
+def bench_paper(args, G, torch, dev):
+    """`--workload paper`: the table of paper_rows as its own JSON line."""
+    keys = args.paper_cases.split(",") if args.paper_cases else list(PAPER_CASES)
+    rows = paper_rows(G, torch, dev, keys)
     main = [r for r in rows if r["N"] == 1 << 22 and r["method"] == "srht"]
     main = main[0] if main else rows[0]
     out = {
@@ -547,6 +553,8 @@ def main():
     ap.add_argument("--s-cap", type=int, default=60)
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's problems (Sec. 5) that the default run appends to config")
     ap.add_argument("--no-sketches", action="store_true",
                     help="skip the sketch-kernel and device-copy measurements")
     ap.add_argument("--cpu-rows", type=int, default=1 << 18)
@@ -721,6 +729,16 @@ def main():
             log(f"cpu oracle sample: O2 {cb['t_o2']:.2f}s ({cb['s']} steps), O1 {cb['t_o1']:.2f}s "
                 f"on {n_s} rows ({cb['cores']} cores), err {cb['err']:.1e}")
 
+    paper = None
+    if not args.no_paper and name == "mixed":
+        # the paper's problems on the same library (not part of the metric):
+        # the mixed workload's data are freed first
+        del X, Y, beta_dev
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        paper = paper_rows(G, torch, dev, list(PAPER_CASES))
+        log(f"paper problems: {len(paper)} results in {time.perf_counter() - t0:.1f}s")
+
     out = {
         "metric": METRIC,
         "value": t_solve,
@@ -744,6 +762,7 @@ def main():
             "f64_form": f64,
             "mixed_vs_f64_speedup": (f64["seconds"] / t_solve) if f64 else None,
             "surrogate_stop": surrogate_stop,
+            "paper_workloads": paper,
         },
         "roofline": {
             "bound": "hbm",
