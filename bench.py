@@ -442,7 +442,7 @@ def bench_backward(args, G, torch, dev):
                                            "algorithmic_bytes": k9_bytes,
                                            "note": "s_max = 0 backward: lambda_0 = M w plus the fused pass"}},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_batched(args, G, torch, dev):
@@ -537,7 +537,13 @@ def bench_batched(args, G, torch, dev):
                      "algorithmic_bytes": moved},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def side_record(rec):
+    """A workload's record as appended to the default run's line (no CPU leg)."""
+    return {k: rec.get(k) for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline",
+                                    "kernels") if rec.get(k) is not None}
 
 
 def main():
@@ -553,8 +559,9 @@ def main():
     ap.add_argument("--s-cap", type=int, default=60)
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-paper", action="store_true",
-                    help="skip the paper's problems (Sec. 5) that the default run appends to config")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the paper's problems (Sec. 5), the backward and the batched workloads "
+                         "that the default run appends to config")
     ap.add_argument("--no-sketches", action="store_true",
                     help="skip the sketch-kernel and device-copy measurements")
     ap.add_argument("--cpu-rows", type=int, default=1 << 18)
@@ -585,9 +592,13 @@ def main():
     dev = torch.device("cuda", 0)
     name = args.workload
     if name == "batched":
-        return bench_batched(args, G, torch, dev)
+        print(json.dumps(bench_batched(args, G, torch, dev)), flush=True)
+        return
     if name == "backward":
-        return bench_backward(args, G, torch, dev)
+        rec = bench_backward(args, G, torch, dev)
+        if rec is not None:
+            print(json.dumps(rec), flush=True)
+        return
     if name == "paper":
         return bench_paper(args, G, torch, dev)
     ref = load_reference(name)
@@ -729,15 +740,32 @@ def main():
             log(f"cpu oracle sample: O2 {cb['t_o2']:.2f}s ({cb['s']} steps), O1 {cb['t_o1']:.2f}s "
                 f"on {n_s} rows ({cb['cores']} cores), err {cb['err']:.1e}")
 
-    paper = None
-    if not args.no_paper and name == "mixed":
-        # the paper's problems on the same library (not part of the metric):
+    paper = backward = batched = None
+    if not args.no_others and name == "mixed":
+        # the paper's problems, the backward and the batched workloads on the
+        # same library (not part of the metric; their own CPU legs skipped):
         # the mixed workload's data are freed first
         del X, Y, beta_dev
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
         paper = paper_rows(G, torch, dev, list(PAPER_CASES))
         log(f"paper problems: {len(paper)} results in {time.perf_counter() - t0:.1f}s")
+        side = argparse.Namespace(**{**vars(args), "no_cpu": True, "kernel_only": False})
+
+        def run_side(fn):
+            # a side workload that misses its own checks is recorded as such;
+            # the main line is still printed
+            try:
+                return side_record(fn(side, G, torch, dev))
+            except SystemExit as e:
+                return {"error": f"exited with status {e.code}"}
+            finally:
+                torch.cuda.empty_cache()
+
+        t0 = time.perf_counter()
+        backward = run_side(bench_backward)
+        batched = run_side(bench_batched)
+        log(f"backward and batched workloads in {time.perf_counter() - t0:.1f}s")
 
     out = {
         "metric": METRIC,
@@ -763,6 +791,8 @@ def main():
             "mixed_vs_f64_speedup": (f64["seconds"] / t_solve) if f64 else None,
             "surrogate_stop": surrogate_stop,
             "paper_workloads": paper,
+            "backward_workload": backward,
+            "batched_workload": batched,
         },
         "roofline": {
             "bound": "hbm",
