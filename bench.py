@@ -759,6 +759,9 @@ def main():
                 return side_record(fn(side, G, torch, dev))
             except SystemExit as e:
                 return {"error": f"exited with status {e.code}"}
+            except Exception as e:  # a library error: recorded, the main line still printed
+                print(f"{fn.__name__}: {type(e).__name__}: {e}", file=sys.stderr)
+                return {"error": f"{type(e).__name__}: {e}"}
             finally:
                 torch.cuda.empty_cache()
 
