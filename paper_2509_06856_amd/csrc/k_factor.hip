@@ -375,28 +375,6 @@ __global__ void convert_scale_batched_kernel(const FactorJob* __restrict__ jobs,
 constexpr int kGJ = 32;
 constexpr int kGJChunk = 64;  // columns (and saved rows) per panel block
 
-// In-place inverse of the 32 x 32 block held by one wave: lane c (< 32) owns
-// column c in col[0..31].  A non-positive or non-finite pivot sets *bad.
-__device__ __forceinline__ void gj_invert32(double (&col)[kGJ], int lane, bool* bad) {
-#pragma unroll
-  for (int s = 0; s < kGJ; ++s) {
-    double piv = readlane_f64(col[s], s);
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      *bad = true;
-      piv = 1.0;
-    }
-    const double inv = 1.0 / piv;
-    const double rs = (lane == s) ? inv : col[s] * inv;  // new row s in column `lane`
-#pragma unroll
-    for (int i = 0; i < kGJ; ++i) {
-      if (i == s) continue;
-      const double f = readlane_f64(col[i], s);  // old P[i][s]
-      col[i] = (lane == s) ? -f * inv : fma(-f, rs, col[i]);
-    }
-    col[s] = rs;
-  }
-}
-
 template <typename DP, typename IP>
 __device__ __forceinline__ void gj_panel(int d, int k0, DP __restrict__ G, DP __restrict__ colp,
                                          IP __restrict__ info, int bx) {
@@ -404,38 +382,105 @@ __device__ __forceinline__ void gj_panel(int d, int k0, DP __restrict__ G, DP __
   __shared__ double Rp[kGJ][kGJChunk + 1];
   const int t = threadIdx.x;
   const int kw = min(kGJ, d - k0);
-  // 1. pivot block inverse (wave 0), padded with the identity past d
-  if (t < 64) {
-    double col[kGJ];
-    const int c = t;
+  // Every thread moves a fixed number of entries in each of 1-3, so the
+  // loops have compile-time trip counts and all their loads are in flight
+  // together (a runtime-bounded loop waits for each load in turn).
+  constexpr int kP = kGJ * kGJ / 256;       // pivot-block entries per thread
+  constexpr int kC = kGJChunk * kGJ / 256;  // column- and row-panel entries per thread
+  // (loads outside the matrix read a clamped, valid address and are
+  // replaced afterwards, so that no load sits behind a branch)
+  // 1. the pivot block into LDS, padded with the identity past d
+  {
+    double v[kP];
 #pragma unroll
-    for (int a = 0; a < kGJ; ++a)
-      col[a] = (c < kGJ && a < kw && c < kw) ? G[(int64_t)(k0 + a) * d + k0 + c]
-                                             : (a == c ? 1.0 : 0.0);
-    bool bad = false;
-    gj_invert32(col, c, &bad);
-    if (c < kGJ) {
-#pragma unroll
-      for (int a = 0; a < kGJ; ++a) {
-        Pinv[a][c] = col[a];
-        if (bx == 0 && a < kw && c < kw) colp[(int64_t)(k0 + a) * kGJ + c] = col[a];
-      }
+    for (int u = 0; u < kP; ++u) {
+      const int e = t + 256 * u;
+      const int a = min(e / kGJ, kw - 1), c = min(e % kGJ, kw - 1);
+      v[u] = G[(int64_t)(k0 + a) * d + k0 + c];
     }
-    if (bad && t == 0) atomicCAS(info, 0, k0 + 1);
+#pragma unroll
+    for (int u = 0; u < kP; ++u) {
+      const int e = t + 256 * u;
+      const int a = e / kGJ, c = e % kGJ;
+      Pinv[a][c] = (a < kw && c < kw) ? v[u] : (a == c ? 1.0 : 0.0);
+    }
   }
   // 2. save the old column panel for rows [64 b, 64 b + 64) outside K
   const int r0 = bx * kGJChunk;
-  for (int e = t; e < kGJChunk * kGJ; e += 256) {
-    const int i = r0 + e / kGJ, a = e % kGJ;
-    if (i < d && (i < k0 || i >= k0 + kw) && a < kw) colp[(int64_t)i * kGJ + a] = G[(int64_t)i * d + k0 + a];
+  {
+    double v[kC];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int e = t + 256 * u;
+      const int i = min(r0 + e / kGJ, d - 1), a = min(e % kGJ, kw - 1);
+      v[u] = G[(int64_t)i * d + k0 + a];
+    }
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int e = t + 256 * u;
+      const int i = r0 + e / kGJ, a = e % kGJ;
+      if (i < d && (i < k0 || i >= k0 + kw) && a < kw) colp[(int64_t)i * kGJ + a] = v[u];
+    }
   }
   // 3. row panel of this block's columns [64 b, 64 b + 64)
   const int c0 = bx * kGJChunk;
-  for (int e = t; e < kGJ * kGJChunk; e += 256) {
-    const int a = e / kGJChunk, j = c0 + e % kGJChunk;
-    Rp[a][e % kGJChunk] = (a < kw && j < d) ? G[(int64_t)(k0 + a) * d + j] : 0.0;
+  {
+    double v[kC];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int e = t + 256 * u;
+      const int a = min(e / kGJChunk, kw - 1), j = min(c0 + e % kGJChunk, d - 1);
+      v[u] = G[(int64_t)(k0 + a) * d + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int e = t + 256 * u;
+      const int a = e / kGJChunk, j = c0 + e % kGJChunk;
+      Rp[a][e % kGJChunk] = (a < kw && j < d) ? v[u] : 0.0;
+    }
   }
   __syncthreads();
+  // 1b. Gauss-Jordan on the pivot block in place, every thread on four entries
+  // of one row (row i = t / 8, columns 4 (t % 8) ..): at step s the pivot row
+  // becomes P[s][.] / P[s][s] (1 / P[s][s] in column s), and every other row
+  // loses P[i][s] times it (-P[i][s] / P[s][s] in column s).  The old values
+  // of the step are read before a barrier and written after it.  A
+  // non-positive or non-finite pivot is reported.
+  {
+    static_assert(kGJ * kGJ == 4 * 256, "four entries per thread");
+    const int i = t >> 3;
+    const int j0 = (t & 7) * 4;
+    bool bad = false;
+    for (int s = 0; s < kGJ; ++s) {
+      double piv = Pinv[s][s];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        bad = true;
+        piv = 1.0;
+      }
+      const double inv = 1.0 / piv;
+      const double f = Pinv[i][s];
+      double rs[4], cur[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u;
+        rs[u] = (j == s) ? inv : Pinv[s][j] * inv;
+        cur[u] = Pinv[i][j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u;
+        Pinv[i][j] = (i == s) ? rs[u] : (j == s) ? -f * inv : fma(-f, rs[u], cur[u]);
+      }
+      __syncthreads();
+    }
+    if (bad && t == 0) atomicCAS(info, 0, k0 + 1);
+  }
+  if (bx == 0)
+    for (int e = t; e < kGJ * kGJ; e += 256) {
+      const int a = e / kGJ, c = e % kGJ;
+      if (a < kw && c < kw) colp[(int64_t)(k0 + a) * kGJ + c] = Pinv[a][c];
+    }
   for (int e = t; e < kGJ * kGJChunk; e += 256) {
     const int a = e / kGJChunk, jj = e % kGJChunk, j = c0 + jj;
     if (a >= kw || j >= d || (j >= k0 && j < k0 + kw)) continue;
@@ -478,27 +523,50 @@ __device__ __forceinline__ void gj_update(int d, int k0, DP __restrict__ G, CP _
       }
     return;
   }
-  for (int e = t; e < kGJ * kGJ; e += 256) {
-    const int r = e / kGJ, c = e % kGJ;
-    Cp[r][c] = (i0 + r < d && c < kw) ? colp[(int64_t)(i0 + r) * kGJ + c] : 0.0;
-    // Pinv (colp rows K) for the pivot columns, else the new row panel
-    const bool in = r < kw && j0 + c < d;
-    Rw[r][c] = !in ? 0.0
-               : pivcols ? colp[(int64_t)(k0 + r) * kGJ + c]
-                         : G[(int64_t)(k0 + r) * d + j0 + c];
+  // a fixed count per thread, every load from a clamped valid address (the
+  // entries outside the matrix are replaced afterwards): all of the two
+  // tiles' loads in flight together
+  {
+    constexpr int kT = kGJ * kGJ / 256;
+    double cv[kT], rv[kT];
+#pragma unroll
+    for (int u = 0; u < kT; ++u) {
+      const int e = t + 256 * u;
+      const int r = e / kGJ, c = min(e % kGJ, kw - 1);
+      cv[u] = colp[(int64_t)min(i0 + r, d - 1) * kGJ + c];
+      // Pinv (colp rows K) for the pivot columns, else the new row panel
+      const int rr = min(r, kw - 1);
+      rv[u] = pivcols ? colp[(int64_t)(k0 + rr) * kGJ + c]
+                      : G[(int64_t)(k0 + rr) * d + min(j0 + e % kGJ, d - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kT; ++u) {
+      const int e = t + 256 * u;
+      const int r = e / kGJ, c = e % kGJ;
+      Cp[r][c] = (i0 + r < d && c < kw) ? cv[u] : 0.0;
+      Rw[r][c] = (r < kw && j0 + c < d) ? rv[u] : 0.0;
+    }
   }
   __syncthreads();
-  for (int e = t; e < kGJ * kGJ; e += 256) {
+  // the tile's old values first (all in flight), then the products
+  constexpr int kU = kGJ * kGJ / 256;
+  double old[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int e = t + 256 * u;
+    const int i = i0 + e / kGJ, j = j0 + e % kGJ;
+    old[u] = G[(int64_t)min(i, d - 1) * d + min(j, d - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int e = t + 256 * u;
     const int r = e / kGJ, c = e % kGJ;
     const int i = i0 + r, j = j0 + c;
     if (i >= d || j >= d) continue;
     double v = 0.0;
 #pragma unroll 8
     for (int q = 0; q < kGJ; ++q) v = fma(Cp[r][q], Rw[q][c], v);
-    if (pivcols)
-      G[(int64_t)i * d + j] = -v;  // Rw holds Pinv here
-    else
-      G[(int64_t)i * d + j] -= v;
+    G[(int64_t)i * d + j] = pivcols ? -v : old[u] - v;  // Rw holds Pinv for the pivot columns
   }
 }
 
