@@ -41,8 +41,19 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha, CP
   const int tx = threadIdx.x % 16;
   const int ty = threadIdx.x / 16;
   double acc[4][4] = {};
-  for (int64_t k0 = kb0; k0 < kend; k0 += kKStep) {
-    for (int e = threadIdx.x; e < kKStep * kTile; e += 256) {
+  // Each thread copies kL entries of A and of B per k step.  Their loads are
+  // unconditional (entries outside the matrices read a clamped, valid address
+  // and are replaced by zero when written to LDS) and the next step's are
+  // issued before the current step's products, so they are all in flight
+  // together and overlap the arithmetic.
+  constexpr int kL = kKStep * kTile / 256;
+  double va[kL], vb[kL];
+  unsigned oka = 0, okb = 0;
+  auto fetch = [&](int64_t k0) {
+    oka = okb = 0;
+#pragma unroll
+    for (int u = 0; u < kL; ++u) {
+      const int e = threadIdx.x + 256 * u;
       int kk, ii;
       if (transA) {  // A stored K x M: contiguous along i
         kk = e / kTile;
@@ -52,9 +63,9 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha, CP
         kk = e % kKStep;
       }
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < M && gk < kend) v = transA ? A[gk * lda + gi] : A[gi * lda + gk];
-      As[kk][ii] = v;
+      oka |= (unsigned)(gi < M && gk < kend) << u;
+      const int64_t ci = min(gi, M - 1), ck = min(gk, kend - 1);
+      va[u] = transA ? A[ck * lda + ci] : A[ci * lda + ck];
       int kb, jj;
       if (transB) {  // B stored N x K
         jj = e / kKStep;
@@ -64,11 +75,27 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, double alpha, CP
         jj = e % kTile;
       }
       const int64_t gj = j0 + jj, gkb = k0 + kb;
-      double w = 0.0;
-      if (gj < N && gkb < kend) w = transB ? B[gj * ldb + gkb] : B[gkb * ldb + gj];
-      Bs[kb][jj] = w;
+      okb |= (unsigned)(gj < N && gkb < kend) << u;
+      const int64_t cj = min(gj, N - 1), ckb = min(gkb, kend - 1);
+      vb[u] = transB ? B[cj * ldb + ckb] : B[ckb * ldb + cj];
+    }
+  };
+  if (kb0 < kend) fetch(kb0);
+  for (int64_t k0 = kb0; k0 < kend; k0 += kKStep) {
+#pragma unroll
+    for (int u = 0; u < kL; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (transA)
+        As[e / kTile][e % kTile] = ((oka >> u) & 1) ? va[u] : 0.0;
+      else
+        As[e % kKStep][e / kKStep] = ((oka >> u) & 1) ? va[u] : 0.0;
+      if (transB)
+        Bs[e % kKStep][e / kKStep] = ((okb >> u) & 1) ? vb[u] : 0.0;
+      else
+        Bs[e / kTile][e % kTile] = ((okb >> u) & 1) ? vb[u] : 0.0;
     }
     __syncthreads();
+    if (k0 + kKStep < kend) fetch(k0 + kKStep);
 #pragma unroll
     for (int kk = 0; kk < kKStep; ++kk) {
       double a[4], b[4];
