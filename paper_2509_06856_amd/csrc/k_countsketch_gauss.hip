@@ -145,17 +145,40 @@ __global__ __launch_bounds__(1024) void cs_colscan_kernel(int64_t r, int waves,
     if (k < r) off[k] = p0 + incl - t;
     if (k == r - 1) off[r] = p0 + incl;
   }
+  // (both walks over the waves' rows load 16 counts at a time, so that their
+  // loads are in flight together instead of one after another)
+  constexpr int kB = 16;
   const int per = (waves + 15) / 16;
   const int w0 = g * per, w1 = min(waves, w0 + per);
   int t = 0;
-  if (k < r)
-    for (int w = w0; w < w1; ++w) t += cntW[(int64_t)w * r + k];
+  if (k < r) {
+    int w = w0;
+    for (; w + kB <= w1; w += kB) {
+      int v[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) v[u] = cntW[(int64_t)(w + u) * r + k];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) t += v[u];
+    }
+    for (; w < w1; ++w) t += cntW[(int64_t)w * r + k];
+  }
   part[g][lane] = t;
   __syncthreads();
   if (k < r) {
     int run = base[lane];
     for (int h = 0; h < g; ++h) run += part[h][lane];
-    for (int w = w0; w < w1; ++w) {
+    int w = w0;
+    for (; w + kB <= w1; w += kB) {
+      int v[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) v[u] = cntW[(int64_t)(w + u) * r + k];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        cntW[(int64_t)(w + u) * r + k] = run;
+        run += v[u];
+      }
+    }
+    for (; w < w1; ++w) {
       const int c = cntW[(int64_t)w * r + k];
       cntW[(int64_t)w * r + k] = run;
       run += c;
