@@ -38,7 +38,7 @@ typedef enum {
   SLSE_ESINGULAR = -4,    /* zero, negative or non-finite pivot in the factorization */
   SLSE_ENOTCONV = -5,     /* tolerance not met within s_max steps (beta holds the last iterate) */
   SLSE_ENONFINITE = -6,   /* NaN/Inf met in the iteration */
-  SLSE_EUNSUPPORTED = -7  /* valid request this build does not implement */
+  SLSE_EUNSUPPORTED = -7  /* valid request this library does not implement */
 } slse_status;
 
 typedef enum { SLSE_F32 = 0, SLSE_F64 = 1, SLSE_BF16 = 2 } slse_dtype;

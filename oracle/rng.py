@@ -3,7 +3,7 @@
 The paper draws the SRHT's Rademacher diagonal D, the uniform permutation P and
 the row sampling B at random (Sec. 3, the SRHT definition), the CountSketch's
 one +-1 per column (Sec. 1.2 and Sec. 5.4) and the Gaussian sketch's iid
-entries (Sec. 1.2).  It does not say how.  This build draws every one of them
+entries (Sec. 1.2).  It does not say how.  Here every one of them is drawn
 from Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
 easy as 1, 2, 3", SC'11), keyed by (seed, stream), so that any single entry can
 be recomputed from its index alone.

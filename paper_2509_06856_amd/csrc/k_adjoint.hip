@@ -171,7 +171,7 @@ void launch3(const AdjointArgs& a, hipStream_t s) {
   else if (nch <= 16)
     launch4<T, G, VEC, 16>(a, lpr, s);
   else
-    fail(SLSE_EUNSUPPORTED, "adjoint: d too large for this build");
+    fail(SLSE_EUNSUPPORTED, "adjoint: d too large for this library");
 }
 
 template <typename T, typename G>

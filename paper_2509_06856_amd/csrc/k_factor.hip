@@ -687,7 +687,7 @@ void launch_convert_scale(int64_t rows, int d, const void* A, int64_t lda, slse_
 
 void launch_cholesky(int d, const double* G, int64_t ldg, double* R, int64_t ldr, int* info,
                      hipStream_t s) {
-  if (d > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this build");
+  if (d > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this library");
   cholesky_kernel<<<1, kCholThreads, 0, s>>>(d, G, ldg, R, ldr, info);
   SLSE_LAUNCH_CHECK();
 }
@@ -699,7 +699,7 @@ int factor_batched_splits(int64_t rows_max) {
 void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_max,
                            slse_dtype at, hipStream_t s) {
   if (B <= 0) return;
-  if (dmax > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this build");
+  if (dmax > kCholMaxD) fail(SLSE_EUNSUPPORTED, "cholesky: d > 512 not supported by this library");
   const unsigned cb = (unsigned)std::min<int64_t>(ceil_div(rows_max * dmax, 256), 1024);
   convert_scale_batched_kernel<<<dim3(cb, (unsigned)B), 256, 0, s>>>(jobs, at == SLSE_F32 ? 1 : 0);
   SLSE_LAUNCH_CHECK();
@@ -727,7 +727,7 @@ void launch_factor_batched(const FactorJob* jobs, int B, int dmax, int64_t rows_
 }
 
 void launch_tri_inv(int d, const double* R, int64_t ldr, double* Rinv, int64_t ldi, hipStream_t s) {
-  if (d > kInvMaxD) fail(SLSE_EUNSUPPORTED, "tri_inv: d > 512 not supported by this build");
+  if (d > kInvMaxD) fail(SLSE_EUNSUPPORTED, "tri_inv: d > 512 not supported by this library");
   tri_inv_kernel<<<(int)ceil_div(d, 4), 256, 0, s>>>(d, R, ldr, Rinv, ldi);
   SLSE_LAUNCH_CHECK();
 }

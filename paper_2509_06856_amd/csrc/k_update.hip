@@ -179,7 +179,7 @@ void launch_update(const UpdateArgs& a, hipStream_t s) {
   const int rpb = rows_per_block_for(a.d);
   const int blocks = (int)ceil_div(a.d, rpb);
   const size_t shm = (size_t)a.d * sizeof(double);
-  if (shm > 64 * 1024) fail(SLSE_EUNSUPPORTED, "update: d too large for this build");
+  if (shm > 64 * 1024) fail(SLSE_EUNSUPPORTED, "update: d too large for this library");
   mihs_update_kernel<<<blocks, kThreads, shm, s>>>(a, rpb);
   SLSE_LAUNCH_CHECK();
 }

@@ -192,7 +192,7 @@ struct SketchShape {
 SketchShape make_sketch_shape(slse_sketch_kind kind, int64_t N, int64_t d, const int64_t* m, int K,
                               int64_t r) {
   require(N > 0 && d >= 1 && N > d, "need N > d >= 1");
-  require(d <= 1024, "d > 1024 is not supported by this build");
+  require(d <= 1024, "d > 1024 is not supported by this library");
   require(K >= 1 && K <= SLSE_MAX_LEVELS && m != nullptr, "need 1 <= K <= SLSE_MAX_LEVELS");
   require(r > d, "need r > d");
   SketchShape s;
@@ -208,7 +208,7 @@ SketchShape make_sketch_shape(slse_sketch_kind kind, int64_t N, int64_t d, const
   s.scale.resize(K);
   if (kind == SLSE_SRHT) {
     s.p = std::max(1, ilog2_ceil(N));
-    require(s.p <= 30, "N too large for this build (N' <= 2^30)");
+    require(s.p <= 30, "N too large for this library (N' <= 2^30)");
     s.n_pad = int64_t(1) << s.p;
     require(s.m[K - 1] <= s.n_pad && r <= s.n_pad, "SRHT: m_K and r must be <= N'");
     for (int i = 0; i < K; ++i) {
@@ -2093,7 +2093,7 @@ slse_status slse_sketch_apply(slse_ctx* ctx, slse_sketch_kind kind, uint64_t see
     const bool bf16 = out_t == SLSE_BF16;
     if (bf16 && !(kind == SLSE_GAUSSIAN && in_t == SLSE_F32))
       fail(SLSE_EUNSUPPORTED, "BF16 products are offered for the Gaussian sketch of F32 data");
-    if (!bf16 && out_t != in_t) fail(SLSE_EUNSUPPORTED, "out dtype must equal in dtype in this build");
+    if (!bf16 && out_t != in_t) fail(SLSE_EUNSUPPORTED, "out dtype must equal in dtype in this library");
     DeviceGuard g(ctx->device);
     SketchShape s = make_sketch_shape(kind, N, d, m, K, r);
     SrhtArgs srht;
@@ -2115,7 +2115,7 @@ slse_status slse_factor(slse_ctx* ctx, int64_t rows, int64_t d, const void* A, i
   return guarded([&]() -> slse_status {
     require(ctx && A && R, "null pointer");
     require(d >= 1 && rows >= d, "need rows >= d >= 1");
-    require(d <= 512, "d > 512 is not supported by the factorization of this build");
+    require(d <= 512, "d > 512 is not supported by the factorization of this library");
     require(lda >= d && ldr >= d && (!M || ldm >= d), "leading dimension too small");
     require(a_t == SLSE_F32 || a_t == SLSE_F64, "A dtype must be F32 or F64");
     require(scale > 0 && std::isfinite(scale), "scale must be positive");
