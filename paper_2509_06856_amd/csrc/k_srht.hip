@@ -30,7 +30,9 @@ namespace {
 // kGroupOrder (two-pass transforms): the workspace Z holds its rows in the
 // last pass's group order, so the last pass reads each group as contiguous
 // rows and the first pass writes them at a stride instead
-enum { kFirst = 1, kLast = 2, kGroupOrder = 4 };
+// kPregathered (first pass of Y's own transform): the rows were gathered
+// through P with D applied by the index-map kernel, so they are read in order
+enum { kFirst = 1, kLast = 2, kGroupOrder = 4, kPregathered = 8 };
 
 template <typename T>
 struct PassParams {
@@ -83,7 +85,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
 
   // index maps of this group, fetched once (contiguous: the first pass has
   // s0 = 0 and the slot maps are stored in the last pass's group order)
-  __shared__ int32_t s_pi[(MODE & kFirst) ? (1 << B) : 1];
+  __shared__ int32_t s_pi[((MODE & kFirst) && !(MODE & kPregathered)) ? (1 << B) : 1];
   __shared__ int32_t s_slot[(MODE & kLast) ? 2 * (1 << B) : 1];
 
   const int ct = (int)(bid % P.n_ct);
@@ -92,7 +94,7 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
   const int64_t hi = g >> P.s0;
   const int64_t hi_part = hi << (P.s0 + B);
   const int col_base = ct * CT;
-  if constexpr ((MODE & kFirst) != 0) {
+  if constexpr ((MODE & kFirst) != 0 && (MODE & kPregathered) == 0) {
     for (int k = threadIdx.x; k < (1 << B); k += NT) s_pi[k] = gptr(P.pi_sgn)[hi_part | k];
   }
   if constexpr ((MODE & kLast) != 0) {
@@ -102,7 +104,8 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
       s_slot[(1 << B) + k] = gptr(P.slotH)[gb + k];
     }
   }
-  if constexpr ((MODE & (kFirst | kLast)) != 0) __syncthreads();
+  if constexpr ((MODE & kLast) != 0 || ((MODE & kFirst) != 0 && (MODE & kPregathered) == 0))
+    __syncthreads();
 
   // phase A: 2^BA rows {q + k 2^BB} of one column per item; stages on the high BA bits
   T v[IA][RA];
@@ -113,7 +116,11 @@ __device__ __forceinline__ void fwht_pass(const PassParams<T>& P, int64_t bid) {
     const int c = it % CT;
     const int q = it / CT;
     const int col = col_base + c;
-    if constexpr ((MODE & kFirst) != 0) {
+    if constexpr ((MODE & kPregathered) != 0) {
+      // rows hi_part | (q + k 2^BB) of the pregathered values, in order
+#pragma unroll
+      for (int k = 0; k < RA; ++k) v[ia][k] = __builtin_nontemporal_load(gptr(P.X + (hi_part | (q + (k << BB)))));
+    } else if constexpr ((MODE & kFirst) != 0) {
       // gather through P with D applied; branch-free so that all 2^BA loads
       // are in flight together (out-of-range rows and padding columns read a
       // valid address and are zeroed afterwards)
@@ -312,6 +319,27 @@ __global__ void srht_index_kernel(int64_t npad, int p, uint64_t seed, int64_t mK
                    npad, p, seed, mK, s0_last, b_last, pi_sgn, slotA);
 }
 
+// The same maps, and Y gathered through P with D applied, in row order:
+// yp[j] = D_j Y[pi(j)] (+0 past N), the bits the first pass's gather would
+// form; Y's own first pass then reads its rows in order, and the random reads
+// of Y overlap the Feistel arithmetic here.
+template <typename T>
+__global__ void srht_index_y_kernel(int64_t npad, int p, uint64_t seed, int64_t mK, int s0_last,
+                                    int b_last, int32_t* __restrict__ pi_sgn,
+                                    int32_t* __restrict__ slotA, const T* __restrict__ Y, int64_t N,
+                                    T* __restrict__ yp) {
+  const int64_t j0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  srht_index_range(j0, stride, npad, p, seed, mK, s0_last, b_last, pi_sgn, slotA);
+  for (int64_t j = j0; j < npad; j += stride) {
+    const int32_t ps = gptr(pi_sgn)[j];
+    const bool neg = ps < 0;
+    const int64_t src = neg ? (int64_t)(~ps) : (int64_t)ps;
+    const T v = src < N ? gptr(Y)[src] : (T)0;
+    gptr(yp)[j] = src < N ? (neg ? -v : v) : (T)0;
+  }
+}
+
 // slotH (pre-filled with -1): the row sigma_hat(t) carries slot t, for t < r
 __global__ void srht_hat_kernel(int64_t r, int p, uint64_t seed, int s0_last, int b_last,
                                 int32_t* __restrict__ slotH) {
@@ -503,7 +531,12 @@ void run_passes(const SrhtArgs& a, hipStream_t s) {
     Q.Ahat = static_cast<T*>(a.Ahat) + a.d;
     Q.zb = bs.back();
     Q.s0 = 0;
-    dispatch_b_y<T, kFirst | kGroupOrder>(bs[0], Q, npad, s);
+    if (a.y_pregathered) {
+      Q.X = static_cast<const T*>(a.Z) + npad * (a.ldz + 1);  // yp, written with the index maps
+      dispatch_b_y<T, kFirst | kGroupOrder | kPregathered>(bs[0], Q, npad, s);
+    } else {
+      dispatch_b_y<T, kFirst | kGroupOrder>(bs[0], Q, npad, s);
+    }
     Q.s0 = bs[0];
     dispatch_b_y<T, kLast | kGroupOrder>(bs[1], Q, npad, s);
   }
@@ -627,7 +660,8 @@ void srht_split_y(SrhtArgs& a) {
 
 size_t srht_z_bytes(const SrhtArgs& a) {
   if (a.p <= a.bmax) return 0;  // a single pass needs no workspace
-  return (size_t)(int64_t(1) << a.p) * (size_t)(a.ldz + (a.split_y ? 1 : 0)) * dtype_size(a.t);
+  // X's columns, then Y's own column and Y gathered through P (split_y)
+  return (size_t)(int64_t(1) << a.p) * (size_t)(a.ldz + (a.split_y ? 2 : 0)) * dtype_size(a.t);
 }
 
 namespace {
@@ -695,17 +729,34 @@ void launch_srht(const SrhtArgs& a, hipStream_t s) {
   const std::vector<int> bs = pass_sizes(a.p, a.bmax);
   const int b_last = bs.back();
   const int s0_last = a.p - b_last;
-  srht_index_kernel<<<blocks, threads, 0, s>>>(npad, a.p, a.seed, a.mK, s0_last, b_last,
-                                               a.pi_sgn, a.slotA);
+  // with Y on its own, Y is gathered through P together with the maps
+  // (SLSE_SRHT_Y_PREGATHER=0: in its first pass instead)
+  SrhtArgs b = a;
+  b.y_pregathered = a.split_y;
+  if (const char* e = std::getenv("SLSE_SRHT_Y_PREGATHER"))
+    if (std::atoi(e) == 0) b.y_pregathered = false;
+  if (b.y_pregathered && a.t == SLSE_F32) {
+    srht_index_y_kernel<float><<<blocks, threads, 0, s>>>(
+        npad, a.p, a.seed, a.mK, s0_last, b_last, a.pi_sgn, a.slotA, static_cast<const float*>(a.Y),
+        a.N, static_cast<float*>(a.Z) + npad * (a.ldz + 1));
+  } else if (b.y_pregathered && a.t == SLSE_F64) {
+    srht_index_y_kernel<double><<<blocks, threads, 0, s>>>(
+        npad, a.p, a.seed, a.mK, s0_last, b_last, a.pi_sgn, a.slotA, static_cast<const double*>(a.Y),
+        a.N, static_cast<double*>(a.Z) + npad * (a.ldz + 1));
+  } else {
+    b.y_pregathered = false;
+    srht_index_kernel<<<blocks, threads, 0, s>>>(npad, a.p, a.seed, a.mK, s0_last, b_last,
+                                                 a.pi_sgn, a.slotA);
+  }
   SLSE_LAUNCH_CHECK();
   launch_fill_i32(a.slotH, -1, npad, s);
   srht_hat_kernel<<<(int)ceil_div(a.r, threads), threads, 0, s>>>(a.r, a.p, a.seed, s0_last,
                                                                   b_last, a.slotH);
   SLSE_LAUNCH_CHECK();
   if (a.t == SLSE_F64)
-    run_passes<double>(a, s);
+    run_passes<double>(b, s);
   else if (a.t == SLSE_F32)
-    run_passes<float>(a, s);
+    run_passes<float>(b, s);
   else
     fail(SLSE_EUNSUPPORTED, "srht: dtype");
 }

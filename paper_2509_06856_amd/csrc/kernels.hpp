@@ -128,6 +128,7 @@ struct SrhtArgs {
   bool xcd_swizzle = true;    // contiguous work runs per XCD
   bool indices_ready = false; // pi_sgn / slotA / slotH already built (batched)
   bool split_y = false;       // Y transformed on its own: Z = X's d columns, then N' values of Y
+  bool y_pregathered = false; // (set at launch) Y gathered through P by the index-map kernel
 };
 
 void srht_plan(SrhtArgs& a, int prefer_ct);

@@ -329,6 +329,11 @@ def test_srht_own_y_passes_match_the_shared_tile(G, N, d, dtype, monkeypatch):
     m = [128, 256, 1024]
     monkeypatch.setenv("SLSE_SRHT_SPLIT_Y", "1")
     A1, H1, _ = G.sketch_apply(X, Y, "srht", 4, m, 3 * d)
+    # Y gathered through P in its own first pass instead of with the index maps
+    monkeypatch.setenv("SLSE_SRHT_Y_PREGATHER", "0")
+    A3, H3, _ = G.sketch_apply(X, Y, "srht", 4, m, 3 * d)
+    monkeypatch.setenv("SLSE_SRHT_Y_PREGATHER", "1")
     monkeypatch.setenv("SLSE_SRHT_SPLIT_Y", "0")
     A2, H2, _ = G.sketch_apply(X, Y, "srht", 4, m, 3 * d)
     assert torch.equal(A1, A2) and torch.equal(H1, H2)
+    assert torch.equal(A1, A3) and torch.equal(H1, H3)
